@@ -1,0 +1,265 @@
+"""Seeded synthetic inputs for the BDL-tree workloads.
+
+This module is shared by the CPU oracle's tests, the GPU parity tests and the
+benchmark.  It only draws numbers: it holds none of the method's arithmetic
+(no distances, no splits, no level bookkeeping beyond remembering which ids
+are live so that erase batches name live points).
+
+Point sets stand in for the paper's synthetic datasets (Section VI: Uniform
+and the clustered VisualVar family); the VisualVar generator itself is not
+available, so clustered sets are Gaussian blobs with log-uniform widths and
+Zipf-weighted cluster sizes.  All coordinates are float32, ids are uint32.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Iterator, List, Optional, Tuple
+
+import numpy as np
+
+__all__ = [
+    "uniform_points",
+    "clustered_points",
+    "Op",
+    "Workload",
+    "workload",
+    "WORKLOADS",
+]
+
+
+def uniform_points(n: int, d: int, seed: int) -> np.ndarray:
+    """n points uniform in [0,1)^d as float32, from PCG64(seed)."""
+    rng = np.random.default_rng(seed)
+    return rng.random((n, d), dtype=np.float32)
+
+
+def clustered_points(n: int, d: int, seed: int, n_clusters: int = 100,
+                     log10_sigma: Tuple[float, float] = (-4.0, -1.0),
+                     zipf_s: float = 1.2) -> np.ndarray:
+    """Variable-density clusters: n points from n_clusters Gaussian blobs.
+
+    Centres are uniform in [0,1)^d, each blob's standard deviation is
+    10**U(log10_sigma), and blob r (1-based) is chosen with probability
+    proportional to r**-zipf_s.  Points are drawn in float64 and cast to
+    float32; nothing is clipped.
+    """
+    rng = np.random.default_rng(seed)
+    centres = rng.random((n_clusters, d))
+    sigma = 10.0 ** rng.uniform(log10_sigma[0], log10_sigma[1], size=n_clusters)
+    w = np.arange(1, n_clusters + 1, dtype=np.float64) ** (-zipf_s)
+    w /= w.sum()
+    which = rng.choice(n_clusters, size=n, p=w)
+    out = np.empty((n, d), dtype=np.float32)
+    chunk = 1 << 22
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        c = which[s:e]
+        z = rng.standard_normal((e - s, d))
+        out[s:e] = (centres[c] + sigma[c, None] * z).astype(np.float32)
+    return out
+
+
+@dataclasses.dataclass
+class Op:
+    """One batch operation: kind is 'insert', 'erase' or 'knn'."""
+    kind: str
+    pts: np.ndarray                  # [n, d] float32 (points or queries)
+    ids: Optional[np.ndarray] = None  # [n] uint32 for insert/erase
+    k: int = 0                        # for knn
+
+    @property
+    def n(self) -> int:
+        return int(self.pts.shape[0])
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    dim: int
+    leaf_size: int
+    buffer_size: int
+    id_capacity: int
+    ops: List[Op]
+    description: str = ""
+
+
+class _LiveIds:
+    """Remembers which ids are live (insertion order) to draw erase batches."""
+
+    def __init__(self) -> None:
+        self.chunks: List[np.ndarray] = []
+        self.dead: Optional[np.ndarray] = None
+
+    def add(self, ids: np.ndarray) -> None:
+        self.chunks.append(np.asarray(ids, dtype=np.uint32))
+
+    def live(self) -> np.ndarray:
+        allids = np.concatenate(self.chunks) if self.chunks else np.zeros(0, np.uint32)
+        if self.dead is not None and self.dead.size:
+            allids = allids[~np.isin(allids, self.dead)]
+        return allids
+
+    def kill(self, ids: np.ndarray) -> None:
+        ids = np.asarray(ids, dtype=np.uint32)
+        self.dead = ids if self.dead is None else np.concatenate([self.dead, ids])
+
+
+def _draw_erase(rng: np.random.Generator, live: np.ndarray, m: int) -> np.ndarray:
+    m = min(m, live.size)
+    return rng.choice(live, size=m, replace=False).astype(np.uint32)
+
+
+def _uniform_small(scale: float = 1.0, seed: int = 0, X: int = 1024, d: int = 2) -> Workload:
+    """10 inserts of 1000 uniform points, 5 erases of 1000 live points, then
+    k=5 queries for 1000 uniform points (leaf 16)."""
+    nb = max(1, int(round(1000 * scale)))
+    pts = uniform_points(10 * nb, d, seed)
+    ids = np.arange(10 * nb, dtype=np.uint32)
+    ops: List[Op] = []
+    live = _LiveIds()
+    for b in range(10):
+        sl = slice(b * nb, (b + 1) * nb)
+        ops.append(Op("insert", pts[sl], ids[sl]))
+        live.add(ids[sl])
+    erng = np.random.default_rng(seed + 1)
+    for _ in range(5):
+        e = _draw_erase(erng, live.live(), nb)
+        live.kill(e)
+        ops.append(Op("erase", pts[e.astype(np.int64)], e))
+    q = uniform_points(max(1, int(round(1000 * scale))), d, seed + 2)
+    ops.append(Op("knn", q, k=5))
+    return Workload("uniform2d_small", d, 16, X, 10 * nb, ops,
+                    "2D uniform, 10x1000 inserts, 5x1000 erases, 1000 queries k=5")
+
+
+def _uniform3d_10m(scale: float = 1.0, seed: int = 0) -> Workload:
+    """Build to n points (10M at scale 1) with 10 equal inserts, erase 10% of
+    live ids in one batch, then k=5 queries for every live point in
+    ascending id order."""
+    d = 3
+    n = int(round(10_000_000 * scale))
+    nb = n // 10
+    n = nb * 10
+    pts = uniform_points(n, d, seed)
+    ids = np.arange(n, dtype=np.uint32)
+    ops: List[Op] = []
+    for b in range(10):
+        sl = slice(b * nb, (b + 1) * nb)
+        ops.append(Op("insert", pts[sl], ids[sl]))
+    erng = np.random.default_rng(seed + 1)
+    e = np.sort(erng.choice(n, size=nb, replace=False)).astype(np.uint32)
+    erng.shuffle(e)
+    ops.append(Op("erase", pts[e.astype(np.int64)], e))
+    alive = np.ones(n, dtype=bool)
+    alive[e.astype(np.int64)] = False
+    q = pts[alive]
+    ops.append(Op("knn", q, k=5))
+    return Workload("uniform3d_10m", d, 16, 1024, n, ops,
+                    f"3D uniform, {n} points via 10 inserts of {nb}, erase {nb}, "
+                    f"k=5 for all {n - nb} live points")
+
+
+def _clustered7d(scale: float = 1.0, seed: int = 0) -> Workload:
+    """d=7 Gaussian blobs; 100 inserts of n/100, erase 10% in one batch,
+    then k=10 for every live point."""
+    d = 7
+    n = int(round(10_000_000 * scale))
+    nb = max(1, n // 100)
+    n = nb * 100
+    pts = clustered_points(n, d, seed)
+    ids = np.arange(n, dtype=np.uint32)
+    ops: List[Op] = []
+    for b in range(100):
+        sl = slice(b * nb, (b + 1) * nb)
+        ops.append(Op("insert", pts[sl], ids[sl]))
+    erng = np.random.default_rng(seed + 1)
+    m = n // 10
+    e = erng.choice(n, size=m, replace=False).astype(np.uint32)
+    ops.append(Op("erase", pts[e.astype(np.int64)], e))
+    alive = np.ones(n, dtype=bool)
+    alive[e.astype(np.int64)] = False
+    ops.append(Op("knn", pts[alive], k=10))
+    return Workload("clustered7d_10m", d, 16, 1024, n, ops,
+                    f"7D clustered, {n} points via 100 inserts, erase {m}, k=10 all live")
+
+
+WORKLOADS = {
+    "uniform2d_small": _uniform_small,
+    "uniform3d_10m": _uniform3d_10m,
+    "clustered7d_10m": _clustered7d,
+}
+
+
+def workload(name: str, scale: float = 1.0, seed: int = 0, **kw) -> Workload:
+    return WORKLOADS[name](scale=scale, seed=seed, **kw)
+
+
+def random_op_sequence(seed: int, d: int, n_ops: int, max_batch: int,
+                       id_capacity: int, p_insert: float = 0.5,
+                       p_erase: float = 0.3, clustered: bool = False,
+                       k_max: int = 16, bad_erase_frac: float = 0.1) -> Iterator[Op]:
+    """Random interleaved inserts, erases and queries for stress tests.
+
+    Erase batches mostly name live (id, point) pairs; a fraction names ids
+    that are not live, or live ids with perturbed coordinates, or repeats an
+    id inside the batch.  Ids are drawn without reuse from [0, id_capacity).
+    """
+    rng = np.random.default_rng(seed)
+    next_id = 0
+    live_ids: List[int] = []
+    store = {}
+    for _ in range(n_ops):
+        r = rng.random()
+        if r < p_insert or not live_ids:
+            b = int(rng.integers(0, max_batch + 1))
+            b = min(b, id_capacity - next_id)
+            if clustered:
+                p = clustered_points(b, d, int(rng.integers(1 << 30)), n_clusters=4)
+            else:
+                p = rng.random((b, d), dtype=np.float32)
+            # occasional exact duplicates of coordinates (distinct ids)
+            if b > 4 and rng.random() < 0.3:
+                src = rng.integers(0, b, size=b // 4)
+                dst = rng.integers(0, b, size=b // 4)
+                p[dst] = p[src]
+            ids = np.arange(next_id, next_id + b, dtype=np.uint32)
+            next_id += b
+            for i in range(b):
+                store[int(ids[i])] = p[i].copy()
+            live_ids.extend(int(x) for x in ids)
+            yield Op("insert", p, ids)
+        elif r < p_insert + p_erase:
+            b = int(rng.integers(0, min(max_batch, len(live_ids)) + 1))
+            pick = rng.choice(len(live_ids), size=b, replace=False) if b else np.zeros(0, np.int64)
+            ids = [live_ids[i] for i in pick]
+            pts = [store[i].copy() for i in ids]
+            nbad = int(round(bad_erase_frac * b))
+            for j in range(nbad):
+                kind = rng.integers(0, 3)
+                if kind == 0:       # id never inserted
+                    ids.append(int(next_id + rng.integers(0, 1000)))
+                    pts.append(rng.random(d, dtype=np.float32))
+                elif kind == 1:     # live id, wrong coordinates
+                    i = live_ids[int(rng.integers(0, len(live_ids)))]
+                    p = store[i].copy()
+                    p[int(rng.integers(0, d))] += np.float32(0.25)
+                    ids.append(i)
+                    pts.append(p)
+                else:               # repeat an id already in the batch
+                    if ids:
+                        j2 = int(rng.integers(0, len(ids)))
+                        ids.append(ids[j2])
+                        pts.append(pts[j2].copy())
+            killed = set(live_ids[i] for i in pick)
+            live_ids = [i for i in live_ids if i not in killed]
+            arr = np.array(pts, dtype=np.float32).reshape(-1, d)
+            yield Op("erase", arr, np.array(ids, dtype=np.uint32))
+        else:
+            nq = int(rng.integers(0, max_batch + 1))
+            q = rng.random((nq, d), dtype=np.float32)
+            if live_ids and nq > 2:
+                # some queries sit exactly on live points
+                for j in range(0, nq, 3):
+                    q[j] = store[live_ids[int(rng.integers(0, len(live_ids)))]]
+            k = int(rng.integers(1, k_max + 1))
+            yield Op("knn", q, k=k)
