@@ -1,0 +1,179 @@
+/*
+ * bdl.h -- C ABI of the MI355X BDL-tree library.
+ *
+ * The BDL-tree ("Parallel Batch-Dynamic kd-trees", Yesantharao, Wang,
+ * Dhulipala, Shun) keeps a set of points as a buffer of fewer than X points
+ * plus static kd-trees whose capacities are 2^i * X (Section III-C, the
+ * logarithmic method).  Batch insertion rebuilds the minimum set of trees
+ * (Insert_L, Alg. 3), batch deletion erases from every tree and rebuilds
+ * trees that fall below half capacity (Erase_L, Alg. 4), and batched k-NN
+ * visits every non-empty tree with one k-NN state per query (kNN_L, Alg. 5).
+ * Each tree is built with the spatial median (Section V-C) in van Emde Boas
+ * order (BuildvEB, Alg. 1).
+ *
+ * All work runs in HIP kernels on one gfx950 GPU.  Points are float32 of a
+ * fixed dimension d (1..16) with caller-chosen uint32 ids.
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: 0 on success, a negative BDL_E* code on failure; the
+ *    calling thread's message is then available from bdl_last_error().
+ *  - Argument errors are found before any GPU work is enqueued and leave the
+ *    tree unchanged.  BDL_ENOMEM also leaves the tree unchanged: new device
+ *    memory is obtained before anything old is released.
+ *  - Device pointers are plain HIP device addresses (for example a torch
+ *    tensor's data_ptr()).  The caller owns every input and output buffer;
+ *    the library copies inserted points into its own device memory.
+ *  - Every call is ordered on the stream given to bdl_create.  A handle is
+ *    not thread-safe.
+ *  - n = 0 and nq = 0 are valid no-ops.
+ */
+#ifndef BDL_H
+#define BDL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BDL_OK 0
+#define BDL_EINVAL (-1) /* invalid argument or precondition */
+#define BDL_ENOMEM (-2) /* device allocation failed or memory budget exceeded */
+#define BDL_EHIP (-3)   /* a HIP runtime call failed */
+
+#define BDL_MAX_DIM 16
+#define BDL_MAX_K 64
+#define BDL_INVALID_ID 0xFFFFFFFFu /* padding id; never a valid point id */
+
+/* bdl_config.flags */
+#define BDL_FLAG_CHECK_INPUTS 1u /* validate ids and coordinates on the GPU
+                                    before each insert (costs one sync) */
+#define BDL_FLAG_PROFILE 2u      /* time each phase with HIP events on the
+                                    tree's stream (see bdl_profile) */
+
+/* Phases timed under BDL_FLAG_PROFILE. */
+#define BDL_PH_GATHER 0    /* Insert_L: gather of the points of new trees */
+#define BDL_PH_PASSES 1    /* Insert_L: per-depth split/partition passes */
+#define BDL_PH_FINISH 2    /* Insert_L: LDS subtree finisher */
+#define BDL_PH_LAYOUT 3    /* Insert_L: vEB ordering and node write-out */
+#define BDL_PH_ERASE 4     /* Erase_L: locate and tombstone */
+#define BDL_PH_ORDER 5     /* kNN_L: Morton ordering of the queries */
+#define BDL_PH_TRAVERSE 6  /* kNN_L: the traversal kernel */
+#define BDL_NPHASES 8
+
+typedef struct bdl_tree bdl_tree; /* opaque, owned by the library */
+
+typedef struct {
+  int32_t dim;          /* d, 1..16 */
+  int32_t leaf_size;    /* points per leaf, >= 1 (Section V-D uses 16) */
+  int32_t buffer_size;  /* X, >= 1 (Section V-D uses 1024) */
+  uint32_t id_capacity; /* every id must be < id_capacity (sizes the id map) */
+  uint64_t mem_budget;  /* device bytes the library may hold; 0 = unlimited */
+  uint32_t flags;       /* BDL_FLAG_* */
+} bdl_config;
+
+/* Create an empty tree whose work is ordered on `stream` (a hipStream_t;
+ * NULL is the null stream).  *out receives the handle. */
+int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out);
+
+/* Insert_L (Alg. 3).  pts: device, row-major [n][dim] float32; ids: device
+ * [n] uint32.  Preconditions: coordinates finite, ids < id_capacity and not
+ * live (not currently in the tree, not repeated in the batch).  With
+ * BDL_FLAG_CHECK_INPUTS a violation of the first two and of "not live" is
+ * reported as BDL_EINVAL with the tree unchanged; otherwise violating
+ * inputs give undefined results (never out-of-bounds accesses).  Input
+ * buffers may be reused once the call returns. */
+int bdl_insert(bdl_tree* t, const float* pts, const uint32_t* ids, int64_t n);
+
+/* Erase_L (Alg. 4).  A pair (pts[i], ids[i]) erases the live point with
+ * that id if its stored coordinates are bitwise equal to pts[i]; otherwise
+ * it is a no-op.  A repeated id erases once.  Afterwards every static tree
+ * whose live count is below half of its capacity 2^i X is rebuilt through
+ * Insert_L.  Synchronises the stream once to read the per-tree live counts.
+ * n_erased (host, may be NULL) receives the number of points erased. */
+int bdl_erase(bdl_tree* t, const float* pts, const uint32_t* ids, int64_t n,
+              int64_t* n_erased);
+
+/* kNN_L (Alg. 5).  q: device [nq][dim] float32; out_ids: device [nq][k]
+ * uint32; out_d2: device [nq][k] float32.  Row i holds the k live points
+ * nearest to q[i], ascending by (squared distance, id), where the squared
+ * distance is the float32 sum over dimensions, in order, of fmaf(t, t, acc)
+ * with t = q[j] - p[j].  Rows with fewer than k live points are padded with
+ * (BDL_INVALID_ID, +inf).  A query equal to a live point returns it at 0.
+ * 1 <= k <= BDL_MAX_K.  Asynchronous. */
+int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_ids,
+            float* out_d2);
+
+/* Remove every point.  Device memory stays allocated for reuse; the tree
+ * is then as if just created.  Asynchronous. */
+int bdl_clear(bdl_tree* t);
+
+/* Device time accumulated per phase since creation or the last reset
+ * (milliseconds, from HIP events recorded on the tree's stream around the
+ * phase's kernels) and the number of times each phase ran.  Synchronises the
+ * stream.  All zero unless the tree was created with BDL_FLAG_PROFILE. */
+typedef struct {
+  double ms[BDL_NPHASES];
+  int64_t calls[BDL_NPHASES];
+} bdl_profile_t;
+int bdl_profile(bdl_tree* t, bdl_profile_t* out, int reset);
+
+/* Block until all work enqueued on the tree's stream has finished.  Returns
+ * BDL_EHIP if a k-NN traversal since the last call met an out-of-range tree
+ * index (a corrupt tree; never expected). */
+int bdl_sync(bdl_tree* t);
+
+void bdl_destroy(bdl_tree* t);
+
+/* Number of live points. */
+int64_t bdl_size(const bdl_tree* t);
+
+/* Host arrays of at least 64 entries: live and capacity of static tree i
+ * for i < *nlev (live 0 for an empty tree); *buf_live receives the buffer's
+ * point count, *F the bitmask of non-empty trees.  Any pointer may be NULL. */
+int bdl_level_info(const bdl_tree* t, int32_t* nlev, int64_t* live, int64_t* cap,
+                   int64_t* buf_live, uint64_t* F);
+
+/* Host arrays of at least 64 entries: slots (points at build time) and
+ * node count of static tree i for i < *nlev; the buffer tree's node count in
+ * *buf_nodes.  Any pointer may be NULL. */
+int bdl_level_sizes(const bdl_tree* t, int32_t* nlev, int64_t* n_slots, int64_t* n_nodes,
+                    int64_t* buf_nodes);
+
+/* Cumulative counters: points written by static-tree builds and points
+ * moved by Erase_L's half-capacity rebuilds.  Any pointer may be NULL. */
+int bdl_counters(const bdl_tree* t, int64_t* rebuilt_points, int64_t* reinserted_points);
+
+/* Node layout of bdl_debug_export_level (host memory, one per node). */
+typedef struct {
+  float lo[BDL_MAX_DIM];   /* tight bounding box of the subtree's points */
+  float hi[BDL_MAX_DIM];
+  float split;             /* internal: left child holds x[dim] < split */
+  int32_t dim;             /* split dimension, -1 for a leaf */
+  int32_t left, right;     /* child node indices, -1 for a leaf */
+  int32_t parent;          /* -1 for the root */
+  int32_t begin, count;    /* slot range of the subtree */
+  int32_t depth;
+  int32_t pad_;
+  uint64_t path;           /* left/right moves from the root, first move in
+                              the most significant of `depth` bits */
+} bdl_node;
+
+/* Copy static tree `level` (0..63) or, for level == -1, the buffer's tree,
+ * to host memory: ids[n_slots] (BDL_INVALID_ID for an erased slot),
+ * pts[n_slots][dim] in slot order, and nodes[n_nodes] in vEB order.  Any
+ * output pointer may be NULL; *n_slots / *n_nodes always receive the sizes.
+ * Synchronises the stream.  Returns BDL_EINVAL for an empty tree. */
+int bdl_debug_export_level(bdl_tree* t, int32_t level, uint32_t* ids, float* pts,
+                           bdl_node* nodes, int64_t* n_slots, int64_t* n_nodes);
+
+/* The buffer's points in arrival order (host outputs, may be NULL). */
+int bdl_debug_export_buffer(bdl_tree* t, uint32_t* ids, float* pts, int64_t* n);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* bdl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BDL_H */

@@ -1,0 +1,312 @@
+"""MI355X BDL-tree: Python binding of the C ABI in include/bdl.h.
+
+The binding only marshals arguments: torch supplies device memory and the
+stream, and every step of Insert_L, Erase_L and kNN_L runs in the HIP
+kernels of libbdl.so.  Importing works without a GPU (so that the library's
+exports can be inspected); creating a tree needs the built library and a
+GPU, and fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbdl.so")
+
+BDL_OK = 0
+BDL_EINVAL = -1
+BDL_ENOMEM = -2
+BDL_EHIP = -3
+MAX_DIM = 16
+MAX_K = 64
+INVALID_ID = 0xFFFFFFFF
+FLAG_CHECK_INPUTS = 1
+
+# Every symbol include/bdl.h declares.
+EXPORTS = [
+    "bdl_create", "bdl_insert", "bdl_erase", "bdl_knn", "bdl_clear", "bdl_sync", "bdl_destroy",
+    "bdl_size", "bdl_level_info", "bdl_counters", "bdl_debug_export_level",
+    "bdl_debug_export_buffer", "bdl_last_error", "bdl_profile", "bdl_level_sizes",
+]
+FLAG_PROFILE = 2
+PHASES = ["gather", "passes", "finish", "layout", "erase", "order", "traverse", "other"]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("calls", ctypes.c_int64 * 8)]
+
+NODE_DTYPE = np.dtype([
+    ("lo", np.float32, (MAX_DIM,)),
+    ("hi", np.float32, (MAX_DIM,)),
+    ("split", np.float32),
+    ("dim", np.int32),
+    ("left", np.int32),
+    ("right", np.int32),
+    ("parent", np.int32),
+    ("begin", np.int32),
+    ("count", np.int32),
+    ("depth", np.int32),
+    ("pad_", np.int32),
+    ("path", np.uint64),
+], align=True)
+
+
+class BdlError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"bdl error {code}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("leaf_size", ctypes.c_int32),
+        ("buffer_size", ctypes.c_int32),
+        ("id_capacity", ctypes.c_uint32),
+        ("mem_budget", ctypes.c_uint64),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libbdl.so and declare its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, u32p, f32p = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float))
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.bdl_create.argtypes = [ctypes.POINTER(Config), vp, ctypes.POINTER(vp)]
+    lib.bdl_insert.argtypes = [vp, vp, vp, i64]
+    lib.bdl_erase.argtypes = [vp, vp, vp, i64, i64p]
+    lib.bdl_knn.argtypes = [vp, vp, i64, i32, vp, vp]
+    lib.bdl_sync.argtypes = [vp]
+    lib.bdl_clear.argtypes = [vp]
+    lib.bdl_profile.argtypes = [vp, ctypes.POINTER(Profile), ctypes.c_int]
+    lib.bdl_destroy.argtypes = [vp]
+    lib.bdl_destroy.restype = None
+    lib.bdl_size.argtypes = [vp]
+    lib.bdl_size.restype = i64
+    lib.bdl_level_info.argtypes = [vp, ctypes.POINTER(i32), i64p, i64p, i64p,
+                                   ctypes.POINTER(ctypes.c_uint64)]
+    lib.bdl_counters.argtypes = [vp, i64p, i64p]
+    lib.bdl_level_sizes.argtypes = [vp, ctypes.POINTER(i32), i64p, i64p, i64p]
+    lib.bdl_debug_export_level.argtypes = [vp, i32, u32p, f32p, vp, i64p, i64p]
+    lib.bdl_debug_export_buffer.argtypes = [vp, u32p, f32p, i64p]
+    lib.bdl_last_error.restype = ctypes.c_char_p
+    for name in ("bdl_create", "bdl_insert", "bdl_erase", "bdl_knn", "bdl_clear", "bdl_sync",
+                 "bdl_profile", "bdl_level_sizes",
+                 "bdl_level_info", "bdl_counters", "bdl_debug_export_level",
+                 "bdl_debug_export_buffer"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        msg = _lib.bdl_last_error().decode(errors="replace")
+        raise BdlError(rc, msg)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Tree:
+    """A BDL-tree resident in HBM of one GPU.
+
+    Points and queries are CUDA (HIP) float32 tensors of shape [n, dim];
+    ids are int32 or uint32 tensors holding the uint32 ids bit for bit.
+    All work is ordered on the stream that is current at construction.
+    """
+
+    def __init__(self, dim: int, leaf_size: int = 16, buffer_size: int = 1024,
+                 id_capacity: int = 1 << 24, mem_budget: int = 0, check_inputs: bool = False,
+                 profile: bool = False, device: Optional[int] = None, stream=None):
+        torch = _torch()
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("a GPU is required: the BDL-tree runs only in HIP kernels")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.dim = int(dim)
+        self.leaf_size = int(leaf_size)
+        self.buffer_size = int(buffer_size)
+        self.id_capacity = int(id_capacity)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            flags = (FLAG_CHECK_INPUTS if check_inputs else 0) | (FLAG_PROFILE if profile else 0)
+            cfg = Config(self.dim, self.leaf_size, self.buffer_size, self.id_capacity,
+                         int(mem_budget), flags)
+            h = ctypes.c_void_p()
+            _check(lib.bdl_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
+                                  ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+
+    # -- lifetime --------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.bdl_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- marshalling -----------------------------------------------------
+    def _pts(self, x, name: str):
+        torch = _torch()
+        if not isinstance(x, torch.Tensor):
+            x = torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32))
+        if x.dtype != torch.float32:
+            raise TypeError(f"{name} must be float32")
+        if x.dim() != 2 or x.shape[1] != self.dim:
+            raise ValueError(f"{name} must have shape [n, {self.dim}]")
+        return x.to(self.device).contiguous()
+
+    def _ids(self, x, n: int):
+        torch = _torch()
+        if not isinstance(x, torch.Tensor):
+            x = torch.from_numpy(np.ascontiguousarray(x, dtype=np.uint32).view(np.int32))
+        if x.dtype not in (torch.int32, getattr(torch, "uint32", torch.int32)):
+            raise TypeError("ids must be int32 or uint32")
+        x = x.reshape(-1)
+        if x.shape[0] != n:
+            raise ValueError("ids and points differ in length")
+        return x.to(self.device).contiguous()
+
+    # -- operations ------------------------------------------------------
+    def insert(self, pts, ids) -> None:
+        """Insert_L (Alg. 3)."""
+        p = self._pts(pts, "pts")
+        i = self._ids(ids, p.shape[0])
+        with _torch().cuda.device(self.device):
+            _check(self._lib.bdl_insert(self._h, ctypes.c_void_p(p.data_ptr()),
+                                        ctypes.c_void_p(i.data_ptr()), p.shape[0]))
+
+    def erase(self, pts, ids) -> int:
+        """Erase_L (Alg. 4); returns the number of points erased."""
+        p = self._pts(pts, "pts")
+        i = self._ids(ids, p.shape[0])
+        out = ctypes.c_int64()
+        with _torch().cuda.device(self.device):
+            _check(self._lib.bdl_erase(self._h, ctypes.c_void_p(p.data_ptr()),
+                                       ctypes.c_void_p(i.data_ptr()), p.shape[0],
+                                       ctypes.byref(out)))
+        return int(out.value)
+
+    def knn(self, q, k: int, out_ids=None, out_d2=None):
+        """kNN_L (Alg. 5): (ids int32 [nq, k], squared distances float32 [nq, k])."""
+        torch = _torch()
+        qq = self._pts(q, "q")
+        nq = qq.shape[0]
+        if out_ids is None:
+            out_ids = torch.empty((nq, k), dtype=torch.int32, device=self.device)
+        if out_d2 is None:
+            out_d2 = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(self._lib.bdl_knn(self._h, ctypes.c_void_p(qq.data_ptr()), nq, int(k),
+                                     ctypes.c_void_p(out_ids.data_ptr()),
+                                     ctypes.c_void_p(out_d2.data_ptr())))
+        return out_ids, out_d2
+
+    def sync(self) -> None:
+        _check(self._lib.bdl_sync(self._h))
+
+    def profile(self, reset: bool = False) -> Dict[str, Dict[str, float]]:
+        """Per-phase device milliseconds and call counts (BDL_FLAG_PROFILE)."""
+        p = Profile()
+        _check(self._lib.bdl_profile(self._h, ctypes.byref(p), 1 if reset else 0))
+        return {name: {"ms": p.ms[i], "calls": p.calls[i]} for i, name in enumerate(PHASES)}
+
+    def clear(self) -> None:
+        """Remove every point; device memory is kept for reuse."""
+        _check(self._lib.bdl_clear(self._h))
+
+    def size(self) -> int:
+        return int(self._lib.bdl_size(self._h))
+
+    def level_info(self) -> Dict:
+        nlev = ctypes.c_int32()
+        live = np.zeros(64, np.int64)
+        cap = np.zeros(64, np.int64)
+        buf = ctypes.c_int64()
+        F = ctypes.c_uint64()
+        p64 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        _check(self._lib.bdl_level_info(self._h, ctypes.byref(nlev), p64(live), p64(cap),
+                                        ctypes.byref(buf), ctypes.byref(F)))
+        n = nlev.value
+        return {"nlev": n, "live": live[:n].copy(), "cap": cap[:n].copy(),
+                "buf_live": buf.value, "F": F.value}
+
+    def level_sizes(self) -> Dict:
+        nlev = ctypes.c_int32()
+        slots = np.zeros(64, np.int64)
+        nodes = np.zeros(64, np.int64)
+        bnodes = ctypes.c_int64()
+        p64 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        _check(self._lib.bdl_level_sizes(self._h, ctypes.byref(nlev), p64(slots), p64(nodes),
+                                         ctypes.byref(bnodes)))
+        n = nlev.value
+        return {"slots": slots[:n].copy(), "nodes": nodes[:n].copy(), "buf_nodes": bnodes.value}
+
+    def counters(self) -> Dict:
+        rb = ctypes.c_int64()
+        ri = ctypes.c_int64()
+        _check(self._lib.bdl_counters(self._h, ctypes.byref(rb), ctypes.byref(ri)))
+        return {"rebuilt": rb.value, "reinserted": ri.value}
+
+    def export_level(self, level: int) -> Optional[Tuple[np.ndarray, np.ndarray, np.ndarray]]:
+        """(ids uint32 [n], pts float32 [n, d], nodes NODE_DTYPE [m]) of static tree
+        `level` (-1: the buffer's tree), or None if that tree is empty."""
+        ns = ctypes.c_int64()
+        nn = ctypes.c_int64()
+        rc = self._lib.bdl_debug_export_level(self._h, level, None, None, None,
+                                              ctypes.byref(ns), ctypes.byref(nn))
+        if rc != 0 or ns.value == 0:
+            return None
+        ids = np.empty(ns.value, np.uint32)
+        pts = np.empty((ns.value, self.dim), np.float32)
+        nodes = np.empty(nn.value, NODE_DTYPE)
+        _check(self._lib.bdl_debug_export_level(
+            self._h, level, ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+            pts.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+            nodes.ctypes.data_as(ctypes.c_void_p), ctypes.byref(ns), ctypes.byref(nn)))
+        return ids, pts, nodes
+
+    def export_buffer(self) -> Tuple[np.ndarray, np.ndarray]:
+        n = ctypes.c_int64()
+        _check(self._lib.bdl_debug_export_buffer(self._h, None, None, ctypes.byref(n)))
+        ids = np.empty(n.value, np.uint32)
+        pts = np.empty((n.value, self.dim), np.float32)
+        if n.value:
+            _check(self._lib.bdl_debug_export_buffer(
+                self._h, ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                pts.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(n)))
+        return ids, pts
+
+
+def build(verbose: bool = False) -> str:
+    from .build_lib import build as _b
+    return _b(verbose=verbose)

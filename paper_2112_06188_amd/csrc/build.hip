@@ -1,0 +1,1215 @@
+// Static kd-tree construction for Insert_L on gfx950.
+//
+// BuildvEB (Alg. 1) with the spatial median (Section V-C), data-parallel
+// over every tree an Insert_L call builds:
+//  1. gather: the points of each new tree go to a contiguous range of a
+//     structure-of-arrays build buffer (Insert_L's "deconstruct and gather");
+//  2. global passes, one depth per pass, for nodes with more points than the
+//     LDS finisher holds: split choice per node, a count of left points per
+//     4096-point tile, a prefix sum over tiles and a stable scatter into the
+//     other build buffer that also accumulates the children's tight boxes;
+//  3. the LDS finisher: one workgroup builds a whole small subtree in LDS and
+//     writes its points as records in final slot order;
+//  4. layout: every node emitted above is keyed by its position in the van
+//     Emde Boas order of the tree's height, sorted, and written out with
+//     child and parent indices.
+// The result is identical to a serial recursive build: splits depend only on
+// a node's point set, and every partition is stable.
+#include "bdl.h"
+#include "build.hpp"
+#include "primitives.hpp"
+
+namespace bdl {
+
+namespace {
+
+constexpr uint16_t kFrozen = 0xFFFF;
+
+__device__ inline const uint32_t* soa_ids(const float* soa, int d, uint64_t cap) {
+  return reinterpret_cast<const uint32_t*>(soa + (uint64_t)d * cap);
+}
+__device__ inline uint32_t* soa_ids_w(float* soa, int d, uint64_t cap) {
+  return reinterpret_cast<uint32_t*>(soa + (uint64_t)d * cap);
+}
+
+__device__ inline uint64_t lanemask_lt() {
+  const int lane = __lane_id();
+  return lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+// Spatial-median split of a node with ordered-u32 box lo[j] / hi[j]
+// (Section V-C): dimension depth mod d moved forward to the first dimension
+// with non-zero extent, value = midpoint of the tight extent; if rounding
+// puts the midpoint on the lower bound (or the sum overflows), the upper
+// bound is used so that both sides are non-empty.
+__device__ inline void choose_split(const uint32_t* lo, const uint32_t* hi, int d, int depth,
+                                    int* dim_out, float* split_out) {
+  int c = depth % d;
+  for (int it = 0; it < d && !(hi[c] > lo[c]); ++it) c = (c + 1 == d) ? 0 : c + 1;
+  float mn = o2f(lo[c]);
+  float mx = o2f(hi[c]);
+  float split = (mn + mx) * 0.5f;
+  if (!(split > mn) || split > mx) split = mx;
+  *dim_out = c;
+  *split_out = split;
+}
+
+__device__ inline void write_emit(uint32_t* emit, int es, uint32_t idx, uint64_t path,
+                                  uint32_t depth, uint32_t job, uint32_t parent, uint32_t side,
+                                  uint32_t begin, uint32_t count, float split, int dim,
+                                  const uint32_t* lo, const uint32_t* hi, int d) {
+  uint32_t* e = emit + (uint64_t)idx * es;
+  e[EF_PATH_LO] = (uint32_t)path;
+  e[EF_PATH_HI] = (uint32_t)(path >> 32);
+  e[EF_DEPTH] = depth;
+  e[EF_JOB] = job;
+  e[EF_PARENT] = parent;
+  e[EF_SIDE] = side;
+  e[EF_BEGIN] = begin;
+  e[EF_COUNT] = count;
+  e[EF_SPLIT] = __float_as_uint(split);
+  e[EF_DIM] = (uint32_t)dim;
+  for (int j = 0; j < d; ++j) {
+    e[EF_BOX + j] = o2f_bits(lo[j]);
+    e[EF_BOX + d + j] = o2f_bits(hi[j]);
+  }
+}
+
+__device__ inline void wave_minmax(uint32_t& mn, uint32_t& mx) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    uint32_t a = __shfl_xor(mn, o, 64);
+    uint32_t b = __shfl_xor(mx, o, 64);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+}
+
+__device__ inline uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// largest s with segtb[s] <= t (segtb strictly increasing, segtb[0] = 0)
+__device__ inline uint32_t find_seg(const uint32_t* segtb, uint32_t ns, uint32_t t) {
+  uint32_t lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi + 1) >> 1;
+    if (segtb[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------------------
+// gather
+// ------------------------------------------------------------------------
+
+__global__ void k_pool_to_soa(PoolSrc src, int d, uint64_t p0, uint64_t cnt, float* soa,
+                              uint64_t cap, uint64_t dst) {
+  const int S = rec_stride(d);
+  uint32_t* ids = soa_ids_w(soa, d, cap);
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t i = p0 + e;
+    uint64_t o = dst + e;
+    uint32_t id;
+    const float* r;
+    if (i < src.bn) {
+      r = src.bufrec + i * S;
+      id = __float_as_uint(r[d]);
+    } else {
+      uint64_t b = i - src.bn;
+      if (src.batch_ids) {
+        r = src.batch + b * d;
+        id = src.batch_ids[b];
+      } else {
+        r = src.batch + b * S;
+        id = __float_as_uint(r[d]);
+      }
+    }
+    for (int j = 0; j < d; ++j) soa[(uint64_t)j * cap + o] = r[j];
+    ids[o] = id;
+  }
+}
+
+__global__ void k_pool_to_records(PoolSrc src, int d, uint64_t p0, uint64_t cnt, float* out,
+                                  uint64_t* map, uint32_t idcap) {
+  const int S = rec_stride(d);
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t i = p0 + e;
+    uint32_t id;
+    const float* r;
+    if (i < src.bn) {
+      r = src.bufrec + i * S;
+      id = __float_as_uint(r[d]);
+    } else {
+      uint64_t b = i - src.bn;
+      if (src.batch_ids) {
+        r = src.batch + b * d;
+        id = src.batch_ids[b];
+      } else {
+        r = src.batch + b * S;
+        id = __float_as_uint(r[d]);
+      }
+    }
+    float* w = out + e * S;
+    for (int j = 0; j < d; ++j) w[j] = r[j];
+    w[d] = __uint_as_float(id);
+    for (int j = d + 1; j < S; ++j) w[j] = 0.0f;
+    if (map && id < idcap) map[id] = ((uint64_t)kBufferLevel << 32) | (uint64_t)e;
+  }
+}
+
+__global__ void k_records_to_soa(const float* rec, int d, uint64_t n, float* soa, uint64_t cap,
+                                 uint64_t dst) {
+  const int S = rec_stride(d);
+  uint32_t* ids = soa_ids_w(soa, d, cap);
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    const float* r = rec + e * S;
+    for (int j = 0; j < d; ++j) soa[(uint64_t)j * cap + dst + e] = r[j];
+    ids[dst + e] = __float_as_uint(r[d]);
+  }
+}
+
+__global__ void __launch_bounds__(kPassThreads)
+k_count_live(const float* rec, int d, uint64_t n, uint32_t* tile_cnt) {
+  __shared__ uint32_t red[4];
+  const int S = rec_stride(d);
+  const uint64_t t0 = (uint64_t)blockIdx.x * kTile;
+  uint32_t c = 0;
+  for (int r = 0; r < kItems; ++r) {
+    uint64_t i = t0 + (uint64_t)r * kPassThreads + threadIdx.x;
+    if (i < n && __float_as_uint(rec[i * S + d]) != kTomb) ++c;
+  }
+  c = wave_sum(c);
+  if (__lane_id() == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) tile_cnt[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// Stable compaction of the live records of one tile to out positions
+// tile_off[tile] + rank, either into build buffers (soa) or into records.
+__global__ void __launch_bounds__(kPassThreads)
+k_compact_live(const float* rec, int d, uint64_t n, const uint32_t* tile_off, float* soa,
+               uint64_t cap, uint64_t dst, float* out_rec) {
+  __shared__ uint32_t lt[kItems][4];
+  const int S = rec_stride(d);
+  const int lane = __lane_id();
+  const int w = threadIdx.x >> 6;
+  const uint64_t t0 = (uint64_t)blockIdx.x * kTile;
+  uint64_t m[kItems];
+  uint32_t fl = 0;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    uint64_t i = t0 + (uint64_t)r * kPassThreads + threadIdx.x;
+    bool f = i < n && __float_as_uint(rec[i * S + d]) != kTomb;
+    fl |= (uint32_t)f << r;
+    m[r] = __ballot(f);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) lt[r][w] = (uint32_t)__popcll(m[r]);
+  }
+  __syncthreads();
+  const uint64_t ltm = lanemask_lt();
+  uint32_t run = 0;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    uint32_t before = 0, row = 0;
+    for (int v = 0; v < 4; ++v) {
+      uint32_t x = lt[r][v];
+      before += v < w ? x : 0u;
+      row += x;
+    }
+    if ((fl >> r) & 1u) {
+      uint64_t i = t0 + (uint64_t)r * kPassThreads + threadIdx.x;
+      uint64_t o = (uint64_t)tile_off[blockIdx.x] + run + before + (uint32_t)__popcll(m[r] & ltm);
+      const float* src = rec + i * S;
+      if (out_rec) {
+        float* wr = out_rec + o * S;
+        for (int j = 0; j < S; ++j) wr[j] = src[j];
+      } else {
+        for (int j = 0; j < d; ++j) soa[(uint64_t)j * cap + dst + o] = src[j];
+        soa_ids_w(soa, d, cap)[dst + o] = __float_as_uint(src[d]);
+      }
+    }
+    run += row;
+  }
+}
+
+// ------------------------------------------------------------------------
+// build setup
+// ------------------------------------------------------------------------
+
+__global__ void k_reset_counters(BuildCounters* c, JobTable jt, Job* jobs_dev) {
+  const int t = threadIdx.x;
+  if (t == 0) {
+    c->nseg[0] = c->nseg[1] = 0;
+    c->ntiles = c->nfin = c->nemit = c->err = 0;
+  }
+  if (t < kMaxJobs) {
+    c->job_nodes[t] = 0;
+    c->job_height[t] = 0;
+    c->job_node_off[t] = 0;
+    for (int j = 0; j < kMaxDim; ++j) {
+      c->job_box[t][j] = 0xFFFFFFFFu;
+      c->job_box[t][kMaxDim + j] = 0u;
+    }
+    if (t < jt.n) jobs_dev[t] = jt.jobs[t];
+  }
+}
+
+__global__ void __launch_bounds__(kPassThreads)
+k_root_box(const float* soa, uint64_t cap, int d, const Job* jobs, BuildCounters* c) {
+  __shared__ uint32_t red[8];
+  const Job J = jobs[blockIdx.y];
+  const uint64_t t0 = (uint64_t)blockIdx.x * kTile;
+  if (t0 >= J.count) return;
+  const int lane = __lane_id();
+  const int w = threadIdx.x >> 6;
+  for (int j = 0; j < d; ++j) {
+    uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+    const float* x = soa + (uint64_t)j * cap + J.base;
+    for (int r = 0; r < kItems; ++r) {
+      uint64_t i = t0 + (uint64_t)r * kPassThreads + threadIdx.x;
+      if (i < J.count) {
+        uint32_t o = f2o(x[i]);
+        mn = o < mn ? o : mn;
+        mx = o > mx ? o : mx;
+      }
+    }
+    wave_minmax(mn, mx);
+    if (lane == 0) {
+      red[w] = mn;
+      red[4 + w] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int v = 1; v < 4; ++v) {
+        mn = red[v] < mn ? red[v] : mn;
+        mx = red[4 + v] > mx ? red[4 + v] : mx;
+      }
+      atomicMin(&c->job_box[blockIdx.y][j], mn);
+      atomicMax(&c->job_box[blockIdx.y][kMaxDim + j], mx);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_init_lists(const Job* jobs, int njobs, BuildCounters* c, Seg* cur, Fin* fin,
+                             uint32_t T, uint64_t max_seg, uint64_t max_fin) {
+  if (threadIdx.x != 0) return;
+  for (int jb = 0; jb < njobs; ++jb) {
+    const Job J = jobs[jb];
+    if (J.count == 0) continue;
+    if (J.count > T) {
+      uint32_t k = c->nseg[0]++;
+      if (k >= max_seg) { c->err |= 1u; return; }
+      Seg& g = cur[k];
+      g.begin = J.base;
+      g.count = J.count;
+      g.job = (uint32_t)jb;
+      g.depth = 0;
+      g.path = 0;
+      g.parent_emit = kNone;
+      g.side = 0;
+      for (int j = 0; j < 2 * kMaxDim; ++j) g.box[j] = c->job_box[jb][j];
+    } else {
+      uint32_t f = c->nfin++;
+      if (f >= max_fin) { c->err |= 2u; return; }
+      Fin& F = fin[f];
+      F.begin = J.base;
+      F.count = J.count;
+      F.job = (uint32_t)jb;
+      F.depth = 0;
+      F.path = 0;
+      F.parent_emit = kNone;
+      F.side = 0;
+      F.bufsel = 0;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// global passes (one depth per pass)
+// ------------------------------------------------------------------------
+
+// Decide every segment of this depth: emit its node, pick its split (or mark
+// it a leaf copied out whole), and number its tiles.
+__global__ void __launch_bounds__(1024)
+k_setup(Seg* cur, uint32_t* segtb, BuildCounters* c, int par, const Job* jobs, uint32_t* emit,
+        int es, int d, uint32_t leaf, uint64_t max_emit, uint64_t max_seg, uint64_t max_tiles) {
+  __shared__ uint32_t wsum[17];
+  __shared__ uint32_t s_base, s_n;
+  if (threadIdx.x == 0) {
+    uint32_t nn = c->nseg[par];
+    if (nn > max_seg || c->err) {
+      // an overflow was flagged: stop working on this build
+      c->err |= nn > max_seg ? 8u : 0u;
+      nn = 0;
+    }
+    c->nseg[par] = nn;
+    s_n = nn;
+    s_base = c->nemit;
+    c->nseg[par ^ 1] = 0;
+  }
+  __syncthreads();
+  const uint32_t n = s_n;
+  if ((uint64_t)s_base + n > max_emit) {
+    if (threadIdx.x == 0) {
+      c->err |= 4u;
+      c->ntiles = 0;
+      c->nseg[par] = 0;
+    }
+    return;
+  }
+  uint32_t carry = 0;
+  for (uint32_t ch = 0; ch < n; ch += blockDim.x) {
+    uint32_t s = ch + threadIdx.x;
+    uint32_t ntl = 0;
+    if (s < n) {
+      Seg& g = cur[s];
+      const uint32_t* lo = g.box;
+      const uint32_t* hi = g.box + kMaxDim;
+      bool degenerate = true;
+      for (int j = 0; j < d; ++j) degenerate = degenerate && (lo[j] == hi[j]);
+      bool isleaf = g.count <= leaf || degenerate || g.depth >= (uint32_t)kMaxDepth;
+      int dim = -1;
+      float split = 0.0f;
+      if (!isleaf) choose_split(lo, hi, d, (int)g.depth, &dim, &split);
+      const uint32_t eidx = s_base + s;
+      const Job& J = jobs[g.job];
+      write_emit(emit, es, eidx, g.path, g.depth, g.job, g.parent_emit, g.side,
+                 g.begin - J.base, g.count, split, dim, lo, hi, d);
+      atomicAdd(&c->job_nodes[g.job], 1u);
+      atomicMax(&c->job_height[g.job], g.depth + 1);
+      g.emit = eidx;
+      g.dim = dim;
+      g.split = split;
+      ntl = (g.count + kTile - 1) / kTile;
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(ntl, wsum, &tot);
+    if (s < n) {
+      cur[s].tile_begin = carry + ex;
+      cur[s].ntiles = ntl;
+      segtb[s] = carry + ex;
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    if (carry > max_tiles) {
+      c->err |= 256u;
+      c->nseg[par] = 0;
+      carry = 0;
+    }
+    c->ntiles = carry;
+    c->nemit = s_base + n;
+  }
+}
+
+__global__ void __launch_bounds__(kPassThreads)
+k_count(const Seg* cur, const uint32_t* segtb, const BuildCounters* c, int par,
+        const float* src, uint64_t cap, uint32_t* tile_left) {
+  __shared__ uint32_t red[4];
+  const uint32_t nt = c->ntiles;
+  const uint32_t ns = c->nseg[par];
+  for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    const uint32_t s = find_seg(segtb, ns, t);
+    const Seg& g = cur[s];
+    const int dim = g.dim;
+    if (dim < 0) {
+      if (threadIdx.x == 0) tile_left[t] = 0;
+      continue;
+    }
+    const float split = g.split;
+    const uint64_t tstart = (uint64_t)g.begin + (uint64_t)(t - g.tile_begin) * kTile;
+    const uint64_t tend = min((uint64_t)g.begin + g.count, tstart + kTile);
+    const float* x = src + (uint64_t)dim * cap;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      uint64_t i = tstart + (uint64_t)r * kPassThreads + threadIdx.x;
+      if (i < tend && x[i] < split) ++cnt;
+    }
+    cnt = wave_sum(cnt);
+    if (__lane_id() == 0) red[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) tile_left[t] = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+  }
+}
+
+// Prefix sum of the tiles' left counts; create the children of every split
+// segment: large ones go to the next depth's list, small ones to the
+// finisher.
+__global__ void __launch_bounds__(1024)
+k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_left,
+           uint32_t* tile_off, Fin* fin, uint32_t T, uint64_t max_seg, uint64_t max_fin) {
+  __shared__ uint32_t wsum[17];
+  const uint32_t nt = c->ntiles;
+  const uint32_t ns = c->nseg[par];
+  uint32_t carry = 0;
+  for (uint32_t ch = 0; ch < nt; ch += blockDim.x) {
+    uint32_t t = ch + threadIdx.x;
+    uint32_t v = t < nt ? tile_left[t] : 0u;
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(v, wsum, &tot);
+    if (t < nt) tile_off[t] = carry + ex;
+    carry += tot;
+  }
+  __syncthreads();
+  for (uint32_t s = threadIdx.x; s < ns; s += blockDim.x) {
+    Seg& g = cur[s];
+    if (g.dim < 0) {
+      g.child[0] = g.child[1] = kNone;
+      continue;
+    }
+    const uint32_t last = g.tile_begin + g.ntiles;
+    const uint32_t g0 = tile_off[g.tile_begin];
+    const uint32_t g1 = last < nt ? tile_off[last] : carry;
+    const uint32_t nl = g1 - g0;
+    g.nleft = nl;
+    for (int side = 0; side < 2; ++side) {
+      const uint32_t cb = side ? g.begin + nl : g.begin;
+      const uint32_t cc = side ? g.count - nl : nl;
+      const uint64_t cpath = (g.path << 1) | (uint64_t)side;
+      if (cc > T) {
+        uint32_t k = atomicAdd(&c->nseg[par ^ 1], 1u);
+        if (k >= max_seg) {
+          atomicOr(&c->err, 8u);
+          g.child[side] = kNone;
+          continue;
+        }
+        Seg& h = nxt[k];
+        h.begin = cb;
+        h.count = cc;
+        h.job = g.job;
+        h.depth = g.depth + 1;
+        h.path = cpath;
+        h.parent_emit = g.emit;
+        h.side = (uint32_t)side;
+        for (int j = 0; j < kMaxDim; ++j) {
+          h.box[j] = 0xFFFFFFFFu;
+          h.box[kMaxDim + j] = 0u;
+        }
+        g.child[side] = k;
+      } else {
+        uint32_t f = atomicAdd(&c->nfin, 1u);
+        g.child[side] = kNone;
+        if (f >= max_fin) {
+          atomicOr(&c->err, 16u);
+          continue;
+        }
+        Fin& F = fin[f];
+        F.begin = cb;
+        F.count = cc;
+        F.job = g.job;
+        F.depth = g.depth + 1;
+        F.path = cpath;
+        F.parent_emit = g.emit;
+        F.side = (uint32_t)side;
+        F.bufsel = (uint32_t)(par ^ 1);
+      }
+    }
+  }
+}
+
+// Stable partition of every tile into the other build buffer; accumulates
+// the tight boxes of children that stay in the global passes; leaves that
+// are too large for the finisher (coincident points) are copied out whole.
+__global__ void __launch_bounds__(kPassThreads)
+k_scatter(const Seg* cur, const uint32_t* segtb, Seg* nxt, const BuildCounters* c, int par,
+          const float* src, float* dst, uint64_t cap, int d, const uint32_t* tile_off,
+          const Job* jobs, uint64_t* map, uint32_t idcap) {
+  __shared__ uint32_t lt[kItems][4];
+  __shared__ uint32_t red[4][4];
+  const uint32_t nt = c->ntiles;
+  const uint32_t ns = c->nseg[par];
+  const int lane = __lane_id();
+  const int w = threadIdx.x >> 6;
+  const uint64_t ltm = lanemask_lt();
+  const uint32_t* sid = soa_ids(src, d, cap);
+  uint32_t* did = soa_ids_w(dst, d, cap);
+  for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    const uint32_t s = find_seg(segtb, ns, t);
+    const Seg& g = cur[s];
+    const uint64_t gbegin = g.begin;
+    const uint64_t tstart = gbegin + (uint64_t)(t - g.tile_begin) * kTile;
+    const uint64_t tend = min(gbegin + g.count, tstart + kTile);
+    const uint32_t tcnt = (uint32_t)(tend - tstart);
+    const int dim = g.dim;
+    if (dim < 0) {
+      const Job J = jobs[g.job];
+      const int S = rec_stride(d);
+      for (int r = 0; r < kItems; ++r) {
+        uint32_t i = r * kPassThreads + threadIdx.x;
+        if (i >= tcnt) continue;
+        uint64_t p = tstart + i;
+        uint64_t slot = p - J.base;
+        float* rr = J.rec + slot * S;
+        for (int j = 0; j < d; ++j) rr[j] = src[(uint64_t)j * cap + p];
+        uint32_t id = sid[p];
+        rr[d] = __uint_as_float(id);
+        for (int j = d + 1; j < S; ++j) rr[j] = 0.0f;
+        if (J.write_map && id < idcap) map[id] = ((uint64_t)J.level << 32) | slot;
+      }
+      continue;
+    }
+    const float split = g.split;
+    const float* x = src + (uint64_t)dim * cap;
+    uint64_t m[kItems];
+    uint32_t fl = 0;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      uint32_t i = r * kPassThreads + threadIdx.x;
+      bool f = i < tcnt && x[tstart + i] < split;
+      fl |= (uint32_t)f << r;
+      m[r] = __ballot(f);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) lt[r][w] = (uint32_t)__popcll(m[r]);
+    }
+    __syncthreads();
+    const uint32_t tloff = tile_off[t] - tile_off[g.tile_begin];
+    const uint64_t lbase = gbegin + tloff;
+    const uint64_t rbase = gbegin + g.nleft + ((tstart - gbegin) - tloff);
+    uint32_t dpos[kItems];
+    uint32_t run = 0;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      uint32_t before = 0, row = 0;
+      for (int v = 0; v < 4; ++v) {
+        uint32_t xv = lt[r][v];
+        before += v < w ? xv : 0u;
+        row += xv;
+      }
+      uint32_t i = r * kPassThreads + threadIdx.x;
+      uint32_t lr = run + before + (uint32_t)__popcll(m[r] & ltm);
+      dpos[r] = ((fl >> r) & 1u) ? (uint32_t)(lbase + lr) : (uint32_t)(rbase + (i - lr));
+      run += row;
+    }
+    const uint32_t c0 = g.child[0], c1 = g.child[1];
+    for (int j = 0; j < d; ++j) {
+      const float* sj = src + (uint64_t)j * cap;
+      float* dj = dst + (uint64_t)j * cap;
+      uint32_t lmn = 0xFFFFFFFFu, lmx = 0u, rmn = 0xFFFFFFFFu, rmx = 0u;
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) {
+        uint32_t i = r * kPassThreads + threadIdx.x;
+        if (i < tcnt) {
+          float v = sj[tstart + i];
+          dj[dpos[r]] = v;
+          uint32_t o = f2o(v);
+          if ((fl >> r) & 1u) {
+            lmn = o < lmn ? o : lmn;
+            lmx = o > lmx ? o : lmx;
+          } else {
+            rmn = o < rmn ? o : rmn;
+            rmx = o > rmx ? o : rmx;
+          }
+        }
+      }
+      wave_minmax(lmn, lmx);
+      wave_minmax(rmn, rmx);
+      if (lane == 0) {
+        red[w][0] = lmn;
+        red[w][1] = lmx;
+        red[w][2] = rmn;
+        red[w][3] = rmx;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        for (int v = 1; v < 4; ++v) {
+          lmn = red[v][0] < lmn ? red[v][0] : lmn;
+          lmx = red[v][1] > lmx ? red[v][1] : lmx;
+          rmn = red[v][2] < rmn ? red[v][2] : rmn;
+          rmx = red[v][3] > rmx ? red[v][3] : rmx;
+        }
+        if (c0 != kNone && lmn <= lmx) {
+          atomicMin(&nxt[c0].box[j], lmn);
+          atomicMax(&nxt[c0].box[kMaxDim + j], lmx);
+        }
+        if (c1 != kNone && rmn <= rmx) {
+          atomicMin(&nxt[c1].box[j], rmn);
+          atomicMax(&nxt[c1].box[kMaxDim + j], rmx);
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      uint32_t i = r * kPassThreads + threadIdx.x;
+      if (i < tcnt) did[dpos[r]] = sid[tstart + i];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------
+// LDS finisher: one workgroup builds a whole subtree of at most TCAP points
+// ------------------------------------------------------------------------
+
+struct Act {
+  uint16_t begin, count, nleft;
+  int8_t dim;
+  uint8_t depth;
+  float split;
+  uint32_t emit;
+  uint64_t path;
+};
+
+template <int DMAX, int TCAP, int MAXACT>
+__global__ void __launch_bounds__(256)
+k_finish(const Fin* fin, uint32_t nfin, const float* soa0, const float* soa1, uint64_t cap,
+         int d, uint32_t leaf, const Job* jobs, uint32_t* emit, int es, BuildCounters* c,
+         uint64_t* map, uint32_t idcap, uint64_t max_emit) {
+  constexpr int PT = TCAP / 256;
+  constexpr int MAXCH = 2 * MAXACT;
+  static_assert(MAXCH <= 256, "one child per thread");
+  static_assert(TCAP % 256 == 0, "blocked scan");
+  __shared__ float xs[DMAX][TCAP];
+  __shared__ uint32_t ids[TCAP];
+  __shared__ uint16_t pos[2][TCAP];
+  __shared__ uint16_t sidv[2][TCAP];
+  __shared__ uint16_t L[TCAP + 2];
+  __shared__ Act act[2][MAXACT];
+  __shared__ uint32_t cbox[MAXCH][2 * DMAX];
+  __shared__ uint16_t remap[MAXCH];
+  __shared__ uint32_t wsum[17];
+  __shared__ uint32_t s_nact, s_nemit, s_base, s_maxdepth;
+
+  const int tid = threadIdx.x;
+  const int lane = __lane_id();
+  const int S = rec_stride(d);
+
+  for (uint32_t fi = blockIdx.x; fi < nfin; fi += gridDim.x) {
+    const Fin F = fin[fi];
+    const uint32_t n = F.count;
+    if (n > TCAP || n == 0) {
+      if (tid == 0) atomicOr(&c->err, 32u);
+      continue;
+    }
+    const float* src = F.bufsel ? soa1 : soa0;
+    const uint32_t* srcid = soa_ids(src, d, cap);
+    const Job J = jobs[F.job];
+    for (uint32_t i = tid; i < n; i += 256) {
+      for (int j = 0; j < d; ++j) xs[j][i] = src[(uint64_t)j * cap + F.begin + i];
+      ids[i] = srcid[F.begin + i];
+      pos[0][i] = (uint16_t)i;
+      sidv[0][i] = 0;
+    }
+    if (tid < 2 * DMAX) cbox[0][tid] = tid < DMAX ? 0xFFFFFFFFu : 0u;
+    if (tid == 0) s_maxdepth = 0;
+    int cur = 0;    // pos/sid buffer holding the current order
+    int ca = 0;     // act table of the current depth
+    uint32_t nch = 1;
+    bool root = true;
+    __syncthreads();
+
+    // child boxes by a segmented min/max over positions (children are
+    // contiguous runs of equal sid)
+    auto child_boxes = [&](int buf) {
+      for (uint32_t b0 = 0; b0 < n; b0 += 256) {
+        const uint32_t i = b0 + tid;
+        const bool valid = i < n;
+        const uint32_t key = valid ? (uint32_t)sidv[buf][i] : (uint32_t)kFrozen;
+        const uint32_t p = valid ? (uint32_t)pos[buf][i] : 0u;
+        bool same[6];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+          const int o = 1 << s;
+          uint32_t ko = (uint32_t)__shfl_up((int)key, o, 64);
+          same[s] = lane >= o && ko == key;
+        }
+        const uint32_t kn = (uint32_t)__shfl_down((int)key, 1, 64);
+        const bool last = key != kFrozen && (lane == 63 || kn != key);
+        for (int j = 0; j < d; ++j) {
+          uint32_t lo = valid ? f2o(xs[j][p]) : 0u;
+          uint32_t hi = lo;
+#pragma unroll
+          for (int s = 0; s < 6; ++s) {
+            const int o = 1 << s;
+            uint32_t olo = (uint32_t)__shfl_up((int)lo, o, 64);
+            uint32_t ohi = (uint32_t)__shfl_up((int)hi, o, 64);
+            if (same[s]) {
+              lo = olo < lo ? olo : lo;
+              hi = ohi > hi ? ohi : hi;
+            }
+          }
+          if (last) {
+            atomicMin(&cbox[key][j], lo);
+            atomicMax(&cbox[key][DMAX + j], hi);
+          }
+        }
+      }
+    };
+
+    child_boxes(cur);
+    __syncthreads();
+
+    while (true) {
+      // ---- classify the children of the previous depth (or the root) ----
+      if (tid == 0) {
+        s_nact = 0;
+        s_nemit = 0;
+      }
+      __syncthreads();
+      const int na = ca ^ 1;  // table that receives this depth's internal nodes
+      uint32_t cbegin = 0, ccount = 0, cdepth = 0, cparent = kNone, cside = 0, le = 0;
+      uint32_t ai = kNone;
+      uint64_t cpath = 0;
+      int cdim = -1;
+      float csplit = 0.0f;
+      const bool have = (uint32_t)tid < nch;
+      if (have) {
+        const uint32_t ch = (uint32_t)tid;
+        if (root) {
+          cbegin = 0;
+          ccount = n;
+          cdepth = F.depth;
+          cpath = F.path;
+          cparent = F.parent_emit;
+          cside = F.side;
+        } else {
+          const Act& A = act[ca][ch >> 1];
+          cside = ch & 1u;
+          cbegin = cside ? A.begin + A.nleft : A.begin;
+          ccount = cside ? A.count - A.nleft : A.nleft;
+          cdepth = A.depth + 1u;
+          cpath = (A.path << 1) | (uint64_t)cside;
+          cparent = A.emit;
+        }
+        const uint32_t* lo = cbox[ch];
+        const uint32_t* hi = cbox[ch] + DMAX;
+        bool degenerate = true;
+        for (int j = 0; j < d; ++j) degenerate = degenerate && lo[j] == hi[j];
+        const bool isleaf = ccount <= leaf || degenerate || cdepth >= (uint32_t)kMaxDepth;
+        if (!isleaf) choose_split(lo, hi, d, (int)cdepth, &cdim, &csplit);
+        le = atomicAdd(&s_nemit, 1u);
+        if (!isleaf) {
+          ai = atomicAdd(&s_nact, 1u);
+          if (ai >= (uint32_t)MAXACT) {
+            atomicOr(&c->err, 64u);
+            ai = kNone;
+          }
+        }
+        remap[ch] = ai == kNone ? kFrozen : (uint16_t)ai;
+        atomicMax(&s_maxdepth, cdepth);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t base = atomicAdd(&c->nemit, s_nemit);
+        if ((uint64_t)base + s_nemit > max_emit) {
+          atomicOr(&c->err, 128u);
+          base = 0xFFFFFFFFu;
+        } else {
+          atomicAdd(&c->job_nodes[F.job], s_nemit);
+        }
+        s_base = base;
+      }
+      __syncthreads();
+      if (have && s_base != 0xFFFFFFFFu) {
+        const uint32_t eidx = s_base + le;
+        write_emit(emit, es, eidx, cpath, cdepth, F.job, cparent, cside,
+                   F.begin + cbegin - J.base, ccount, csplit, cdim, cbox[tid], cbox[tid] + DMAX, d);
+        if (ai != kNone) {
+          Act& A = act[na][ai];
+          A.begin = (uint16_t)cbegin;
+          A.count = (uint16_t)ccount;
+          A.nleft = 0;
+          A.dim = (int8_t)cdim;
+          A.depth = (uint8_t)cdepth;
+          A.split = csplit;
+          A.emit = eidx;
+          A.path = cpath;
+        }
+      }
+      root = false;
+      __syncthreads();
+      const uint32_t nact =
+          (s_base == 0xFFFFFFFFu || s_nact > (uint32_t)MAXACT) ? 0u : s_nact;
+      if (nact == 0) break;
+      // ---- point each position at its node in the new table ----
+      for (uint32_t i = tid; i < n; i += 256) {
+        uint16_t s = sidv[cur][i];
+        if (s != kFrozen) sidv[cur][i] = remap[s];
+      }
+      ca = na;
+      __syncthreads();
+      // ---- flags and block-wide exclusive scan (blocked positions) ----
+      uint32_t fl = 0, cnt = 0;
+#pragma unroll
+      for (int q = 0; q < PT; ++q) {
+        const uint32_t i = (uint32_t)tid * PT + q;
+        if (i < n) {
+          const uint16_t s = sidv[cur][i];
+          if (s != kFrozen) {
+            const Act& A = act[ca][s];
+            const bool f = xs[A.dim][pos[cur][i]] < A.split;
+            fl |= (uint32_t)f << q;
+            cnt += f;
+          }
+        }
+      }
+      uint32_t tot;
+      uint32_t run = block_excl_scan(cnt, wsum, &tot);
+#pragma unroll
+      for (int q = 0; q < PT; ++q) {
+        const uint32_t i = (uint32_t)tid * PT + q;
+        if (i < n) L[i] = (uint16_t)run;
+        run += (fl >> q) & 1u;
+      }
+      if (tid == 0) L[n] = (uint16_t)tot;
+      __syncthreads();
+      for (uint32_t a = tid; a < nact; a += 256) {
+        Act& A = act[ca][a];
+        A.nleft = (uint16_t)(L[A.begin + A.count] - L[A.begin]);
+      }
+      __syncthreads();
+      // ---- stable scatter into the other position buffer ----
+      for (uint32_t i = tid; i < n; i += 256) {
+        const uint16_t s = sidv[cur][i];
+        const uint16_t p = pos[cur][i];
+        if (s == kFrozen) {
+          pos[cur ^ 1][i] = p;
+          sidv[cur ^ 1][i] = kFrozen;
+        } else {
+          const Act& A = act[ca][s];
+          const uint32_t lr = (uint32_t)L[i] - (uint32_t)L[A.begin];
+          const bool f = L[i + 1] != L[i];
+          const uint32_t np =
+              f ? A.begin + lr : A.begin + A.nleft + (i - A.begin - lr);
+          pos[cur ^ 1][np] = p;
+          sidv[cur ^ 1][np] = (uint16_t)(2u * s + (f ? 0u : 1u));
+        }
+      }
+      nch = 2 * nact;
+      for (uint32_t e = tid; e < nch * 2 * DMAX; e += 256) {
+        const uint32_t j = e % (2 * DMAX);
+        cbox[e / (2 * DMAX)][j] = j < (uint32_t)DMAX ? 0xFFFFFFFFu : 0u;
+      }
+      cur ^= 1;
+      __syncthreads();
+      child_boxes(cur);
+      __syncthreads();
+    }
+    // ---- write the subtree's points in final slot order ----
+    for (uint32_t i = tid; i < n; i += 256) {
+      const uint16_t p = pos[cur][i];
+      const uint64_t slot = (uint64_t)F.begin + i - J.base;
+      float* rr = J.rec + slot * S;
+      for (int j = 0; j < d; ++j) rr[j] = xs[j][p];
+      const uint32_t id = ids[p];
+      rr[d] = __uint_as_float(id);
+      for (int j = d + 1; j < S; ++j) rr[j] = 0.0f;
+      if (J.write_map && id < idcap) map[id] = ((uint64_t)J.level << 32) | slot;
+    }
+    if (tid == 0) atomicMax(&c->job_height[F.job], s_maxdepth + 1u);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------
+// layout
+// ------------------------------------------------------------------------
+
+__global__ void k_job_offsets(BuildCounters* c, int njobs) {
+  if (threadIdx.x != 0) return;
+  uint32_t run = 0;
+  for (int j = 0; j < njobs; ++j) {
+    c->job_node_off[j] = run;
+    run += c->job_nodes[j];
+  }
+}
+
+__global__ void k_layout_keys(const uint32_t* emit, int es, uint32_t n, const BuildCounters* c,
+                              int job_shift, uint64_t* keys, uint32_t* vals) {
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const uint32_t* r = emit + (uint64_t)e * es;
+    const uint64_t path = (uint64_t)r[EF_PATH_LO] | ((uint64_t)r[EF_PATH_HI] << 32);
+    const uint32_t job = r[EF_JOB];
+    uint64_t key = veb_key((int)c->job_height[job], (int)r[EF_DEPTH], path);
+    if (job_shift >= 0) key |= (uint64_t)job << job_shift;
+    keys[e] = key;
+    vals[e] = e;
+  }
+}
+
+__global__ void k_layout_jobkeys(const uint32_t* emit, int es, uint32_t n, const uint32_t* vals,
+                                 uint64_t* keys) {
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+    keys[r] = emit[(uint64_t)vals[r] * es + EF_JOB];
+}
+
+__global__ void k_layout_rank(const uint32_t* vals, uint32_t n, const uint32_t* emit, int es,
+                              const BuildCounters* c, uint32_t* final_of) {
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const uint32_t e = vals[r];
+    const uint32_t job = emit[(uint64_t)e * es + EF_JOB];
+    final_of[e] = r - c->job_node_off[job];
+  }
+}
+
+__global__ void k_layout_write(const uint32_t* emit, int es, uint32_t n, const uint32_t* final_of,
+                               const Job* jobs, int d, uint32_t* err) {
+  const int NS = node_stride(d);
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const uint32_t* r = emit + (uint64_t)e * es;
+    const Job& J = jobs[r[EF_JOB]];
+    const uint32_t f = final_of[e];
+    const uint32_t parent = r[EF_PARENT];
+    if (f >= J.node_cap || (parent != kNone && final_of[parent] >= J.node_cap)) {
+      atomicOr(err, 512u);
+      continue;
+    }
+    float* nd = J.nodes + (uint64_t)f * NS;
+    const int dim = (int)r[EF_DIM];
+    nd[NF_SPLIT] = __uint_as_float(r[EF_SPLIT]);
+    nd[NF_DIM] = __int_as_float(dim);
+    if (dim < 0) {
+      nd[NF_A] = __uint_as_float(r[EF_BEGIN]);
+      nd[NF_B] = __uint_as_float(r[EF_COUNT]);
+    }
+    nd[NF_PARENT] = __int_as_float(parent == kNone ? -1 : (int)final_of[parent]);
+    for (int j = 0; j < 2 * d; ++j) nd[NF_BOX + j] = __uint_as_float(r[EF_BOX + j]);
+    for (int j = NF_BOX + 2 * d; j < NS; ++j) nd[j] = 0.0f;
+    if (parent != kNone) {
+      float* pn = J.nodes + (uint64_t)final_of[parent] * NS;
+      pn[r[EF_SIDE] ? NF_B : NF_A] = __uint_as_float(f);
+    }
+  }
+}
+
+struct U32x64 {
+  uint32_t v[64];
+};
+
+__global__ void k_store_vals(uint32_t* dst, U32x64 vals, int n) {
+  if ((int)threadIdx.x < n) dst[threadIdx.x] = vals.v[threadIdx.x];
+}
+
+__global__ void k_fill(uint32_t* dst, uint32_t v, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = v;
+}
+
+inline unsigned grid_for(uint64_t n, unsigned threads, unsigned cap = 4096) {
+  uint64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+template <int DMAX, int TCAP, int MAXACT>
+void launch_finish(uint32_t nfin, const BuildScratch& sc, int d, uint32_t leaf, uint64_t* map,
+                   uint32_t idcap, hipStream_t s) {
+  unsigned g = nfin < 65535u ? nfin : 65535u;
+  hipLaunchKernelGGL((k_finish<DMAX, TCAP, MAXACT>), dim3(g), dim3(256), 0, s, sc.fin, nfin,
+                     sc.soa[0], sc.soa[1], sc.cap, d, leaf, sc.jobs, sc.emit, emit_stride(d),
+                     sc.ctr, map, idcap, sc.max_emit);
+}
+
+}  // namespace
+
+// Finisher configurations: (max dim, LDS point capacity, max internal nodes
+// per depth).  The threshold also guarantees that one depth of a finisher
+// subtree has at most MAXACT internal nodes (each holds > leaf points).
+uint32_t finisher_threshold(int d, int leaf_size) {
+  uint32_t tcap, maxact;
+  if (d <= 3) { tcap = 1792; maxact = 128; }
+  else if (d <= 8) { tcap = 1024; maxact = 64; }
+  else { tcap = 512; maxact = 32; }
+  uint64_t t = (uint64_t)maxact * (uint64_t)(leaf_size + 1);
+  return (uint32_t)(t < tcap ? t : tcap);
+}
+
+size_t build_scratch_bytes(uint64_t cap, int d, uint32_t T) {
+  uint64_t max_seg = cap / T + kMaxJobs + 8;
+  uint64_t max_tiles = cap / kTile + max_seg + 8;
+  uint64_t max_fin = 2 * (uint64_t)(kMaxDepth + 1) * (cap / T + 1) + 2 * kMaxJobs;
+  uint64_t max_emit = 2 * cap + kMaxJobs;
+  size_t b = 0;
+  b += 2 * (size_t)(d + 1) * cap * 4;
+  b += 2 * max_seg * (sizeof(Seg) + 4);
+  b += 2 * max_tiles * 4;
+  b += max_fin * sizeof(Fin);
+  b += max_emit * (size_t)emit_stride(d) * 4;
+  b += 2 * max_emit * 12 + max_emit * 4;
+  b += (radix_tmp_words(max_emit) + scan_tmp_words(cap) + 16) * 4;
+  b += (cap / kTile + 2) * 4;
+  return b;
+}
+
+void launch_pool_to_soa(const PoolSrc& src, int d, uint64_t p0, uint64_t cnt, float* soa,
+                        uint64_t cap, uint64_t dst, hipStream_t s) {
+  if (!cnt) return;
+  hipLaunchKernelGGL(k_pool_to_soa, dim3(grid_for(cnt, 256)), dim3(256), 0, s, src, d, p0, cnt,
+                     soa, cap, dst);
+}
+
+void launch_pool_to_records(const PoolSrc& src, int d, uint64_t p0, uint64_t cnt, float* rec,
+                            uint64_t* map, uint32_t idcap, hipStream_t s) {
+  if (!cnt) return;
+  hipLaunchKernelGGL(k_pool_to_records, dim3(grid_for(cnt, 256)), dim3(256), 0, s, src, d, p0,
+                     cnt, rec, map, idcap);
+}
+
+void launch_records_to_soa(const float* rec, int d, uint64_t n, float* soa, uint64_t cap,
+                           uint64_t dst, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_records_to_soa, dim3(grid_for(n, 256)), dim3(256), 0, s, rec, d, n, soa,
+                     cap, dst);
+}
+
+void launch_compact_live(const float* rec, int d, uint64_t n, float* soa, uint64_t cap,
+                         uint64_t dst, float* out_rec, uint32_t* tile_cnt, uint32_t* tmp,
+                         hipStream_t s) {
+  if (!n) return;
+  const uint32_t nt = (uint32_t)((n + kTile - 1) / kTile);
+  hipLaunchKernelGGL(k_count_live, dim3(nt), dim3(kPassThreads), 0, s, rec, d, n, tile_cnt);
+  scan_exclusive_u32(tile_cnt, tile_cnt, nt, nullptr, tmp, s);
+  hipLaunchKernelGGL(k_compact_live, dim3(nt), dim3(kPassThreads), 0, s, rec, d, n, tile_cnt,
+                     soa, cap, dst, out_rec);
+}
+
+void launch_store_u32(uint32_t* dst, const uint32_t* vals, int n, hipStream_t s) {
+  U32x64 v;
+  for (int i = 0; i < 64; ++i) v.v[i] = i < n ? vals[i] : 0u;
+  hipLaunchKernelGGL(k_store_vals, dim3(1), dim3(64), 0, s, dst, v, n);
+}
+
+void launch_fill_u32(uint32_t* dst, uint32_t v, uint64_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, v, n);
+}
+
+static int hip_fail(const char** err, const char* what) {
+  *err = what;
+  return BDL_EHIP;
+}
+
+int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32_t T,
+              uint64_t* map, uint32_t idcap, hipStream_t s, uint32_t* job_nodes,
+              const char** err, const PhaseTimer& pt) {
+  const int njobs = jt.n;
+  uint64_t R = 0, maxcount = 0;
+  for (int j = 0; j < njobs; ++j) {
+    R += jt.jobs[j].count;
+    if (jt.jobs[j].count > maxcount) maxcount = jt.jobs[j].count;
+  }
+  if (R == 0) {
+    for (int j = 0; j < njobs; ++j) job_nodes[j] = 0;
+    return 0;
+  }
+  const int es = emit_stride(d);
+  pt.begin(BDL_PH_PASSES);
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(kMaxJobs), 0, s, sc.ctr, jt, sc.jobs);
+  {
+    dim3 g((unsigned)((maxcount + kTile - 1) / kTile), (unsigned)njobs);
+    hipLaunchKernelGGL(k_root_box, g, dim3(kPassThreads), 0, s, sc.soa[0], sc.cap, d, sc.jobs,
+                       sc.ctr);
+  }
+  hipLaunchKernelGGL(k_init_lists, dim3(1), dim3(64), 0, s, sc.jobs, njobs, sc.ctr, sc.seg[0],
+                     sc.fin, T, sc.max_seg, sc.max_fin);
+  // global passes: a budget of depths, then one readback to see whether any
+  // segment still exceeds the finisher threshold
+  int depth = 0;
+  int budget = 1;
+  while (((uint64_t)T << budget) < maxcount && budget < 40) ++budget;
+  budget += 3;
+  const unsigned pass_grid = grid_for(R, kTile, 2048);
+  while (true) {
+    for (int b = 0; b < budget; ++b, ++depth) {
+      const int par = depth & 1;
+      hipLaunchKernelGGL(k_setup, dim3(1), dim3(1024), 0, s, sc.seg[par], sc.segtb[par], sc.ctr,
+                         par, sc.jobs, sc.emit, es, d, leaf, sc.max_emit, sc.max_seg,
+                         sc.max_tiles);
+      hipLaunchKernelGGL(k_count, dim3(pass_grid), dim3(kPassThreads), 0, s, sc.seg[par],
+                         sc.segtb[par], sc.ctr, par, sc.soa[par], sc.cap, sc.tile_left);
+      hipLaunchKernelGGL(k_tilescan, dim3(1), dim3(1024), 0, s, sc.seg[par], sc.seg[par ^ 1],
+                         sc.ctr, par, sc.tile_left, sc.tile_off, sc.fin, T, sc.max_seg,
+                         sc.max_fin);
+      hipLaunchKernelGGL(k_scatter, dim3(pass_grid), dim3(kPassThreads), 0, s, sc.seg[par],
+                         sc.segtb[par], sc.seg[par ^ 1], sc.ctr, par, sc.soa[par],
+                         sc.soa[par ^ 1], sc.cap, d, sc.tile_off, sc.jobs, map, idcap);
+    }
+    pt.end(BDL_PH_PASSES);
+    if (hipMemcpyAsync(sc.host_ctr, sc.ctr, sizeof(BuildCounters), hipMemcpyDeviceToHost, s) !=
+        hipSuccess)
+      return hip_fail(err, "counter readback failed");
+    if (hipStreamSynchronize(s) != hipSuccess) return hip_fail(err, "build passes failed");
+    if (sc.host_ctr->err) {
+      *err = "build scratch overflow in the global passes";
+      return BDL_EHIP;
+    }
+    if (sc.host_ctr->nseg[depth & 1] == 0) break;
+    if (depth > kMaxDepth + 2) {
+      *err = "build did not terminate";
+      return BDL_EHIP;
+    }
+    budget = 8;
+    pt.begin(BDL_PH_PASSES);
+  }
+  const uint32_t nfin = sc.host_ctr->nfin;
+  pt.begin(BDL_PH_FINISH);
+  if (nfin) {
+    if (d <= 3) launch_finish<3, 1792, 128>(nfin, sc, d, leaf, map, idcap, s);
+    else if (d <= 8) launch_finish<8, 1024, 64>(nfin, sc, d, leaf, map, idcap, s);
+    else launch_finish<16, 512, 32>(nfin, sc, d, leaf, map, idcap, s);
+  }
+  pt.end(BDL_PH_FINISH);
+  if (hipMemcpyAsync(sc.host_ctr, sc.ctr, sizeof(BuildCounters), hipMemcpyDeviceToHost, s) !=
+      hipSuccess)
+    return hip_fail(err, "counter readback failed");
+  if (hipStreamSynchronize(s) != hipSuccess) return hip_fail(err, "finisher failed");
+  const BuildCounters& hc = *sc.host_ctr;
+  if (hc.err) {
+    *err = "build scratch overflow in the finisher";
+    return BDL_EHIP;
+  }
+  const uint32_t nemit = hc.nemit;
+  int maxH = 0;
+  for (int j = 0; j < njobs; ++j) {
+    job_nodes[j] = hc.job_nodes[j];
+    if ((int)hc.job_height[j] > maxH) maxH = (int)hc.job_height[j];
+  }
+  int jobbits = 0;
+  while ((1 << jobbits) < njobs) ++jobbits;
+  pt.begin(BDL_PH_LAYOUT);
+  hipLaunchKernelGGL(k_job_offsets, dim3(1), dim3(64), 0, s, sc.ctr, njobs);
+  const bool composite = maxH + jobbits <= 64;
+  const unsigned g = grid_for(nemit, 256);
+  hipLaunchKernelGGL(k_layout_keys, dim3(g), dim3(256), 0, s, sc.emit, es, nemit, sc.ctr,
+                     composite && jobbits > 0 ? maxH : -1, sc.keys[0], sc.vals[0]);
+  int which = radix_sort_pairs_u64(sc.keys[0], sc.vals[0], sc.keys[1], sc.vals[1], nemit, 0,
+                                   composite ? maxH + jobbits : maxH, sc.tmp, s);
+  if (!composite && jobbits > 0) {
+    hipLaunchKernelGGL(k_layout_jobkeys, dim3(g), dim3(256), 0, s, sc.emit, es, nemit,
+                       sc.vals[which], sc.keys[which]);
+    which ^= radix_sort_pairs_u64(sc.keys[which], sc.vals[which], sc.keys[which ^ 1],
+                                  sc.vals[which ^ 1], nemit, 0, jobbits, sc.tmp, s);
+  }
+  hipLaunchKernelGGL(k_layout_rank, dim3(g), dim3(256), 0, s, sc.vals[which], nemit, sc.emit, es,
+                     sc.ctr, sc.final_of);
+  hipLaunchKernelGGL(k_layout_write, dim3(g), dim3(256), 0, s, sc.emit, es, nemit, sc.final_of,
+                     sc.jobs, d, &sc.ctr->err);
+  pt.end(BDL_PH_LAYOUT);
+  if (hipGetLastError() != hipSuccess) return hip_fail(err, "build kernel launch failed");
+  if (hipMemcpyAsync(sc.host_ctr, sc.ctr, sizeof(BuildCounters), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return hip_fail(err, "layout failed");
+  if (sc.host_ctr->err) {
+    *err = "node layout out of range";
+    return BDL_EHIP;
+  }
+  return 0;
+}
+
+}  // namespace bdl

@@ -1,0 +1,67 @@
+// Host launchers of the static-tree build (BuildvEB with the spatial median)
+// and of the gather steps of Insert_L.
+#pragma once
+
+#include "bdl_common.hpp"
+
+namespace bdl {
+
+// Device scratch of one Insert_L build, sized for up to `cap` points.
+struct BuildScratch {
+  uint64_t cap = 0;        // points
+  uint64_t max_seg = 0;    // per depth list capacity
+  uint64_t max_fin = 0;
+  uint64_t max_emit = 0;
+  float* soa[2] = {nullptr, nullptr};  // ping-pong build buffers, (d+1) * cap
+  Seg* seg[2] = {nullptr, nullptr};
+  uint32_t* segtb[2] = {nullptr, nullptr};
+  uint32_t* tile_left = nullptr;
+  uint32_t* tile_off = nullptr;
+  uint64_t max_tiles = 0;
+  Fin* fin = nullptr;
+  uint32_t* emit = nullptr;      // max_emit * emit_stride(d) words
+  uint64_t* keys[2] = {nullptr, nullptr};
+  uint32_t* vals[2] = {nullptr, nullptr};
+  uint32_t* final_of = nullptr;
+  uint32_t* tmp = nullptr;       // scan / sort scratch
+  uint64_t tmp_words = 0;
+  uint32_t* tile_cnt = nullptr;  // compaction per-tile counts (tiles of kTile)
+  BuildCounters* ctr = nullptr;
+  BuildCounters* host_ctr = nullptr;  // pinned mirror
+  Job* jobs = nullptr;           // device copy of the job table
+};
+
+// Sizes (bytes) of the scratch needed for `cap` points of dimension d.
+size_t build_scratch_bytes(uint64_t cap, int d, uint32_t T);
+
+// Finisher threshold: subtrees of at most this many points are built in LDS.
+uint32_t finisher_threshold(int d, int leaf_size);
+
+// --- gather kernels ---
+// pool elements [p0, p0 + cnt) -> build buffer positions [dst, dst + cnt)
+void launch_pool_to_soa(const PoolSrc& src, int d, uint64_t p0, uint64_t cnt, float* soa,
+                        uint64_t cap, uint64_t dst, hipStream_t s);
+// pool elements [p0, p0 + cnt) -> records (the new buffer pool), map entries
+void launch_pool_to_records(const PoolSrc& src, int d, uint64_t p0, uint64_t cnt, float* rec,
+                            uint64_t* map, uint32_t idcap, hipStream_t s);
+// records [0, n) all live -> build buffer positions [dst, dst + n)
+void launch_records_to_soa(const float* rec, int d, uint64_t n, float* soa, uint64_t cap,
+                           uint64_t dst, hipStream_t s);
+// stable compaction of live records [0, n) (id != tomb) into build buffer
+// positions starting at dst (to_soa) or into records out (!to_soa).
+void launch_compact_live(const float* rec, int d, uint64_t n, float* soa, uint64_t cap,
+                         uint64_t dst, float* out_rec, uint32_t* tile_cnt, uint32_t* tmp,
+                         hipStream_t s);
+
+// Build every job of the table from build buffer 0.  Writes records (slot
+// order), nodes (vEB order) and, where requested, the id map.  Fills
+// job_nodes[i] with the node count of job i.  Returns 0 or a BDL_E* code.
+int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32_t T,
+              uint64_t* map, uint32_t idcap, hipStream_t s, uint32_t* job_nodes,
+              const char** err, const PhaseTimer& pt);
+
+// small utilities
+void launch_store_u32(uint32_t* dst, const uint32_t* vals, int n, hipStream_t s);
+void launch_fill_u32(uint32_t* dst, uint32_t v, uint64_t n, hipStream_t s);
+
+}  // namespace bdl

@@ -1,0 +1,305 @@
+// Batched k-NN over the log structure (kNN_L, Alg. 5) on gfx950.
+//
+// One lane per query.  Every lane keeps its k best (squared distance, id)
+// keys in registers and visits the trees one after another, largest first
+// (Section V-B), then the buffer's tree.  Inside a tree it follows kNN_S
+// (Section IV-A.3): descend towards the leaf that holds the query, then
+// unwind through parent links; on the way up the sibling subtree is entered
+// unless its tight box lies strictly farther than the current k-th distance.
+// Parent links make the traversal stackless.  Which order subtrees are
+// visited in does not change the result: it is the exact k nearest by
+// (squared distance, id), because the box distance is a float32 lower bound
+// of every point distance inside the box and pruning is strict.
+#include "bdl.h"
+#include "knn.hpp"
+#include "primitives.hpp"
+
+namespace bdl {
+
+namespace {
+
+constexpr uint64_t kPadKey = (0x7F800000ull << 32) | 0xFFFFFFFFull;
+
+template <int D>
+__device__ inline float select_dim(const float (&qq)[D], int dim) {
+  float v = qq[0];
+#pragma unroll
+  for (int j = 1; j < D; ++j) v = dim == j ? qq[j] : v;
+  return v;
+}
+
+// mindist^2 from the query to a box lo[0..D), hi[0..D): per dimension the
+// gap max(lo - q, 0, q - hi), accumulated like a point distance.
+template <int D>
+__device__ inline float box_dist2(const float (&qq)[D], const float* box) {
+  float acc = 0.0f;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    float a = box[j] - qq[j];
+    float b = qq[j] - box[D + j];
+    float t = a > 0.0f ? a : (b > 0.0f ? b : 0.0f);
+    acc = __builtin_fmaf(t, t, acc);
+  }
+  return acc;
+}
+
+// Insert c into the ascending array a (c < a[KMAX-1]); the largest key
+// falls off the end.  New a[j] = max(a[j-1], min(a[j], c)), a[0] = min(a[0], c).
+template <int KMAX>
+__device__ inline void topk_insert(uint64_t (&a)[KMAX], uint64_t c) {
+#pragma unroll
+  for (int j = KMAX - 1; j > 0; --j) {
+    uint64_t lo = a[j] < c ? a[j] : c;
+    a[j] = a[j - 1] > lo ? a[j - 1] : lo;
+  }
+  a[0] = a[0] < c ? a[0] : c;
+}
+
+template <int D, int KMAX>
+__global__ void __launch_bounds__(256)
+k_knn(const float* __restrict__ q, uint64_t nq, int k, const uint32_t* __restrict__ order,
+      LevelViews views, uint32_t* __restrict__ out_ids, float* __restrict__ out_d2,
+      uint32_t* __restrict__ err) {
+  constexpr int S = (D + 1 + 3) & ~3;
+  constexpr int NS = (5 + 2 * D + 3) & ~3;
+  constexpr int SV = S / 4;
+  constexpr int NV = NS / 4;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nq) return;
+  const uint64_t qi = order ? (uint64_t)order[t] : t;
+  float qq[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) qq[j] = q[qi * D + j];
+  const int skip = KMAX - k;
+  uint64_t key[KMAX];
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) key[j] = j < skip ? 0ull : kPadKey;
+
+  for (int v = 0; v < views.n; ++v) {
+    const float4* __restrict__ nodes = reinterpret_cast<const float4*>(views.v[v].nodes);
+    const float4* __restrict__ rec = reinterpret_cast<const float4*>(views.v[v].rec);
+    const uint32_t nn = views.v[v].n_nodes;
+    const uint32_t ns = views.v[v].n_slots;
+    int n = 0;
+    bool up = false;
+    // every node is entered once and left once; a longer walk means corrupt
+    // parent links, so stop instead of looping
+    uint64_t steps_left = 4ull * nn + 16;
+    while (true) {
+      if (--steps_left == 0) {
+        atomicOr(err, 8u);
+        break;
+      }
+      if (!up) {
+        if ((uint32_t)n >= nn) {
+          atomicOr(err, 1u);
+          break;
+        }
+        float f[NS];
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+          float4 x = nodes[(uint64_t)n * NV + u];
+          f[4 * u + 0] = x.x;
+          f[4 * u + 1] = x.y;
+          f[4 * u + 2] = x.z;
+          f[4 * u + 3] = x.w;
+        }
+        const float worst = __uint_as_float((uint32_t)(key[KMAX - 1] >> 32));
+        if (box_dist2<D>(qq, f + NF_BOX) > worst) {
+          up = true;
+          continue;
+        }
+        const int dim = __float_as_int(f[NF_DIM]);
+        const int a = __float_as_int(f[NF_A]);
+        const int b = __float_as_int(f[NF_B]);
+        if (dim < 0) {
+          if ((uint32_t)a > ns || (uint32_t)b > ns - (uint32_t)a) {
+            atomicOr(err, 2u);
+            break;
+          }
+          for (int sl = a; sl < a + b; ++sl) {
+            float r[S];
+#pragma unroll
+            for (int u = 0; u < SV; ++u) {
+              float4 x = rec[(uint64_t)sl * SV + u];
+              r[4 * u + 0] = x.x;
+              r[4 * u + 1] = x.y;
+              r[4 * u + 2] = x.z;
+              r[4 * u + 3] = x.w;
+            }
+            const uint32_t id = __float_as_uint(r[D]);
+            if (id == kTomb) continue;
+            float acc = 0.0f;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+              float tt = qq[j] - r[j];
+              acc = __builtin_fmaf(tt, tt, acc);
+            }
+            const uint64_t ck = ((uint64_t)__float_as_uint(acc) << 32) | id;
+            if (ck < key[KMAX - 1]) topk_insert<KMAX>(key, ck);
+          }
+          up = true;
+          continue;
+        }
+        n = select_dim<D>(qq, dim) < f[NF_SPLIT] ? a : b;
+      } else {
+        if (n == 0) break;
+        const int p = __float_as_int(nodes[(uint64_t)n * NV + 1].x);
+        if ((uint32_t)p >= nn) {
+          atomicOr(err, 4u);
+          break;
+        }
+        const float4 h = nodes[(uint64_t)p * NV];
+        const int dim = __float_as_int(h.y);
+        const int a = __float_as_int(h.z);
+        const int b = __float_as_int(h.w);
+        const int nearc = select_dim<D>(qq, dim) < h.x ? a : b;
+        if (n == nearc) {
+          n = nearc == a ? b : a;
+          up = false;
+        } else {
+          n = p;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) {
+    if (j >= skip) {
+      const uint64_t o = qi * (uint64_t)k + (uint64_t)(j - skip);
+      out_ids[o] = (uint32_t)key[j];
+      out_d2[o] = __uint_as_float((uint32_t)(key[j] >> 32));
+    }
+  }
+}
+
+__global__ void k_query_box_init(uint32_t* box) {
+  const int t = threadIdx.x;
+  if (t < kMaxDim) {
+    box[t] = 0xFFFFFFFFu;
+    box[kMaxDim + t] = 0u;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_query_box(const float* q, uint64_t nq, int d, uint32_t* box) {
+  __shared__ uint32_t red[8];
+  const int lane = __lane_id();
+  const int w = threadIdx.x >> 6;
+  for (int j = 0; j < d; ++j) {
+    uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+      uint32_t o = f2o(q[i * d + j]);
+      mn = o < mn ? o : mn;
+      mx = o > mx ? o : mx;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      uint32_t a = __shfl_xor(mn, o, 64);
+      uint32_t b = __shfl_xor(mx, o, 64);
+      mn = a < mn ? a : mn;
+      mx = b > mx ? b : mx;
+    }
+    if (lane == 0) {
+      red[w] = mn;
+      red[4 + w] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int v = 1; v < 4; ++v) {
+        mn = red[v] < mn ? red[v] : mn;
+        mx = red[4 + v] > mx ? red[4 + v] : mx;
+      }
+      atomicMin(&box[j], mn);
+      atomicMax(&box[kMaxDim + j], mx);
+    }
+    __syncthreads();
+  }
+}
+
+// Morton key with bits = floor(30 / d) bits per dimension.
+__global__ void k_morton(const float* q, uint64_t nq, int d, const uint32_t* box, uint32_t* keys,
+                         uint32_t* vals) {
+  const int bits = 30 / d > 0 ? 30 / d : 1;
+  const float cells = (float)(1u << bits);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t cell[kMaxDim];
+    for (int j = 0; j < d; ++j) {
+      float lo = o2f(box[j]), hi = o2f(box[kMaxDim + j]);
+      float ext = hi - lo;
+      float u = ext > 0.0f ? (q[i * d + j] - lo) / ext : 0.0f;
+      int c = (int)(u * cells);
+      c = c < 0 ? 0 : (c >= (int)(1u << bits) ? (int)(1u << bits) - 1 : c);
+      cell[j] = (uint32_t)c;
+    }
+    uint32_t key = 0;
+    for (int b = bits - 1; b >= 0; --b)
+      for (int j = 0; j < d; ++j) key = (key << 1) | ((cell[j] >> b) & 1u);
+    keys[i] = key;
+    vals[i] = (uint32_t)i;
+  }
+}
+
+template <int D, int KMAX>
+void launch_one(int k, const float* q, uint64_t nq, const LevelViews& views,
+                const uint32_t* order, uint32_t* out_ids, float* out_d2, uint32_t* err,
+                hipStream_t s) {
+  const unsigned g = (unsigned)((nq + 255) / 256);
+  hipLaunchKernelGGL((k_knn<D, KMAX>), dim3(g), dim3(256), 0, s, q, nq, k, order, views,
+                     out_ids, out_d2, err);
+}
+
+template <int D>
+void launch_d(int k, const float* q, uint64_t nq, const LevelViews& views, const uint32_t* order,
+              uint32_t* out_ids, float* out_d2, uint32_t* err, hipStream_t s) {
+  if (k <= 4) launch_one<D, 4>(k, q, nq, views, order, out_ids, out_d2, err, s);
+  else if (k <= 8) launch_one<D, 8>(k, q, nq, views, order, out_ids, out_d2, err, s);
+  else if (k <= 16) launch_one<D, 16>(k, q, nq, views, order, out_ids, out_d2, err, s);
+  else if (k <= 32) launch_one<D, 32>(k, q, nq, views, order, out_ids, out_d2, err, s);
+  else launch_one<D, 64>(k, q, nq, views, order, out_ids, out_d2, err, s);
+}
+
+}  // namespace
+
+size_t query_scratch_bytes(uint64_t cap) {
+  return 4 * (size_t)cap * 4 + radix_tmp_words(cap) * 4 + 2 * kMaxDim * 4;
+}
+
+const uint32_t* morton_order(int d, const float* q, uint64_t nq, QueryScratch& qs,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_query_box_init, dim3(1), dim3(64), 0, s, qs.box);
+  unsigned g = (unsigned)((nq + 255) / 256);
+  if (g > 1024) g = 1024;
+  hipLaunchKernelGGL(k_query_box, dim3(g), dim3(256), 0, s, q, nq, d, qs.box);
+  unsigned g2 = (unsigned)((nq + 255) / 256);
+  if (g2 > 4096) g2 = 4096;
+  hipLaunchKernelGGL(k_morton, dim3(g2), dim3(256), 0, s, q, nq, d, qs.box, qs.keys[0],
+                     qs.vals[0]);
+  const int bits = (30 / d > 0 ? 30 / d : 1) * d;
+  int which = radix_sort_pairs_u32(qs.keys[0], qs.vals[0], qs.keys[1], qs.vals[1], nq, 0, bits,
+                                   qs.tmp, s);
+  return qs.vals[which];
+}
+
+int launch_knn(int d, int k, const float* q, uint64_t nq, const LevelViews& views,
+               const uint32_t* order, uint32_t* out_ids, float* out_d2, uint32_t* err,
+               hipStream_t s) {
+  switch (d) {
+#define BDL_KNN_CASE(DD) \
+  case DD:               \
+    launch_d<DD>(k, q, nq, views, order, out_ids, out_d2, err, s); \
+    break;
+    BDL_KNN_CASE(1) BDL_KNN_CASE(2) BDL_KNN_CASE(3) BDL_KNN_CASE(4)
+    BDL_KNN_CASE(5) BDL_KNN_CASE(6) BDL_KNN_CASE(7) BDL_KNN_CASE(8)
+    BDL_KNN_CASE(9) BDL_KNN_CASE(10) BDL_KNN_CASE(11) BDL_KNN_CASE(12)
+    BDL_KNN_CASE(13) BDL_KNN_CASE(14) BDL_KNN_CASE(15) BDL_KNN_CASE(16)
+#undef BDL_KNN_CASE
+    default:
+      return BDL_EINVAL;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : BDL_EHIP;
+}
+
+}  // namespace bdl

@@ -1,0 +1,210 @@
+// Device-wide exclusive scan and stable LSD radix sort for gfx950.
+#include "primitives.hpp"
+
+namespace bdl {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+constexpr int kRadixThreads = 256;
+constexpr int kRadixItems = 8;
+constexpr int kRadixTile = kRadixThreads * kRadixItems;
+
+__device__ inline int pidx(int i) { return i + (i >> 5); }  // LDS bank padding
+
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_reduce(const uint32_t* __restrict__ in, uint64_t n, uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t wsum[17];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  uint32_t s = 0;
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    uint64_t i = base + (uint64_t)r * kScanThreads + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  uint32_t tot;
+  block_excl_scan(s, wsum, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024)
+k_scan_top(uint32_t* __restrict__ bsum, uint32_t nb, uint32_t* __restrict__ total) {
+  __shared__ uint32_t wsum[17];
+  uint32_t carry = 0;
+  for (uint32_t c = 0; c < nb; c += blockDim.x) {
+    uint32_t i = c + threadIdx.x;
+    uint32_t v = i < nb ? bsum[i] : 0u;
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(v, wsum, &tot);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_apply(const uint32_t* in, uint32_t* out, uint64_t n, const uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t tile[kScanTile + kScanTile / 32];
+  __shared__ uint32_t wsum[17];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    int li = r * kScanThreads + threadIdx.x;
+    uint64_t i = base + li;
+    tile[pidx(li)] = i < n ? in[i] : 0u;
+  }
+  __syncthreads();
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) s += tile[pidx(threadIdx.x * kScanItems + j)];
+  uint32_t run = block_excl_scan(s, wsum, nullptr) + bsum[blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    int li = pidx(threadIdx.x * kScanItems + j);
+    uint32_t v = tile[li];
+    tile[li] = run;
+    run += v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    int li = r * kScanThreads + threadIdx.x;
+    uint64_t i = base + li;
+    if (i < n) out[i] = tile[pidx(li)];
+  }
+}
+
+template <typename K>
+__global__ void __launch_bounds__(kRadixThreads)
+k_radix_hist(const K* __restrict__ keys, uint64_t n, int shift, int bits,
+             uint32_t* __restrict__ hist, uint32_t nb) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t mask = (1u << bits) - 1u;
+  const uint64_t base = (uint64_t)blockIdx.x * kRadixTile;
+#pragma unroll
+  for (int r = 0; r < kRadixItems; ++r) {
+    uint64_t i = base + (uint64_t)r * kRadixThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: element order inside the tile is preserved among equal
+// digits.  Ranks come from wave ballots (peer masks per digit) combined
+// across the four waves and across rounds through LDS counters.
+template <typename K>
+__global__ void __launch_bounds__(kRadixThreads)
+k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                K* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n, int shift,
+                int bits, const uint32_t* __restrict__ hscan, uint32_t nb) {
+  __shared__ uint32_t offs[256];
+  __shared__ uint32_t running[256];
+  __shared__ uint32_t wcnt[4][256];
+  const int tid = threadIdx.x;
+  const int lane = __lane_id();
+  const int w = tid >> 6;
+  const uint32_t mask = (1u << bits) - 1u;
+  offs[tid] = hscan[(uint64_t)tid * nb + blockIdx.x];
+  running[tid] = 0;
+  for (int i = 0; i < 4; ++i) wcnt[i][tid] = 0;
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * kRadixTile;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  for (int r = 0; r < kRadixItems; ++r) {
+    uint64_t i = base + (uint64_t)r * kRadixThreads + tid;
+    bool valid = i < n;
+    K key = 0;
+    uint32_t val = 0, dig = 0;
+    if (valid) {
+      key = kin[i];
+      val = vin[i];
+      dig = (uint32_t)(key >> shift) & mask;
+    }
+    uint64_t m = __ballot(valid);
+    for (int b = 0; b < bits; ++b) {
+      bool bit = (dig >> b) & 1u;
+      uint64_t bb = __ballot(valid && bit);
+      m &= bit ? bb : ~bb;
+    }
+    uint32_t wrank = (uint32_t)__popcll(m & lt_mask);
+    if (valid && wrank == 0) wcnt[w][dig] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (valid) {
+      uint32_t pre = running[dig];
+      for (int v = 0; v < w; ++v) pre += wcnt[v][dig];
+      uint32_t dst = offs[dig] + pre + wrank;
+      kout[dst] = key;
+      vout[dst] = val;
+    }
+    __syncthreads();
+    running[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+    wcnt[0][tid] = 0;
+    wcnt[1][tid] = 0;
+    wcnt[2][tid] = 0;
+    wcnt[3][tid] = 0;
+    __syncthreads();
+  }
+}
+
+template <typename K>
+int radix_sort_pairs(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, uint64_t n,
+                     int begin_bit, int end_bit, uint32_t* tmp, hipStream_t s) {
+  if (n == 0 || begin_bit >= end_bit) return 0;
+  const uint32_t nb = (uint32_t)((n + kRadixTile - 1) / kRadixTile);
+  uint32_t* hist = tmp;
+  uint32_t* stmp = tmp + (size_t)256 * nb;
+  K* kb[2] = {keys, keys_alt};
+  uint32_t* vb[2] = {vals, vals_alt};
+  int cur = 0;
+  for (int shift = begin_bit; shift < end_bit; shift += 8) {
+    int bits = end_bit - shift < 8 ? end_bit - shift : 8;
+    hipLaunchKernelGGL(k_radix_hist<K>, dim3(nb), dim3(kRadixThreads), 0, s, kb[cur], n, shift,
+                       bits, hist, nb);
+    scan_exclusive_u32(hist, hist, (uint64_t)256 * nb, nullptr, stmp, s);
+    hipLaunchKernelGGL(k_radix_scatter<K>, dim3(nb), dim3(kRadixThreads), 0, s, kb[cur], vb[cur],
+                       kb[cur ^ 1], vb[cur ^ 1], n, shift, bits, hist, nb);
+    cur ^= 1;
+  }
+  return cur;
+}
+
+}  // namespace
+
+size_t scan_tmp_words(uint64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 2; }
+
+void scan_exclusive_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
+                        uint32_t* tmp, hipStream_t s) {
+  if (n == 0) {
+    if (total) hipMemsetAsync(total, 0, sizeof(uint32_t), s);
+    return;
+  }
+  const uint32_t nb = (uint32_t)((n + kScanTile - 1) / kScanTile);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, in, n, tmp);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, nb, total);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanThreads), 0, s, in, out, n, tmp);
+}
+
+size_t radix_tmp_words(uint64_t n) {
+  uint64_t nb = (n + kRadixTile - 1) / kRadixTile;
+  return (size_t)(256 * nb + scan_tmp_words(256 * nb));
+}
+
+int radix_sort_pairs_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
+                         uint32_t* vals_alt, uint64_t n, int begin_bit, int end_bit,
+                         uint32_t* tmp, hipStream_t s) {
+  return radix_sort_pairs<uint64_t>(keys, vals, keys_alt, vals_alt, n, begin_bit, end_bit, tmp, s);
+}
+
+int radix_sort_pairs_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                         uint32_t* vals_alt, uint64_t n, int begin_bit, int end_bit,
+                         uint32_t* tmp, hipStream_t s) {
+  return radix_sort_pairs<uint32_t>(keys, vals, keys_alt, vals_alt, n, begin_bit, end_bit, tmp, s);
+}
+
+}  // namespace bdl

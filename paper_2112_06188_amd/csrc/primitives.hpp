@@ -1,0 +1,67 @@
+// Device-wide primitives used by the build and the query paths: exclusive
+// prefix sums (the prefix-sum primitive of Section III-D) and a stable LSD
+// radix sort of (key, uint32 value) pairs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bdl {
+
+// Inclusive/exclusive scans inside a 64-lane wavefront and a workgroup.
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan over the workgroup (blockDim.x a multiple of 64, <= 1024).
+// `wsum` is LDS scratch of at least 17 words.  Returns the exclusive prefix;
+// *total receives the workgroup sum.  Contains __syncthreads.
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t* total) {
+  const int lane = __lane_id();
+  const int w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  uint32_t inc = wave_incl_scan(v);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int i = 0; i < nw; ++i) {
+      uint32_t t = wsum[i];
+      wsum[i] = run;
+      run += t;
+    }
+    wsum[16] = run;
+  }
+  __syncthreads();
+  uint32_t r = wsum[w] + inc - v;
+  if (total) *total = wsum[16];
+  __syncthreads();
+  return r;
+}
+
+// Scratch (uint32 words) needed by scan_exclusive_u32 for n elements.
+size_t scan_tmp_words(uint64_t n);
+// out[i] = sum(in[0..i)); in == out is allowed.  If total != nullptr the sum
+// of all n elements is written there (device).
+void scan_exclusive_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
+                        uint32_t* tmp, hipStream_t s);
+
+// Scratch (uint32 words) needed by the radix sorts for n elements.
+size_t radix_tmp_words(uint64_t n);
+// Stable sort of n pairs by key bits [begin_bit, end_bit).  Returns 0 when
+// the sorted pairs are in (keys, vals), 1 when they are in (keys_alt,
+// vals_alt).
+int radix_sort_pairs_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
+                         uint32_t* vals_alt, uint64_t n, int begin_bit, int end_bit,
+                         uint32_t* tmp, hipStream_t s);
+int radix_sort_pairs_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                         uint32_t* vals_alt, uint64_t n, int begin_bit, int end_bit,
+                         uint32_t* tmp, hipStream_t s);
+
+}  // namespace bdl

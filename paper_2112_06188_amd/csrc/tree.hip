@@ -1,0 +1,866 @@
+// Host controller of the BDL-tree and the C ABI declared in bdl.h.
+//
+// The controller only decides: it mirrors F (the bitmask of non-empty static
+// trees, Section III-C), every tree's slot and live counts and the buffer's
+// size, plans each Insert_L (which trees are built, which are cleared, which
+// pool slice goes where) and owns the device memory.  All work on points is
+// done by the kernels in build.hip, erase.hip and knn.hip, enqueued on the
+// tree's stream.
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "bdl.h"
+#include "bdl_common.hpp"
+#include "build.hpp"
+#include "erase.hpp"
+#include "knn.hpp"
+#include "primitives.hpp"
+
+using namespace bdl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+struct LevelState {
+  float* rec = nullptr;
+  float* nodes = nullptr;
+  int64_t cap = 0;
+  int64_t n_slots = 0;
+  int64_t live = 0;
+  int64_t n_nodes = 0;
+  bool on = false;
+};
+
+}  // namespace
+
+struct bdl_tree {
+  bdl_config cfg;
+  hipStream_t s = nullptr;
+  int d = 0, S = 0, NS = 0;
+  uint32_t T = 0;
+  uint64_t F = 0;
+  LevelState lev[kMaxLevels];
+  // buffer: arrival-order pool (two arrays, ping-pong) and its tree
+  float* pool[2] = {nullptr, nullptr};
+  int pcur = 0;
+  int64_t bn = 0;
+  float* brec = nullptr;
+  float* bnodes = nullptr;
+  int64_t b_nodes = 0;
+  uint64_t* map = nullptr;
+  uint32_t* d_live = nullptr;   // kMaxLevels
+  uint32_t* d_misc = nullptr;   // erase counters [0..1], validation [4..6]
+  uint32_t* h_pin = nullptr;    // pinned staging, kMaxLevels + 16 words
+  BuildScratch sc;
+  QueryScratch qs;
+  float* rbuf = nullptr;        // Erase_L's gathered points R (records)
+  int64_t rbuf_cap = 0;
+  int64_t rebuilt = 0, reinserted = 0;
+  size_t held = 0;
+  std::unordered_map<void*, size_t> sizes;
+  // phase timing (BDL_FLAG_PROFILE)
+  PhaseTimer pt;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  hipEvent_t ev_open[BDL_NPHASES] = {};
+  double prof_ms[BDL_NPHASES] = {};
+  int64_t prof_calls[BDL_NPHASES] = {};
+};
+
+namespace {
+
+void* dmalloc(bdl_tree* t, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (t->cfg.mem_budget && t->held + bytes > t->cfg.mem_budget) return nullptr;
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  t->held += bytes;
+  t->sizes[p] = bytes;
+  return p;
+}
+
+void dfree(bdl_tree* t, void* p) {
+  if (!p) return;
+  auto it = t->sizes.find(p);
+  if (it != t->sizes.end()) {
+    t->held -= it->second;
+    t->sizes.erase(it);
+  }
+  (void)hipFree(p);
+}
+
+hipEvent_t take_event(bdl_tree* t) {
+  if (!t->ev_free.empty()) {
+    hipEvent_t e = t->ev_free.back();
+    t->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+void phase_mark(void* ctx, int ph, int is_end) {
+  bdl_tree* t = (bdl_tree*)ctx;
+  if (!is_end) {
+    hipEvent_t e = take_event(t);
+    if (e && hipEventRecord(e, t->s) == hipSuccess) t->ev_open[ph] = e;
+    return;
+  }
+  hipEvent_t a = t->ev_open[ph];
+  t->ev_open[ph] = nullptr;
+  if (!a) return;
+  hipEvent_t b = take_event(t);
+  if (!b || hipEventRecord(b, t->s) != hipSuccess) {
+    t->ev_free.push_back(a);
+    return;
+  }
+  t->ev_pending.push_back({ph, {a, b}});
+}
+
+// Fold completed event pairs into the per-phase totals.
+void resolve_events(bdl_tree* t) {
+  for (auto& pe : t->ev_pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(pe.second.second) == hipSuccess &&
+        hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
+      t->prof_ms[pe.first] += ms;
+      t->prof_calls[pe.first] += 1;
+    }
+    t->ev_free.push_back(pe.second.first);
+    t->ev_free.push_back(pe.second.second);
+  }
+  t->ev_pending.clear();
+}
+
+int64_t level_cap(const bdl_tree* t, int i) { return ((int64_t)1 << i) * t->cfg.buffer_size; }
+
+void free_build_scratch(bdl_tree* t) {
+  BuildScratch& sc = t->sc;
+  for (int i = 0; i < 2; ++i) {
+    dfree(t, sc.soa[i]);
+    dfree(t, sc.seg[i]);
+    dfree(t, sc.segtb[i]);
+    dfree(t, sc.keys[i]);
+    dfree(t, sc.vals[i]);
+  }
+  dfree(t, sc.tile_left);
+  dfree(t, sc.tile_off);
+  dfree(t, sc.fin);
+  dfree(t, sc.emit);
+  dfree(t, sc.final_of);
+  dfree(t, sc.tmp);
+  dfree(t, sc.tile_cnt);
+  BuildCounters* hc = sc.host_ctr;
+  BuildCounters* dc = sc.ctr;
+  Job* jb = sc.jobs;
+  sc = BuildScratch();
+  sc.host_ctr = hc;
+  sc.ctr = dc;
+  sc.jobs = jb;
+}
+
+// Grow the build scratch to hold `need` points.  Returns false on ENOMEM
+// (the old scratch is kept).
+bool ensure_build_scratch(bdl_tree* t, uint64_t need) {
+  if (need <= t->sc.cap) return true;
+  uint64_t cap = t->sc.cap ? t->sc.cap : 4096;
+  while (cap < need) cap *= 2;
+  if (cap > (1ull << 31)) cap = need;
+  const int d = t->d;
+  BuildScratch n;
+  n.cap = cap;
+  n.max_seg = cap / t->T + kMaxJobs + 8;
+  n.max_tiles = cap / kTile + n.max_seg + 8;
+  n.max_fin = 2 * (uint64_t)(kMaxDepth + 1) * (cap / t->T + 1) + 2 * kMaxJobs;
+  n.max_emit = 2 * cap + kMaxJobs;
+  n.tmp_words = radix_tmp_words(n.max_emit);
+  uint64_t st = scan_tmp_words(cap) + 16;
+  if (st > n.tmp_words) n.tmp_words = st;
+  bool ok = true;
+  auto A = [&](size_t bytes) -> void* {
+    void* p = ok ? dmalloc(t, bytes) : nullptr;
+    if (!p) ok = false;
+    return p;
+  };
+  for (int i = 0; i < 2; ++i) {
+    n.soa[i] = (float*)A((size_t)(d + 1) * cap * 4);
+    n.seg[i] = (Seg*)A(n.max_seg * sizeof(Seg));
+    n.segtb[i] = (uint32_t*)A(n.max_seg * 4);
+    n.keys[i] = (uint64_t*)A(n.max_emit * 8);
+    n.vals[i] = (uint32_t*)A(n.max_emit * 4);
+  }
+  n.tile_left = (uint32_t*)A(n.max_tiles * 4);
+  n.tile_off = (uint32_t*)A(n.max_tiles * 4);
+  n.fin = (Fin*)A(n.max_fin * sizeof(Fin));
+  n.emit = (uint32_t*)A(n.max_emit * (size_t)emit_stride(d) * 4);
+  n.final_of = (uint32_t*)A(n.max_emit * 4);
+  n.tmp = (uint32_t*)A(n.tmp_words * 4);
+  n.tile_cnt = (uint32_t*)A((cap / kTile + 2) * 4 + (2ull << 20));
+  if (!ok) {
+    void* ps[] = {n.soa[0], n.soa[1], n.seg[0], n.seg[1], n.segtb[0], n.segtb[1], n.keys[0],
+                  n.keys[1], n.vals[0], n.vals[1], n.tile_left, n.tile_off, n.fin, n.emit,
+                  n.final_of, n.tmp, n.tile_cnt};
+    for (void* p : ps) dfree(t, p);
+    return false;
+  }
+  (void)hipStreamSynchronize(t->s);
+  free_build_scratch(t);
+  n.host_ctr = t->sc.host_ctr;
+  n.ctr = t->sc.ctr;
+  n.jobs = t->sc.jobs;
+  t->sc = n;
+  return true;
+}
+
+bool ensure_query_scratch(bdl_tree* t, uint64_t need) {
+  if (need <= t->qs.cap) return true;
+  uint64_t cap = t->qs.cap ? t->qs.cap : 65536;
+  while (cap < need) cap *= 2;
+  QueryScratch n;
+  n.cap = cap;
+  bool ok = true;
+  auto A = [&](size_t bytes) -> void* {
+    void* p = ok ? dmalloc(t, bytes) : nullptr;
+    if (!p) ok = false;
+    return p;
+  };
+  for (int i = 0; i < 2; ++i) {
+    n.keys[i] = (uint32_t*)A(cap * 4);
+    n.vals[i] = (uint32_t*)A(cap * 4);
+  }
+  n.tmp = (uint32_t*)A(radix_tmp_words(cap) * 4);
+  n.box = (uint32_t*)A(2 * kMaxDim * 4);
+  if (!ok) {
+    void* ps[] = {n.keys[0], n.keys[1], n.vals[0], n.vals[1], n.tmp, n.box};
+    for (void* p : ps) dfree(t, p);
+    return false;
+  }
+  (void)hipStreamSynchronize(t->s);
+  void* old[] = {t->qs.keys[0], t->qs.keys[1], t->qs.vals[0], t->qs.vals[1], t->qs.tmp,
+                 t->qs.box};
+  for (void* p : old) dfree(t, p);
+  t->qs = n;
+  return true;
+}
+
+bool ensure_level(bdl_tree* t, int j) {
+  LevelState& L = t->lev[j];
+  if (L.rec) return true;
+  const int64_t cap = level_cap(t, j);
+  float* rec = (float*)dmalloc(t, (size_t)cap * t->S * 4);
+  if (!rec) return false;
+  float* nodes = (float*)dmalloc(t, (size_t)(2 * cap) * t->NS * 4);
+  if (!nodes) {
+    dfree(t, rec);
+    return false;
+  }
+  L.rec = rec;
+  L.nodes = nodes;
+  L.cap = cap;
+  return true;
+}
+
+void upload_live(bdl_tree* t) {
+  uint32_t v[kMaxLevels];
+  for (int i = 0; i < kMaxLevels; ++i) v[i] = t->lev[i].on ? (uint32_t)t->lev[i].live : 0u;
+  launch_store_u32(t->d_live, v, kMaxLevels, t->s);
+}
+
+// Insert_L (Alg. 3) over the pool = buffer (arrival order) ++ batch.  The
+// batch is either caller rows [n][d] with ids, or records (batch_ids null).
+// Readings of what the paper leaves open:
+//  - floor(|pool| / X) whole chunks of X points leave the pool; its last
+//    |pool| mod X points form the new buffer (this reproduces Fig. 4);
+//  - F_new = F + floor(|pool| / X); new trees J = F_new \ F; cleared trees
+//    C = F \ F_new (all below the highest new tree j*);
+//  - j* takes the live points of the cleared trees (ascending tree, then
+//    slot order) followed by the leading pool slice that fills its nominal
+//    capacity 2^j* X; each other new tree, highest first, takes the next
+//    pool slice of 2^j X points.
+int insert_impl(bdl_tree* t, const float* batch, const uint32_t* batch_ids, int64_t n) {
+  const int64_t X = t->cfg.buffer_size;
+  const int64_t pn = t->bn + n;
+  const uint64_t m = (uint64_t)(pn / X);
+  const uint64_t Fn = t->F + m;
+  if (Fn >> (kMaxLevels - 1)) return fail(BDL_EINVAL, "too many points for the level table");
+  const uint64_t J = Fn & ~t->F;
+  const uint64_t C = t->F & ~Fn;
+  struct Src {
+    int kind;  // 0 whole level, 1 live records of a level, 2 pool range
+    int level;
+    uint64_t p0, cnt, dst;
+  };
+  std::vector<Src> srcs;
+  JobTable jt;
+  std::memset(&jt, 0, sizeof(jt));
+  uint64_t base = 0;
+  int64_t off = 0;
+  std::vector<int> job_level;
+  if (J) {
+    const int js = 63 - __builtin_clzll(J);
+    int64_t ccap = 0, clive = 0;
+    for (int i = 0; i < kMaxLevels; ++i)
+      if ((C >> i) & 1u) {
+        ccap += level_cap(t, i);
+        clive += t->lev[i].live;
+      }
+    const int64_t slice = level_cap(t, js) - ccap;
+    if (slice < 0 || slice > pn) return fail(BDL_EINVAL, "inconsistent insert plan");
+    uint64_t acc = base;
+    for (int i = 0; i < kMaxLevels; ++i) {
+      if (!((C >> i) & 1u)) continue;
+      const LevelState& L = t->lev[i];
+      srcs.push_back({L.live == L.n_slots ? 0 : 1, i, 0, (uint64_t)L.n_slots, acc});
+      acc += (uint64_t)L.live;
+    }
+    srcs.push_back({2, -1, 0, (uint64_t)slice, acc});
+    Job jb{};
+    jb.base = (uint32_t)base;
+    jb.count = (uint32_t)(clive + slice);
+    jb.level = (uint32_t)js;
+    jb.write_map = 1;
+    jt.jobs[jt.n++] = jb;
+    job_level.push_back(js);
+    base += (uint64_t)(clive + slice);
+    off = slice;
+    for (int j = js - 1; j >= 0; --j) {
+      if (!((J >> j) & 1u)) continue;
+      const int64_t c = level_cap(t, j);
+      srcs.push_back({2, -1, (uint64_t)off, (uint64_t)c, base});
+      Job jj{};
+      jj.base = (uint32_t)base;
+      jj.count = (uint32_t)c;
+      jj.level = (uint32_t)j;
+      jj.write_map = 1;
+      jt.jobs[jt.n++] = jj;
+      job_level.push_back(j);
+      base += (uint64_t)c;
+      off += c;
+    }
+  }
+  const int64_t bn_new = pn - off;
+  if (bn_new < 0 || bn_new >= X) return fail(BDL_EINVAL, "inconsistent buffer plan");
+  if (bn_new > 0) {
+    srcs.push_back({2, -1, (uint64_t)off, (uint64_t)bn_new, base});
+    Job jb{};
+    jb.base = (uint32_t)base;
+    jb.count = (uint32_t)bn_new;
+    jb.level = kBufferLevel;
+    jb.write_map = 0;
+    jt.jobs[jt.n++] = jb;
+    job_level.push_back(-1);
+    base += (uint64_t)bn_new;
+  }
+  const uint64_t R = base;
+  if (R >= (1ull << 31)) return fail(BDL_EINVAL, "insert rebuilds too many points at once");
+  // ---- memory first: nothing has been enqueued yet ----
+  for (int i = 0; i < jt.n; ++i)
+    if (job_level[i] >= 0 && !ensure_level(t, job_level[i]))
+      return fail(BDL_ENOMEM, "cannot allocate a static tree");
+  if (!t->pool[0]) {
+    t->pool[0] = (float*)dmalloc(t, (size_t)X * t->S * 4);
+    t->pool[1] = (float*)dmalloc(t, (size_t)X * t->S * 4);
+    t->brec = (float*)dmalloc(t, (size_t)X * t->S * 4);
+    t->bnodes = (float*)dmalloc(t, (size_t)(2 * X) * t->NS * 4);
+    if (!t->pool[0] || !t->pool[1] || !t->brec || !t->bnodes) {
+      dfree(t, t->pool[0]);
+      dfree(t, t->pool[1]);
+      dfree(t, t->brec);
+      dfree(t, t->bnodes);
+      t->pool[0] = t->pool[1] = t->brec = t->bnodes = nullptr;
+      return fail(BDL_ENOMEM, "cannot allocate the buffer");
+    }
+  }
+  if (R && !ensure_build_scratch(t, R)) return fail(BDL_ENOMEM, "cannot allocate build scratch");
+  for (int i = 0; i < jt.n; ++i) {
+    if (job_level[i] >= 0) {
+      jt.jobs[i].rec = t->lev[job_level[i]].rec;
+      jt.jobs[i].nodes = t->lev[job_level[i]].nodes;
+      jt.jobs[i].node_cap = (uint32_t)(2 * t->lev[job_level[i]].cap);
+    } else {
+      jt.jobs[i].rec = t->brec;
+      jt.jobs[i].nodes = t->bnodes;
+      jt.jobs[i].node_cap = (uint32_t)(2 * X);
+    }
+  }
+  // ---- gather ----
+  t->pt.begin(BDL_PH_GATHER);
+  PoolSrc ps;
+  ps.bufrec = t->pool[t->pcur];
+  ps.bn = (uint64_t)t->bn;
+  ps.batch = batch;
+  ps.batch_ids = batch_ids;
+  ps.n = (uint64_t)n;
+  BuildScratch& sc = t->sc;
+  for (const Src& sr : srcs) {
+    if (sr.kind == 0) {
+      launch_records_to_soa(t->lev[sr.level].rec, t->d, sr.cnt, sc.soa[0], sc.cap, sr.dst, t->s);
+    } else if (sr.kind == 1) {
+      launch_compact_live(t->lev[sr.level].rec, t->d, sr.cnt, sc.soa[0], sc.cap, sr.dst, nullptr,
+                          sc.tile_cnt, sc.tmp, t->s);
+    } else {
+      launch_pool_to_soa(ps, t->d, sr.p0, sr.cnt, sc.soa[0], sc.cap, sr.dst, t->s);
+    }
+  }
+  launch_pool_to_records(ps, t->d, (uint64_t)off, (uint64_t)bn_new, t->pool[t->pcur ^ 1], t->map,
+                         t->cfg.id_capacity, t->s);
+  t->pt.end(BDL_PH_GATHER);
+  // ---- build ----
+  uint32_t job_nodes[kMaxJobs] = {0};
+  const char* err = nullptr;
+  int rc = run_build(jt, sc, t->d, (uint32_t)t->cfg.leaf_size, t->T, t->map, t->cfg.id_capacity,
+                     t->s, job_nodes, &err, t->pt);
+  if (rc) return fail(rc, err ? err : "build failed");
+  // ---- commit ----
+  for (int i = 0; i < kMaxLevels; ++i) {
+    if (!((C >> i) & 1u)) continue;
+    LevelState& L = t->lev[i];
+    L.on = false;
+    L.n_slots = L.live = L.n_nodes = 0;
+  }
+  t->b_nodes = 0;
+  for (int i = 0; i < jt.n; ++i) {
+    if (job_level[i] >= 0) {
+      LevelState& L = t->lev[job_level[i]];
+      L.on = true;
+      L.n_slots = L.live = jt.jobs[i].count;
+      L.n_nodes = job_nodes[i];
+      t->rebuilt += jt.jobs[i].count;
+    } else {
+      t->b_nodes = job_nodes[i];
+    }
+  }
+  t->pcur ^= 1;
+  t->bn = bn_new;
+  t->F = Fn;
+  upload_live(t);
+  if (hipGetLastError() != hipSuccess) return fail(BDL_EHIP, "kernel launch failed in insert");
+  return 0;
+}
+
+LevelViews make_views(const bdl_tree* t) {
+  LevelViews v;
+  std::memset(&v, 0, sizeof(v));
+  for (int i = kMaxLevels - 1; i >= 0; --i) {
+    const LevelState& L = t->lev[i];
+    if (!L.on || L.n_nodes == 0) continue;
+    v.v[v.n].rec = L.rec;
+    v.v[v.n].nodes = L.nodes;
+    v.v[v.n].n_slots = (uint32_t)L.n_slots;
+    v.v[v.n].n_nodes = (uint32_t)L.n_nodes;
+    ++v.n;
+  }
+  if (t->bn > 0 && t->b_nodes > 0) {
+    v.v[v.n].rec = t->brec;
+    v.v[v.n].nodes = t->bnodes;
+    v.v[v.n].n_slots = (uint32_t)t->bn;
+    v.v[v.n].n_nodes = (uint32_t)t->b_nodes;
+    ++v.n;
+  }
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bdl_last_error(void) { return g_err.c_str(); }
+
+int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out) {
+  if (!cfg || !out) return fail(BDL_EINVAL, "null argument");
+  *out = nullptr;
+  if (cfg->dim < 1 || cfg->dim > BDL_MAX_DIM) return fail(BDL_EINVAL, "dim must be in 1..16");
+  if (cfg->leaf_size < 1) return fail(BDL_EINVAL, "leaf_size must be >= 1");
+  if (cfg->buffer_size < 1 || cfg->buffer_size > (1 << 24))
+    return fail(BDL_EINVAL, "buffer_size must be in 1..2^24");
+  if (cfg->id_capacity < 1) return fail(BDL_EINVAL, "id_capacity must be >= 1");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(BDL_EHIP, "no HIP device");
+  bdl_tree* t = new bdl_tree();
+  t->cfg = *cfg;
+  t->s = (hipStream_t)stream;
+  t->d = cfg->dim;
+  t->S = rec_stride(cfg->dim);
+  t->NS = node_stride(cfg->dim);
+  t->T = finisher_threshold(cfg->dim, cfg->leaf_size);
+  if (cfg->flags & BDL_FLAG_PROFILE) {
+    t->pt.ctx = t;
+    t->pt.mark = phase_mark;
+  }
+  t->map = (uint64_t*)dmalloc(t, (size_t)cfg->id_capacity * 8);
+  t->d_live = (uint32_t*)dmalloc(t, kMaxLevels * 4);
+  t->d_misc = (uint32_t*)dmalloc(t, 16 * 4);
+  t->sc.ctr = (BuildCounters*)dmalloc(t, sizeof(BuildCounters));
+  t->sc.jobs = (Job*)dmalloc(t, sizeof(Job) * kMaxJobs);
+  bool ok = t->map && t->d_live && t->d_misc && t->sc.ctr && t->sc.jobs;
+  if (ok && hipHostMalloc((void**)&t->h_pin, (kMaxLevels + 16) * 4, hipHostMallocDefault) !=
+                hipSuccess)
+    ok = false;
+  if (ok && hipHostMalloc((void**)&t->sc.host_ctr, sizeof(BuildCounters), hipHostMallocDefault) !=
+                hipSuccess)
+    ok = false;
+  if (!ok) {
+    bdl_destroy(t);
+    return fail(BDL_ENOMEM, "cannot allocate the tree");
+  }
+  launch_fill_u32((uint32_t*)t->map, 0xFFFFFFFFu, (uint64_t)cfg->id_capacity * 2, t->s);
+  launch_fill_u32(t->d_live, 0u, kMaxLevels, t->s);
+  launch_fill_u32(t->d_misc, 0u, 16, t->s);
+  if (hipStreamSynchronize(t->s) != hipSuccess) {
+    bdl_destroy(t);
+    return fail(BDL_EHIP, "stream synchronisation failed");
+  }
+  *out = t;
+  return 0;
+}
+
+void bdl_destroy(bdl_tree* t) {
+  if (!t) return;
+  (void)hipStreamSynchronize(t->s);
+  std::vector<void*> ps;
+  for (auto& kv : t->sizes) ps.push_back(kv.first);
+  for (void* p : ps) dfree(t, p);
+  resolve_events(t);
+  for (hipEvent_t e : t->ev_free) (void)hipEventDestroy(e);
+  for (hipEvent_t e : t->ev_open)
+    if (e) (void)hipEventDestroy(e);
+  if (t->h_pin) (void)hipHostFree(t->h_pin);
+  if (t->sc.host_ctr) (void)hipHostFree(t->sc.host_ctr);
+  delete t;
+}
+
+int bdl_clear(bdl_tree* t) {
+  if (!t) return fail(BDL_EINVAL, "null tree");
+  for (int i = 0; i < kMaxLevels; ++i) {
+    LevelState& L = t->lev[i];
+    L.on = false;
+    L.n_slots = L.live = L.n_nodes = 0;
+  }
+  t->F = 0;
+  t->bn = 0;
+  t->b_nodes = 0;
+  t->rebuilt = t->reinserted = 0;
+  launch_fill_u32((uint32_t*)t->map, 0xFFFFFFFFu, (uint64_t)t->cfg.id_capacity * 2, t->s);
+  launch_fill_u32(t->d_live, 0u, kMaxLevels, t->s);
+  if (hipGetLastError() != hipSuccess) return fail(BDL_EHIP, "clear failed");
+  return 0;
+}
+
+int bdl_profile(bdl_tree* t, bdl_profile_t* out, int reset) {
+  if (!t) return fail(BDL_EINVAL, "null tree");
+  if (hipStreamSynchronize(t->s) != hipSuccess) return fail(BDL_EHIP, "stream error");
+  resolve_events(t);
+  if (out) {
+    for (int i = 0; i < BDL_NPHASES; ++i) {
+      out->ms[i] = t->prof_ms[i];
+      out->calls[i] = t->prof_calls[i];
+    }
+  }
+  if (reset) {
+    for (int i = 0; i < BDL_NPHASES; ++i) {
+      t->prof_ms[i] = 0.0;
+      t->prof_calls[i] = 0;
+    }
+  }
+  return 0;
+}
+
+int bdl_sync(bdl_tree* t) {
+  if (!t) return fail(BDL_EINVAL, "null tree");
+  if (hipMemcpyAsync(t->h_pin + kMaxLevels + 8, t->d_misc + 8, 4, hipMemcpyDeviceToHost, t->s) !=
+          hipSuccess ||
+      hipStreamSynchronize(t->s) != hipSuccess)
+    return fail(BDL_EHIP, "stream error");
+  if (t->h_pin[kMaxLevels + 8]) {
+    launch_fill_u32(t->d_misc + 8, 0u, 1, t->s);
+    (void)hipStreamSynchronize(t->s);
+    return fail(BDL_EHIP, "k-NN traversal met an out-of-range tree index");
+  }
+  return 0;
+}
+
+int bdl_insert(bdl_tree* t, const float* pts, const uint32_t* ids, int64_t n) {
+  if (!t) return fail(BDL_EINVAL, "null tree");
+  if (n < 0) return fail(BDL_EINVAL, "negative n");
+  if (n == 0) return 0;
+  if (!pts || !ids) return fail(BDL_EINVAL, "null points or ids");
+  if (n >= (1ll << 31)) return fail(BDL_EINVAL, "batch too large");
+  if (t->cfg.flags & BDL_FLAG_CHECK_INPUTS) {
+    launch_fill_u32(t->d_misc + 4, 0u, 3, t->s);
+    launch_validate(pts, ids, (uint64_t)n, t->d, t->map, t->cfg.id_capacity, t->d_misc + 4, t->s);
+    if (hipMemcpyAsync(t->h_pin, t->d_misc + 4, 12, hipMemcpyDeviceToHost, t->s) != hipSuccess ||
+        hipStreamSynchronize(t->s) != hipSuccess)
+      return fail(BDL_EHIP, "input validation failed to run");
+    if (t->h_pin[0]) return fail(BDL_EINVAL, "ids must be < id_capacity");
+    if (t->h_pin[1]) return fail(BDL_EINVAL, "an inserted id is already live");
+    if (t->h_pin[2]) return fail(BDL_EINVAL, "coordinates must be finite");
+  }
+  return insert_impl(t, pts, ids, n);
+}
+
+int bdl_erase(bdl_tree* t, const float* pts, const uint32_t* ids, int64_t n, int64_t* n_erased) {
+  if (!t) return fail(BDL_EINVAL, "null tree");
+  if (n_erased) *n_erased = 0;
+  if (n < 0) return fail(BDL_EINVAL, "negative n");
+  if (n == 0) return 0;
+  if (!pts || !ids) return fail(BDL_EINVAL, "null points or ids");
+  // Erase_L's R holds at most half of the static trees' capacity; reserve it
+  // before anything changes so that ENOMEM leaves the tree unchanged.
+  int64_t half = 0;
+  for (int i = 0; i < kMaxLevels; ++i)
+    if (t->lev[i].on) half += t->lev[i].cap / 2;
+  if (half > t->rbuf_cap) {
+    int64_t cap = t->rbuf_cap ? t->rbuf_cap : 4096;
+    while (cap < half) cap *= 2;
+    float* nb = (float*)dmalloc(t, (size_t)cap * t->S * 4);
+    if (!nb) return fail(BDL_ENOMEM, "cannot allocate the rebuild buffer");
+    (void)hipStreamSynchronize(t->s);
+    dfree(t, t->rbuf);
+    t->rbuf = nb;
+    t->rbuf_cap = cap;
+  }
+  if (!ensure_build_scratch(t, (uint64_t)bdl_size(t) + t->cfg.buffer_size))
+    return fail(BDL_ENOMEM, "cannot allocate build scratch");
+  EraseTable et;
+  std::memset(&et, 0, sizeof(et));
+  for (int i = 0; i < kMaxLevels; ++i)
+    if (t->lev[i].on) {
+      et.rec[i] = t->lev[i].rec;
+      et.nslots[i] = (uint32_t)t->lev[i].n_slots;
+    }
+  et.pool = t->pool[t->pcur];
+  et.bn = (uint32_t)t->bn;
+  launch_fill_u32(t->d_misc, 0u, 2, t->s);
+  t->pt.begin(BDL_PH_ERASE);
+  launch_erase(pts, ids, (uint64_t)n, t->d, t->map, t->cfg.id_capacity, et, t->d_live, t->d_misc,
+               t->s);
+  t->pt.end(BDL_PH_ERASE);
+  if (hipMemcpyAsync(t->h_pin, t->d_live, kMaxLevels * 4, hipMemcpyDeviceToHost, t->s) !=
+          hipSuccess ||
+      hipMemcpyAsync(t->h_pin + kMaxLevels, t->d_misc, 8, hipMemcpyDeviceToHost, t->s) !=
+          hipSuccess ||
+      hipStreamSynchronize(t->s) != hipSuccess)
+    return fail(BDL_EHIP, "erase failed");
+  const uint32_t erased = t->h_pin[kMaxLevels];
+  const uint32_t bufhits = t->h_pin[kMaxLevels + 1];
+  for (int i = 0; i < kMaxLevels; ++i)
+    if (t->lev[i].on) t->lev[i].live = t->h_pin[i];
+  if (n_erased) *n_erased = erased;
+  if (bufhits) {
+    // the buffer keeps its arrival order and shrinks (no half rule)
+    launch_compact_live(t->pool[t->pcur], t->d, (uint64_t)t->bn, nullptr, 0, 0,
+                        t->pool[t->pcur ^ 1], t->sc.tile_cnt, t->sc.tmp, t->s);
+    t->pcur ^= 1;
+    t->bn -= bufhits;
+  }
+  // half-capacity rule (Alg. 4): gather trees with 2 * live < 2^i X into R
+  int64_t rn = 0;
+  for (int i = 0; i < kMaxLevels; ++i) {
+    LevelState& L = t->lev[i];
+    if (!L.on || 2 * L.live >= L.cap) continue;
+    if (L.live > 0)
+      launch_compact_live(L.rec, t->d, (uint64_t)L.n_slots, nullptr, 0, 0, t->rbuf + rn * t->S,
+                          t->sc.tile_cnt, t->sc.tmp, t->s);
+    rn += L.live;
+    L.on = false;
+    L.n_slots = L.live = L.n_nodes = 0;
+    t->F &= ~(1ull << i);
+  }
+  if (rn > 0 || bufhits) {
+    int rc = insert_impl(t, t->rbuf, nullptr, rn);
+    if (rc) return rc;
+    t->reinserted += rn;
+  } else {
+    upload_live(t);
+  }
+  if (hipGetLastError() != hipSuccess) return fail(BDL_EHIP, "kernel launch failed in erase");
+  return 0;
+}
+
+int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_ids, float* out_d2) {
+  if (!t) return fail(BDL_EINVAL, "null tree");
+  if (k < 1 || k > BDL_MAX_K) return fail(BDL_EINVAL, "k must be in 1..64");
+  if (nq < 0) return fail(BDL_EINVAL, "negative nq");
+  if (nq == 0) return 0;
+  if (!q || !out_ids || !out_d2) return fail(BDL_EINVAL, "null query or output");
+  if (nq >= (1ll << 32)) return fail(BDL_EINVAL, "query batch too large");
+  const uint32_t* order = nullptr;
+  if ((uint64_t)nq >= kSortQueriesMin) {
+    if (!ensure_query_scratch(t, (uint64_t)nq)) return fail(BDL_ENOMEM, "query scratch");
+    t->pt.begin(BDL_PH_ORDER);
+    order = morton_order(t->d, q, (uint64_t)nq, t->qs, t->s);
+    t->pt.end(BDL_PH_ORDER);
+  }
+  LevelViews v = make_views(t);
+  t->pt.begin(BDL_PH_TRAVERSE);
+  int rc = launch_knn(t->d, k, q, (uint64_t)nq, v, order, out_ids, out_d2, t->d_misc + 8, t->s);
+  t->pt.end(BDL_PH_TRAVERSE);
+  if (rc) return fail(rc, "k-NN launch failed");
+  return 0;
+}
+
+int64_t bdl_size(const bdl_tree* t) {
+  if (!t) return 0;
+  int64_t s = t->bn;
+  for (int i = 0; i < kMaxLevels; ++i)
+    if (t->lev[i].on) s += t->lev[i].live;
+  return s;
+}
+
+int bdl_level_info(const bdl_tree* t, int32_t* nlev, int64_t* live, int64_t* cap,
+                   int64_t* buf_live, uint64_t* F) {
+  if (!t) return fail(BDL_EINVAL, "null tree");
+  int top = 0;
+  for (int i = 0; i < kMaxLevels; ++i)
+    if (t->lev[i].on) top = i + 1;
+  if (nlev) *nlev = top;
+  for (int i = 0; i < top; ++i) {
+    if (live) live[i] = t->lev[i].on ? t->lev[i].live : 0;
+    if (cap) cap[i] = level_cap(t, i);
+  }
+  if (buf_live) *buf_live = t->bn;
+  if (F) *F = t->F;
+  return 0;
+}
+
+int bdl_level_sizes(const bdl_tree* t, int32_t* nlev, int64_t* n_slots, int64_t* n_nodes,
+                    int64_t* buf_nodes) {
+  if (!t) return fail(BDL_EINVAL, "null tree");
+  int top = 0;
+  for (int i = 0; i < kMaxLevels; ++i)
+    if (t->lev[i].on) top = i + 1;
+  if (nlev) *nlev = top;
+  for (int i = 0; i < top; ++i) {
+    if (n_slots) n_slots[i] = t->lev[i].on ? t->lev[i].n_slots : 0;
+    if (n_nodes) n_nodes[i] = t->lev[i].on ? t->lev[i].n_nodes : 0;
+  }
+  if (buf_nodes) *buf_nodes = t->bn ? t->b_nodes : 0;
+  return 0;
+}
+
+int bdl_counters(const bdl_tree* t, int64_t* rebuilt_points, int64_t* reinserted_points) {
+  if (!t) return fail(BDL_EINVAL, "null tree");
+  if (rebuilt_points) *rebuilt_points = t->rebuilt;
+  if (reinserted_points) *reinserted_points = t->reinserted;
+  return 0;
+}
+
+int bdl_debug_export_level(bdl_tree* t, int32_t level, uint32_t* ids, float* pts,
+                           bdl_node* nodes, int64_t* n_slots, int64_t* n_nodes) {
+  if (!t) return fail(BDL_EINVAL, "null tree");
+  const float* rec;
+  const float* nd;
+  int64_t ns, nn;
+  if (level == -1) {
+    rec = t->brec;
+    nd = t->bnodes;
+    ns = t->bn;
+    nn = t->b_nodes;
+  } else {
+    if (level < 0 || level >= kMaxLevels || !t->lev[level].on)
+      return fail(BDL_EINVAL, "empty tree");
+    rec = t->lev[level].rec;
+    nd = t->lev[level].nodes;
+    ns = t->lev[level].n_slots;
+    nn = t->lev[level].n_nodes;
+  }
+  if (n_slots) *n_slots = ns;
+  if (n_nodes) *n_nodes = nn;
+  if (ns == 0) return level == -1 ? 0 : fail(BDL_EINVAL, "empty tree");
+  const int d = t->d, S = t->S, NS = t->NS;
+  std::vector<float> hr((size_t)ns * S), hn((size_t)nn * NS);
+  if (hipStreamSynchronize(t->s) != hipSuccess ||
+      hipMemcpy(hr.data(), rec, hr.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      (nn && hipMemcpy(hn.data(), nd, hn.size() * 4, hipMemcpyDeviceToHost) != hipSuccess))
+    return fail(BDL_EHIP, "export copy failed");
+  for (int64_t i = 0; i < ns; ++i) {
+    if (ids) std::memcpy(&ids[i], &hr[(size_t)i * S + d], 4);
+    if (pts)
+      for (int j = 0; j < d; ++j) pts[(size_t)i * d + j] = hr[(size_t)i * S + j];
+  }
+  if (nodes && nn) {
+    auto I = [&](int64_t i, int f) {
+      int32_t v;
+      std::memcpy(&v, &hn[(size_t)i * NS + f], 4);
+      return v;
+    };
+    for (int64_t i = 0; i < nn; ++i) {
+      bdl_node& o = nodes[i];
+      std::memset(&o, 0, sizeof(o));
+      o.split = hn[(size_t)i * NS + NF_SPLIT];
+      o.dim = I(i, NF_DIM);
+      o.parent = I(i, NF_PARENT);
+      for (int j = 0; j < d; ++j) {
+        o.lo[j] = hn[(size_t)i * NS + NF_BOX + j];
+        o.hi[j] = hn[(size_t)i * NS + NF_BOX + d + j];
+      }
+      if (o.dim < 0) {
+        o.split = 0.0f;
+        o.left = o.right = -1;
+        o.begin = I(i, NF_A);
+        o.count = I(i, NF_B);
+      } else {
+        o.left = I(i, NF_A);
+        o.right = I(i, NF_B);
+      }
+    }
+    // depth, path and subtree slot ranges from the root down / leaves up
+    std::vector<int64_t> order;
+    order.reserve(nn);
+    order.push_back(0);
+    nodes[0].depth = 0;
+    nodes[0].path = 0;
+    for (size_t h = 0; h < order.size(); ++h) {
+      bdl_node& p = nodes[order[h]];
+      if (p.dim < 0) continue;
+      for (int side = 0; side < 2; ++side) {
+        int32_t c = side ? p.right : p.left;
+        if (c < 0 || c >= nn) return fail(BDL_EHIP, "corrupt node array");
+        nodes[c].depth = p.depth + 1;
+        nodes[c].path = (p.path << 1) | (uint64_t)side;
+        order.push_back(c);
+      }
+    }
+    for (size_t h = order.size(); h-- > 0;) {
+      bdl_node& p = nodes[order[h]];
+      if (p.dim < 0) continue;
+      p.begin = nodes[p.left].begin;
+      p.count = nodes[p.left].count + nodes[p.right].count;
+    }
+  }
+  return 0;
+}
+
+int bdl_debug_export_buffer(bdl_tree* t, uint32_t* ids, float* pts, int64_t* n) {
+  if (!t) return fail(BDL_EINVAL, "null tree");
+  if (n) *n = t->bn;
+  if (t->bn == 0) return 0;
+  const int d = t->d, S = t->S;
+  std::vector<float> hr((size_t)t->bn * S);
+  if (hipStreamSynchronize(t->s) != hipSuccess ||
+      hipMemcpy(hr.data(), t->pool[t->pcur], hr.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(BDL_EHIP, "export copy failed");
+  for (int64_t i = 0; i < t->bn; ++i) {
+    if (ids) std::memcpy(&ids[i], &hr[(size_t)i * S + d], 4);
+    if (pts)
+      for (int j = 0; j < d; ++j) pts[(size_t)i * d + j] = hr[(size_t)i * S + j];
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+"""The 10M-point 3D workload at full size, in the launch configuration the
+benchmark times: 10 Insert_L batches of 1M uniform points, one Erase_L of
+1M random live points, kNN_L k=5 for all 9M live points.
+
+Checked at full size: the level schedule against the binary-counter closed
+form, the self-match property for every query (each query is a live point
+and coordinates are distinct, so its nearest neighbour is itself at 0), and
+sampled rows against the brute-force definition over the live set.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from bdl_inputs import workload
+from gpu_util import assert_knn_equal, bits, log, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def test_uniform3d_10m_full_size():
+    import torch
+
+    import paper_2112_06188_amd as bdl
+
+    torch.cuda.set_device(0)
+    log("case: uniform3d_10m full size")
+    w = workload("uniform3d_10m")
+    t = bdl.Tree(w.dim, leaf_size=w.leaf_size, buffer_size=w.buffer_size,
+                 id_capacity=w.id_capacity)
+    live = np.ones(w.id_capacity, dtype=bool)
+    all_pts = np.concatenate([op.pts for op in w.ops if op.kind == "insert"])
+    for op in w.ops:
+        if op.kind == "insert":
+            t.insert(to_dev(op.pts, torch), to_dev(op.ids, torch))
+        elif op.kind == "erase":
+            # before the erase: the closed form of 10M insert-only points
+            info = t.level_info()
+            assert bits(info["F"]) == [0, 2, 5, 9, 10, 13] and info["buf_live"] == 640
+            assert t.erase(to_dev(op.pts, torch), to_dev(op.ids, torch)) == op.n
+            live[op.ids.astype(np.int64)] = False
+        else:
+            qop = op
+    info = t.level_info()
+    assert bits(info["F"]) == [0, 2, 5, 9, 10, 13]
+    # the buffer holds the 640 newest points and loses those the erase names
+    assert info["buf_live"] == int(live[w.id_capacity - 640:].sum())
+    assert t.counters()["rebuilt"] == 23_520_256
+    # erasing 10% uniformly keeps every tree above half capacity
+    assert t.counters()["reinserted"] == 0
+    assert t.size() == 9_000_000
+    gi, gd = t.knn(to_dev(qop.pts, torch), qop.k)
+    t.sync()
+    qids = np.nonzero(live)[0].astype(np.uint32)
+    assert torch.equal(gi[:, 0], to_dev(qids, torch))
+    assert bool((gd[:, 0] == 0).all())
+    assert bool((gd[:, 1:] >= gd[:, :-1]).all())
+    rng = np.random.default_rng(7)
+    sel = np.sort(rng.choice(qop.n, size=192, replace=False))
+    oi, od = oracle.bruteforce_knn(all_pts[live], qids, qop.pts[sel], qop.k)
+    assert_knn_equal(gi.cpu().numpy()[sel], gd.cpu().numpy()[sel], oi, od, "full size sample")
+    t.close()
