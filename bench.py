@@ -59,6 +59,7 @@ def gpu_bench(args):
     n_er = sum(p.shape[0] for p, _ in erases)
     tree = bdl.Tree(w.dim, leaf_size=w.leaf_size, buffer_size=w.buffer_size,
                     id_capacity=w.id_capacity, profile=True)
+    tree.set_param(bdl.PARAM_KNN_KERNEL, args.knn_kernel)
     stream = torch.cuda.current_stream(dev)
     lat = {"insert": [], "erase": [], "knn": []}
 
@@ -137,6 +138,7 @@ def gpu_bench(args):
         "dtype": "f32",
         "data": "synthetic (seeded uniform float32 points in [0,1)^3)",
         "config": {"workload": w.name, "n_points": n_ins, "dim": w.dim, "k": k,
+                   "knn_kernel": ["lane", "wave"][args.knn_kernel],
                    "insert_batches": len(inserts), "erase_points": n_er, "queries": nq,
                    "leaf_size": w.leaf_size, "buffer_size": w.buffer_size},
         "knn_queries_per_s": nq / (knn_ms * 1e-3),
@@ -144,7 +146,9 @@ def gpu_bench(args):
         "erase_pts_per_s": n_er / (er_ms * 1e-3),
         "latency_ms": {kind: {"p50": _pct(v, 50), "p99": _pct(v, 99), "n": len(v)}
                        for kind, v in lat.items()},
-        "phase_ms_per_step": {kname: v["ms"] / args.steps for kname, v in prof.items()},
+        "phase_ms_per_step": {kname: v["ms"] / args.steps for kname, v in prof.items()
+                              if kname != "knn_work"},
+        "knn_work_per_query": {kname: v / (args.steps * nq) for kname, v in prof["knn_work"].items()},
         "final_levels": [i for i in range(64) if (info["F"] >> i) & 1],
         "buffer_points": info["buf_live"],
         "self_match_all_queries": self_ok,
@@ -215,6 +219,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="uniform3d_10m")
     ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--knn-kernel", type=int, default=1, choices=[0, 1],
+                    help="0: one lane per query, 1: one wavefront per 64 queries")
     ap.add_argument("--cpu-sample", type=int, default=200_000,
                     help="queries the CPU oracle answers for the baseline (0: skip)")
     args = ap.parse_args()

@@ -104,6 +104,13 @@ int bdl_erase(bdl_tree* t, const float* pts, const uint32_t* ids, int64_t n,
 int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_ids,
             float* out_d2);
 
+/* Tuning parameters (bdl_set_param).  They change speed, never results. */
+#define BDL_PARAM_KNN_KERNEL 1 /* 0: one lane per query; 1: one wavefront per
+                                  64 neighbouring queries (default) */
+#define BDL_PARAM_SORT_MIN 2   /* query batches of at least this many queries
+                                  are visited in Morton order (default 4096) */
+int bdl_set_param(bdl_tree* t, int32_t param, int64_t value);
+
 /* Remove every point.  Device memory stays allocated for reuse; the tree
  * is then as if just created.  Asynchronous. */
 int bdl_clear(bdl_tree* t);
@@ -115,6 +122,10 @@ int bdl_clear(bdl_tree* t);
 typedef struct {
   double ms[BDL_NPHASES];
   int64_t calls[BDL_NPHASES];
+  /* k-NN work summed over queries: nodes entered, leaves scanned and point
+   * distances evaluated (with the wavefront kernel a lane does the work of
+   * every node its wave enters) */
+  int64_t knn_nodes, knn_leaves, knn_points;
 } bdl_profile_t;
 int bdl_profile(bdl_tree* t, bdl_profile_t* out, int reset);
 

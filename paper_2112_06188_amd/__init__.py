@@ -31,13 +31,20 @@ EXPORTS = [
     "bdl_create", "bdl_insert", "bdl_erase", "bdl_knn", "bdl_clear", "bdl_sync", "bdl_destroy",
     "bdl_size", "bdl_level_info", "bdl_counters", "bdl_debug_export_level",
     "bdl_debug_export_buffer", "bdl_last_error", "bdl_profile", "bdl_level_sizes",
+    "bdl_set_param",
 ]
 FLAG_PROFILE = 2
+PARAM_KNN_KERNEL = 1
+PARAM_SORT_MIN = 2
+KNN_LANE = 0
+KNN_WAVE = 1
 PHASES = ["gather", "passes", "finish", "layout", "erase", "order", "traverse", "other"]
 
 
 class Profile(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("calls", ctypes.c_int64 * 8)]
+    _fields_ = [("ms", ctypes.c_double * 8), ("calls", ctypes.c_int64 * 8),
+                ("knn_nodes", ctypes.c_int64), ("knn_leaves", ctypes.c_int64),
+                ("knn_points", ctypes.c_int64)]
 
 NODE_DTYPE = np.dtype([
     ("lo", np.float32, (MAX_DIM,)),
@@ -93,6 +100,7 @@ def load_library(path: str = LIB_PATH):
     lib.bdl_knn.argtypes = [vp, vp, i64, i32, vp, vp]
     lib.bdl_sync.argtypes = [vp]
     lib.bdl_clear.argtypes = [vp]
+    lib.bdl_set_param.argtypes = [vp, i32, i64]
     lib.bdl_profile.argtypes = [vp, ctypes.POINTER(Profile), ctypes.c_int]
     lib.bdl_destroy.argtypes = [vp]
     lib.bdl_destroy.restype = None
@@ -106,7 +114,7 @@ def load_library(path: str = LIB_PATH):
     lib.bdl_debug_export_buffer.argtypes = [vp, u32p, f32p, i64p]
     lib.bdl_last_error.restype = ctypes.c_char_p
     for name in ("bdl_create", "bdl_insert", "bdl_erase", "bdl_knn", "bdl_clear", "bdl_sync",
-                 "bdl_profile", "bdl_level_sizes",
+                 "bdl_profile", "bdl_level_sizes", "bdl_set_param",
                  "bdl_level_info", "bdl_counters", "bdl_debug_export_level",
                  "bdl_debug_export_buffer"):
         getattr(lib, name).restype = ctypes.c_int
@@ -238,7 +246,13 @@ class Tree:
         """Per-phase device milliseconds and call counts (BDL_FLAG_PROFILE)."""
         p = Profile()
         _check(self._lib.bdl_profile(self._h, ctypes.byref(p), 1 if reset else 0))
-        return {name: {"ms": p.ms[i], "calls": p.calls[i]} for i, name in enumerate(PHASES)}
+        out = {name: {"ms": p.ms[i], "calls": p.calls[i]} for i, name in enumerate(PHASES)}
+        out["knn_work"] = {"nodes": p.knn_nodes, "leaves": p.knn_leaves, "points": p.knn_points}
+        return out
+
+    def set_param(self, param: int, value: int) -> None:
+        """Tuning knobs (PARAM_*); they change speed, never results."""
+        _check(self._lib.bdl_set_param(self._h, int(param), int(value)))
 
     def clear(self) -> None:
         """Remove every point; device memory is kept for reuse."""

@@ -43,23 +43,26 @@ __device__ inline float box_dist2(const float (&qq)[D], const float* box) {
   return acc;
 }
 
-// Insert c into the ascending array a (c < a[KMAX-1]); the largest key
-// falls off the end.  New a[j] = max(a[j-1], min(a[j], c)), a[0] = min(a[0], c).
+// Insert c into the ascending array a (c < a[KMAX-1], keys distinct); the
+// largest key falls off the end.  With g[j] = (a[j] > c), which is false
+// below the insertion point and true from it on:
+//   new a[j] = g[j-1] ? a[j-1] : (g[j] ? c : a[j]),  new a[0] = g[0] ? c : a[0].
+// All comparisons use the old values, so they issue back to back.
 template <int KMAX>
 __device__ inline void topk_insert(uint64_t (&a)[KMAX], uint64_t c) {
+  bool g[KMAX];
 #pragma unroll
-  for (int j = KMAX - 1; j > 0; --j) {
-    uint64_t lo = a[j] < c ? a[j] : c;
-    a[j] = a[j - 1] > lo ? a[j - 1] : lo;
-  }
-  a[0] = a[0] < c ? a[0] : c;
+  for (int j = 0; j < KMAX; ++j) g[j] = a[j] > c;
+#pragma unroll
+  for (int j = KMAX - 1; j > 0; --j) a[j] = g[j - 1] ? a[j - 1] : (g[j] ? c : a[j]);
+  a[0] = g[0] ? c : a[0];
 }
 
 template <int D, int KMAX>
 __global__ void __launch_bounds__(256)
 k_knn(const float* __restrict__ q, uint64_t nq, int k, const uint32_t* __restrict__ order,
       LevelViews views, uint32_t* __restrict__ out_ids, float* __restrict__ out_d2,
-      uint32_t* __restrict__ err) {
+      uint32_t* __restrict__ err, unsigned long long* __restrict__ stats) {
   constexpr int S = (D + 1 + 3) & ~3;
   constexpr int NS = (5 + 2 * D + 3) & ~3;
   constexpr int SV = S / 4;
@@ -75,6 +78,7 @@ k_knn(const float* __restrict__ q, uint64_t nq, int k, const uint32_t* __restric
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) key[j] = j < skip ? 0ull : kPadKey;
 
+  uint32_t c_nodes = 0, c_leaves = 0, c_points = 0;
   for (int v = 0; v < views.n; ++v) {
     const float4* __restrict__ nodes = reinterpret_cast<const float4*>(views.v[v].nodes);
     const float4* __restrict__ rec = reinterpret_cast<const float4*>(views.v[v].rec);
@@ -105,6 +109,7 @@ k_knn(const float* __restrict__ q, uint64_t nq, int k, const uint32_t* __restric
           f[4 * u + 3] = x.w;
         }
         const float worst = __uint_as_float((uint32_t)(key[KMAX - 1] >> 32));
+        ++c_nodes;
         if (box_dist2<D>(qq, f + NF_BOX) > worst) {
           up = true;
           continue;
@@ -117,6 +122,8 @@ k_knn(const float* __restrict__ q, uint64_t nq, int k, const uint32_t* __restric
             atomicOr(err, 2u);
             break;
           }
+          ++c_leaves;
+          c_points += (uint32_t)b;
           for (int sl = a; sl < a + b; ++sl) {
             float r[S];
 #pragma unroll
@@ -163,6 +170,199 @@ k_knn(const float* __restrict__ q, uint64_t nq, int k, const uint32_t* __restric
       }
     }
   }
+  if (stats) {
+    atomicAdd(&stats[0], (unsigned long long)c_nodes);
+    atomicAdd(&stats[1], (unsigned long long)c_leaves);
+    atomicAdd(&stats[2], (unsigned long long)c_points);
+  }
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) {
+    if (j >= skip) {
+      const uint64_t o = qi * (uint64_t)k + (uint64_t)(j - skip);
+      out_ids[o] = (uint32_t)key[j];
+      out_d2[o] = __uint_as_float((uint32_t)(key[j] >> 32));
+    }
+  }
+}
+
+// XCD-aware block order: gfx950 hands consecutive workgroups to its 8 XCDs
+// round robin, each with its own L2.  Remap so that XCD x runs one contiguous
+// range of the (Morton-ordered) query blocks; neighbouring waves then share
+// tree nodes in the same L2.
+__device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  const uint32_t x = b & 7u;
+  const uint32_t q = nb >> 3, r = nb & 7u;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+template <int NV>
+__device__ inline void load_node(const float4* __restrict__ nodes, int n, float (&f)[4 * NV]) {
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    float4 x = nodes[(uint64_t)n * NV + u];
+    f[4 * u + 0] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x.x)));
+    f[4 * u + 1] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x.y)));
+    f[4 * u + 2] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x.z)));
+    f[4 * u + 3] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x.w)));
+  }
+}
+
+// Wavefront-cooperative variant: the 64 lanes of a wave hold 64 queries that
+// are neighbours in Morton order and walk each tree together, depth first.
+// At an internal node both children are read at once and each is tested by a
+// ballot over the lanes' strict prune tests: a child is entered when ANY lane
+// may still find a neighbour in it.  The near child (the side of the split
+// where the majority of the wave's queries lie) is entered first; the far one
+// is pushed on a wave-uniform stack kept in one VGPR (entry i in lane i) and
+// tested again when popped.  Node and leaf data are read at wave-uniform
+// addresses (scalar loads for nodes, one coalesced load per leaf broadcast
+// with v_readlane); every lane keeps its own k best keys.  Entering extra
+// nodes never changes a lane's result.
+template <int D, int KMAX>
+__global__ void __launch_bounds__(256)
+k_knn_wave(const float* __restrict__ q, uint64_t nq, int k, const uint32_t* __restrict__ order,
+           LevelViews views, uint32_t* __restrict__ out_ids, float* __restrict__ out_d2,
+           uint32_t* __restrict__ err, unsigned long long* __restrict__ stats) {
+  constexpr int S = (D + 1 + 3) & ~3;
+  constexpr int NS = (5 + 2 * D + 3) & ~3;
+  constexpr int SV = S / 4;
+  constexpr int NV = NS / 4;
+  const uint64_t t = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const bool valid = t < nq;
+  const int lane = __lane_id();
+  const uint64_t qi = valid ? (order ? (uint64_t)order[t] : t) : 0;
+  float qq[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) qq[j] = valid ? q[qi * D + j] : 0.0f;
+  const int skip = KMAX - k;
+  uint64_t key[KMAX];
+  // a lane without a query never asks for a node: its keys are all 0, so no
+  // box distance is ever within its k-th distance
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) key[j] = (j < skip || !valid) ? 0ull : kPadKey;
+  const uint64_t vmask = __ballot(valid);
+  const int nvalid = __popcll(vmask);
+  if (nvalid == 0) return;
+  uint32_t c_nodes = 0, c_leaves = 0, c_points = 0;
+
+  auto wanted = [&](const float (&f)[NS]) -> bool {
+    const float worst = __uint_as_float((uint32_t)(key[KMAX - 1] >> 32));
+    return __ballot(valid && !(box_dist2<D>(qq, f + NF_BOX) > worst)) != 0ull;
+  };
+
+  for (int v = 0; v < views.n; ++v) {
+    const float4* __restrict__ nodes = reinterpret_cast<const float4*>(views.v[v].nodes);
+    const float4* __restrict__ rec = reinterpret_cast<const float4*>(views.v[v].rec);
+    const uint32_t nn = views.v[v].n_nodes;
+    const uint32_t ns = views.v[v].n_slots;
+    if (nn == 0) continue;
+    int stk = 0;  // lane i holds stack entry i
+    int sp = 0;
+    float cur[NS];
+    load_node<NV>(nodes, 0, cur);
+    ++c_nodes;
+    bool have = wanted(cur);
+    uint32_t steps_left = 2u * nn + 8u;
+    while (true) {
+      if (have) {
+        if (--steps_left == 0) {
+          if (lane == 0) atomicOr(err, 8u);
+          break;
+        }
+        const int dim = __float_as_int(cur[NF_DIM]);
+        const int a = __float_as_int(cur[NF_A]);
+        const int b = __float_as_int(cur[NF_B]);
+        if (dim < 0) {
+          if ((uint32_t)a > ns || (uint32_t)b > ns - (uint32_t)a) {
+            if (lane == 0) atomicOr(err, 2u);
+            break;
+          }
+          ++c_leaves;
+          c_points += (uint32_t)b;
+          // the leaf's records are read at wave-uniform addresses (scalar
+          // loads, four records per step) and used straight from SGPRs
+          const int end = a + b;
+          for (int sl = a; sl < end; sl += 4) {
+            float r[4][S];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int si = sl + i < end ? sl + i : sl;
+#pragma unroll
+              for (int u = 0; u < SV; ++u) {
+                float4 x = rec[(uint64_t)si * SV + u];
+                r[i][4 * u + 0] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x.x)));
+                r[i][4 * u + 1] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x.y)));
+                r[i][4 * u + 2] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x.z)));
+                r[i][4 * u + 3] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x.w)));
+              }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const uint32_t id = __float_as_uint(r[i][D]);
+              if (sl + i >= end || id == kTomb) continue;
+              float acc = 0.0f;
+#pragma unroll
+              for (int j = 0; j < D; ++j) {
+                float tt = qq[j] - r[i][j];
+                acc = __builtin_fmaf(tt, tt, acc);
+              }
+              const uint64_t ck = ((uint64_t)__float_as_uint(acc) << 32) | id;
+              if (ck < key[KMAX - 1]) topk_insert<KMAX>(key, ck);
+            }
+          }
+          have = false;
+        } else {
+          if ((uint32_t)a >= nn || (uint32_t)b >= nn) {
+            if (lane == 0) atomicOr(err, 1u);
+            break;
+          }
+          const uint64_t lv = __ballot(valid && select_dim<D>(qq, dim) < cur[NF_SPLIT]);
+          const bool left_first = 2 * __popcll(lv) >= nvalid;
+          float fa[NS], fb[NS];
+          load_node<NV>(nodes, a, fa);
+          load_node<NV>(nodes, b, fb);
+          c_nodes += 2;
+          const bool wa = wanted(fa);
+          const bool wb = wanted(fb);
+          const bool wn = left_first ? wa : wb;
+          const bool wf = left_first ? wb : wa;
+          if (wn && wf) {
+            if (sp >= 64) {
+              if (lane == 0) atomicOr(err, 16u);
+              break;
+            }
+            stk = lane == sp ? (left_first ? b : a) : stk;
+            ++sp;
+          }
+          if (wn || wf) {
+#pragma unroll
+            for (int u = 0; u < NS; ++u) cur[u] = (left_first == wn) ? fa[u] : fb[u];
+            have = true;
+          } else {
+            have = false;
+          }
+        }
+      } else {
+        if (sp == 0) break;
+        --sp;
+        const int n = __builtin_amdgcn_readlane(stk, sp);
+        if ((uint32_t)n >= nn) {
+          if (lane == 0) atomicOr(err, 4u);
+          break;
+        }
+        load_node<NV>(nodes, n, cur);
+        ++c_nodes;
+        have = wanted(cur);
+      }
+    }
+  }
+  // counts per lane with a query: wave-level work times the active lanes
+  if (stats && lane == 0) {
+    atomicAdd(&stats[0], (unsigned long long)c_nodes * nvalid);
+    atomicAdd(&stats[1], (unsigned long long)c_leaves * nvalid);
+    atomicAdd(&stats[2], (unsigned long long)c_points * nvalid);
+  }
+  if (!valid) return;
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) {
     if (j >= skip) {
@@ -243,22 +443,34 @@ __global__ void k_morton(const float* q, uint64_t nq, int d, const uint32_t* box
 }
 
 template <int D, int KMAX>
-void launch_one(int k, const float* q, uint64_t nq, const LevelViews& views,
+void launch_one(int mode, int k, const float* q, uint64_t nq, const LevelViews& views,
                 const uint32_t* order, uint32_t* out_ids, float* out_d2, uint32_t* err,
-                hipStream_t s) {
+                unsigned long long* stats, hipStream_t s) {
   const unsigned g = (unsigned)((nq + 255) / 256);
-  hipLaunchKernelGGL((k_knn<D, KMAX>), dim3(g), dim3(256), 0, s, q, nq, k, order, views,
-                     out_ids, out_d2, err);
+  if (mode == kKnnWave)
+    hipLaunchKernelGGL((k_knn_wave<D, KMAX>), dim3(g), dim3(256), 0, s, q, nq, k, order, views,
+                       out_ids, out_d2, err, stats);
+  else
+    hipLaunchKernelGGL((k_knn<D, KMAX>), dim3(g), dim3(256), 0, s, q, nq, k, order, views,
+                       out_ids, out_d2, err, stats);
 }
 
 template <int D>
-void launch_d(int k, const float* q, uint64_t nq, const LevelViews& views, const uint32_t* order,
-              uint32_t* out_ids, float* out_d2, uint32_t* err, hipStream_t s) {
-  if (k <= 4) launch_one<D, 4>(k, q, nq, views, order, out_ids, out_d2, err, s);
-  else if (k <= 8) launch_one<D, 8>(k, q, nq, views, order, out_ids, out_d2, err, s);
-  else if (k <= 16) launch_one<D, 16>(k, q, nq, views, order, out_ids, out_d2, err, s);
-  else if (k <= 32) launch_one<D, 32>(k, q, nq, views, order, out_ids, out_d2, err, s);
-  else launch_one<D, 64>(k, q, nq, views, order, out_ids, out_d2, err, s);
+void launch_d(int mode, int k, const float* q, uint64_t nq, const LevelViews& views,
+              const uint32_t* order, uint32_t* out_ids, float* out_d2, uint32_t* err,
+              unsigned long long* st, hipStream_t s) {
+  if (mode == kKnnWave) {
+    // register arrays sized to the common k exactly (no sentinel slots)
+    if (k == 1) return launch_one<D, 1>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
+    if (k == 2) return launch_one<D, 2>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
+    if (k == 5) return launch_one<D, 5>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
+    if (k == 10) return launch_one<D, 10>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
+  }
+  if (k <= 4) launch_one<D, 4>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
+  else if (k <= 8) launch_one<D, 8>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
+  else if (k <= 16) launch_one<D, 16>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
+  else if (k <= 32) launch_one<D, 32>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
+  else launch_one<D, 64>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
 }
 
 }  // namespace
@@ -283,13 +495,13 @@ const uint32_t* morton_order(int d, const float* q, uint64_t nq, QueryScratch& q
   return qs.vals[which];
 }
 
-int launch_knn(int d, int k, const float* q, uint64_t nq, const LevelViews& views,
+int launch_knn(int mode, int d, int k, const float* q, uint64_t nq, const LevelViews& views,
                const uint32_t* order, uint32_t* out_ids, float* out_d2, uint32_t* err,
-               hipStream_t s) {
+               unsigned long long* stats, hipStream_t s) {
   switch (d) {
 #define BDL_KNN_CASE(DD) \
   case DD:               \
-    launch_d<DD>(k, q, nq, views, order, out_ids, out_d2, err, s); \
+    launch_d<DD>(mode, k, q, nq, views, order, out_ids, out_d2, err, stats, s); \
     break;
     BDL_KNN_CASE(1) BDL_KNN_CASE(2) BDL_KNN_CASE(3) BDL_KNN_CASE(4)
     BDL_KNN_CASE(5) BDL_KNN_CASE(6) BDL_KNN_CASE(7) BDL_KNN_CASE(8)

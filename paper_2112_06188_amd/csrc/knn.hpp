@@ -21,10 +21,17 @@ constexpr uint64_t kSortQueriesMin = 4096;
 
 // kNN_L over the given trees (visited in the given order).  order may be
 // null (queries in input order).  Returns 0 or a BDL_E* code.
+// Traversal variants: one lane per query, or one wavefront per group of 64
+// neighbouring queries.
+constexpr int kKnnLane = 0;
+constexpr int kKnnWave = 1;
+
 // err (device) receives a nonzero bit if a tree index is out of range.
-int launch_knn(int d, int k, const float* q, uint64_t nq, const LevelViews& views,
+// stats (device, may be null) accumulates, per query, nodes entered, leaves
+// scanned and points whose distance was evaluated.
+int launch_knn(int mode, int d, int k, const float* q, uint64_t nq, const LevelViews& views,
                const uint32_t* order, uint32_t* out_ids, float* out_d2, uint32_t* err,
-               hipStream_t s);
+               unsigned long long* stats, hipStream_t s);
 
 // Compute a Morton order of the queries; returns the device array holding
 // the permutation (inside qs).

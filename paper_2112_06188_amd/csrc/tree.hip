@@ -58,12 +58,15 @@ struct bdl_tree {
   uint64_t* map = nullptr;
   uint32_t* d_live = nullptr;   // kMaxLevels
   uint32_t* d_misc = nullptr;   // erase counters [0..1], validation [4..6]
+  unsigned long long* d_stats = nullptr;  // k-NN work counters (profiling)
   uint32_t* h_pin = nullptr;    // pinned staging, kMaxLevels + 16 words
   BuildScratch sc;
   QueryScratch qs;
   float* rbuf = nullptr;        // Erase_L's gathered points R (records)
   int64_t rbuf_cap = 0;
   int64_t rebuilt = 0, reinserted = 0;
+  int knn_mode = kKnnWave;
+  uint64_t sort_min = kSortQueriesMin;
   size_t held = 0;
   std::unordered_map<void*, size_t> sizes;
   // phase timing (BDL_FLAG_PROFILE)
@@ -505,9 +508,10 @@ int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out) {
   t->map = (uint64_t*)dmalloc(t, (size_t)cfg->id_capacity * 8);
   t->d_live = (uint32_t*)dmalloc(t, kMaxLevels * 4);
   t->d_misc = (uint32_t*)dmalloc(t, 16 * 4);
+  t->d_stats = (unsigned long long*)dmalloc(t, 8 * 8);
   t->sc.ctr = (BuildCounters*)dmalloc(t, sizeof(BuildCounters));
   t->sc.jobs = (Job*)dmalloc(t, sizeof(Job) * kMaxJobs);
-  bool ok = t->map && t->d_live && t->d_misc && t->sc.ctr && t->sc.jobs;
+  bool ok = t->map && t->d_live && t->d_misc && t->d_stats && t->sc.ctr && t->sc.jobs;
   if (ok && hipHostMalloc((void**)&t->h_pin, (kMaxLevels + 16) * 4, hipHostMallocDefault) !=
                 hipSuccess)
     ok = false;
@@ -521,6 +525,7 @@ int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out) {
   launch_fill_u32((uint32_t*)t->map, 0xFFFFFFFFu, (uint64_t)cfg->id_capacity * 2, t->s);
   launch_fill_u32(t->d_live, 0u, kMaxLevels, t->s);
   launch_fill_u32(t->d_misc, 0u, 16, t->s);
+  launch_fill_u32((uint32_t*)t->d_stats, 0u, 16, t->s);
   if (hipStreamSynchronize(t->s) != hipSuccess) {
     bdl_destroy(t);
     return fail(BDL_EHIP, "stream synchronisation failed");
@@ -544,6 +549,22 @@ void bdl_destroy(bdl_tree* t) {
   delete t;
 }
 
+int bdl_set_param(bdl_tree* t, int32_t param, int64_t value) {
+  if (!t) return fail(BDL_EINVAL, "null tree");
+  switch (param) {
+    case BDL_PARAM_KNN_KERNEL:
+      if (value != kKnnLane && value != kKnnWave) return fail(BDL_EINVAL, "unknown k-NN kernel");
+      t->knn_mode = (int)value;
+      return 0;
+    case BDL_PARAM_SORT_MIN:
+      if (value < 1) return fail(BDL_EINVAL, "sort threshold must be >= 1");
+      t->sort_min = (uint64_t)value;
+      return 0;
+    default:
+      return fail(BDL_EINVAL, "unknown parameter");
+  }
+}
+
 int bdl_clear(bdl_tree* t) {
   if (!t) return fail(BDL_EINVAL, "null tree");
   for (int i = 0; i < kMaxLevels; ++i) {
@@ -565,17 +586,25 @@ int bdl_profile(bdl_tree* t, bdl_profile_t* out, int reset) {
   if (!t) return fail(BDL_EINVAL, "null tree");
   if (hipStreamSynchronize(t->s) != hipSuccess) return fail(BDL_EHIP, "stream error");
   resolve_events(t);
+  unsigned long long st[3] = {0, 0, 0};
+  if (hipMemcpy(st, t->d_stats, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(BDL_EHIP, "counter readback failed");
   if (out) {
     for (int i = 0; i < BDL_NPHASES; ++i) {
       out->ms[i] = t->prof_ms[i];
       out->calls[i] = t->prof_calls[i];
     }
+    out->knn_nodes = (int64_t)st[0];
+    out->knn_leaves = (int64_t)st[1];
+    out->knn_points = (int64_t)st[2];
   }
   if (reset) {
     for (int i = 0; i < BDL_NPHASES; ++i) {
       t->prof_ms[i] = 0.0;
       t->prof_calls[i] = 0;
     }
+    launch_fill_u32((uint32_t*)t->d_stats, 0u, 16, t->s);
+    (void)hipStreamSynchronize(t->s);
   }
   return 0;
 }
@@ -700,7 +729,7 @@ int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_id
   if (!q || !out_ids || !out_d2) return fail(BDL_EINVAL, "null query or output");
   if (nq >= (1ll << 32)) return fail(BDL_EINVAL, "query batch too large");
   const uint32_t* order = nullptr;
-  if ((uint64_t)nq >= kSortQueriesMin) {
+  if ((uint64_t)nq >= t->sort_min) {
     if (!ensure_query_scratch(t, (uint64_t)nq)) return fail(BDL_ENOMEM, "query scratch");
     t->pt.begin(BDL_PH_ORDER);
     order = morton_order(t->d, q, (uint64_t)nq, t->qs, t->s);
@@ -708,7 +737,8 @@ int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_id
   }
   LevelViews v = make_views(t);
   t->pt.begin(BDL_PH_TRAVERSE);
-  int rc = launch_knn(t->d, k, q, (uint64_t)nq, v, order, out_ids, out_d2, t->d_misc + 8, t->s);
+  int rc = launch_knn(t->knn_mode, t->d, k, q, (uint64_t)nq, v, order, out_ids, out_d2,
+                      t->d_misc + 8, t->pt.mark ? t->d_stats : nullptr, t->s);
   t->pt.end(BDL_PH_TRAVERSE);
   if (rc) return fail(rc, "k-NN launch failed");
   return 0;

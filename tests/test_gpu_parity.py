@@ -35,9 +35,14 @@ def bdl():
     return m
 
 
-def _pair(bdl, d, leaf, X, idcap=1 << 22, **kw):
-    return bdl.Tree(d, leaf_size=leaf, buffer_size=X, id_capacity=idcap, **kw), \
-        oracle.OracleBDL(d, leaf, X)
+def _pair(bdl, d, leaf, X, idcap=1 << 22, knn_kernel=None, **kw):
+    t = bdl.Tree(d, leaf_size=leaf, buffer_size=X, id_capacity=idcap, **kw)
+    if knn_kernel is not None:
+        t.set_param(bdl.PARAM_KNN_KERNEL, knn_kernel)
+    return t, oracle.OracleBDL(d, leaf, X)
+
+
+KERNELS = [0, 1]  # one lane per query; one wavefront per 64 queries
 
 
 def test_single_insert_small(torch, bdl):
@@ -49,12 +54,13 @@ def test_single_insert_small(torch, bdl):
                what="single")
 
 
+@pytest.mark.parametrize("kern", KERNELS)
 @pytest.mark.parametrize("X", [1024, 16])
-def test_uniform2d_small_workload(torch, bdl, X):
+def test_uniform2d_small_workload(torch, bdl, X, kern):
     """The 2D workload of 10x1000 inserts, 5x1000 erases and 1000 queries."""
-    log(f"case: uniform2d_small X={X}")
+    log(f"case: uniform2d_small X={X} kernel={kern}")
     w = workload("uniform2d_small", X=X)
-    t, o = _pair(bdl, w.dim, w.leaf_size, X)
+    t, o = _pair(bdl, w.dim, w.leaf_size, X, knn_kernel=kern)
     run_parity(t, o, w.ops, torch, w.dim, what=f"uniform2d X={X}")
 
 
@@ -70,12 +76,13 @@ def test_random_ops(torch, bdl, seed, d, X, leaf, clustered):
     run_parity(t, o, ops, torch, d, what=f"random seed={seed}")
 
 
+@pytest.mark.parametrize("kern", KERNELS)
 @pytest.mark.parametrize("d,n", [(3, 200_000), (2, 150_001), (7, 90_000), (16, 40_000)])
-def test_large_levels_use_global_passes(torch, bdl, d, n):
+def test_large_levels_use_global_passes(torch, bdl, d, n, kern):
     """Trees larger than the LDS finisher go through the per-depth global
     passes (several 4096-point tiles per node) before the finisher."""
-    log(f"case: large level d={d} n={n}")
-    t, o = _pair(bdl, d, 16, 1024)
+    log(f"case: large level d={d} n={n} kernel={kern}")
+    t, o = _pair(bdl, d, 16, 1024, knn_kernel=kern)
     p = uniform_points(n, d, 10 + d)
     ids = (np.arange(n, dtype=np.uint32) * 7 + 3)
     ops = [Op("insert", p[: n // 3], ids[: n // 3]), Op("insert", p[n // 3:], ids[n // 3:]),
@@ -84,6 +91,21 @@ def test_large_levels_use_global_passes(torch, bdl, d, n):
     ops.append(Op("erase", p[e], ids[e]))
     ops.append(Op("knn", uniform_points(5000, d, 21), k=5))
     run_parity(t, o, ops, torch, d, what=f"large d={d}")
+
+
+def test_unsorted_small_batches_both_kernels(torch, bdl):
+    """Batches below the Morton-order threshold run in input order; a batch
+    whose size is not a multiple of the wavefront leaves idle lanes."""
+    log("case: small unsorted batches")
+    d = 3
+    for kern in KERNELS:
+        t, o = _pair(bdl, d, 8, 32, knn_kernel=kern)
+        p = uniform_points(3000, d, 40)
+        ids = np.arange(3000, dtype=np.uint32)
+        ops = [Op("insert", p, ids)]
+        for nq in (1, 63, 65, 200, 4095, 4097):
+            ops.append(Op("knn", uniform_points(nq, d, 41 + nq), k=6))
+        run_parity(t, o, ops, torch, d, check_structure=False, what=f"small kern={kern}")
 
 
 def test_coincident_points_larger_than_finisher(torch, bdl):
@@ -122,11 +144,12 @@ def test_deep_trees_and_depth_cap(torch, bdl):
     assert max(heights) == 63
 
 
+@pytest.mark.parametrize("kern", KERNELS)
 @pytest.mark.parametrize("k", [1, 2, 5, 10, 16, 17, 33, 64])
-def test_knn_k_range(torch, bdl, k):
-    log(f"case: k={k}")
+def test_knn_k_range(torch, bdl, k, kern):
+    log(f"case: k={k} kernel={kern}")
     d = 3
-    t, o = _pair(bdl, d, 16, 64)
+    t, o = _pair(bdl, d, 16, 64, knn_kernel=kern)
     p = uniform_points(5000, d, 30)
     ids = np.arange(5000, dtype=np.uint32)
     run_parity(t, o, [Op("insert", p, ids), Op("knn", uniform_points(6000, d, 31), k=k)], torch,
