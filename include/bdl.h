@@ -109,6 +109,9 @@ int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_id
                                   64 neighbouring queries (default) */
 #define BDL_PARAM_SORT_MIN 2   /* query batches of at least this many queries
                                   are visited in Morton order (default 4096) */
+#define BDL_PARAM_KNN_BLOCK 3  /* k-NN workgroup size: 64, 128 or 256 (default) */
+#define BDL_PARAM_USE_GRAPHS 4 /* 1 (default): bdl_knn_batch replays captured
+                                  hipGraphs; 0: it launches eagerly */
 int bdl_set_param(bdl_tree* t, int32_t param, int64_t value);
 
 /* Remove every point.  Device memory stays allocated for reuse; the tree
@@ -128,6 +131,26 @@ typedef struct {
   int64_t knn_nodes, knn_leaves, knn_points;
 } bdl_profile_t;
 int bdl_profile(bdl_tree* t, bdl_profile_t* out, int reset);
+
+/* One request of a batched k-NN call (device pointers, as in bdl_knn). */
+typedef struct {
+  const float* q;     /* [nq][dim] */
+  int64_t nq;
+  int32_t k;          /* 1..BDL_MAX_K */
+  int32_t pad_;
+  uint32_t* out_ids;  /* [nq][k] */
+  float* out_d2;      /* [nq][k] */
+} bdl_knn_request;
+
+/* Batched form of kNN_L: the requests' results are those bdl_knn would give
+ * for each request in turn (no update runs in between), but all requests run
+ * in one launch sequence: their queries are concatenated, ordered jointly,
+ * and traversed by one kernel in which every query carries its own k and
+ * output location.  With BDL_PARAM_USE_GRAPHS (default on) the sequence is
+ * captured once per size bucket (a power of two of at least 4096 queries)
+ * and replayed as a hipGraph.  Asynchronous; reqs is a host array that may
+ * be reused once the call returns. */
+int bdl_knn_batch(bdl_tree* t, const bdl_knn_request* reqs, int32_t nreq);
 
 /* Block until all work enqueued on the tree's stream has finished.  Returns
  * BDL_EHIP if a k-NN traversal since the last call met an out-of-range tree

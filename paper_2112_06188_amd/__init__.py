@@ -31,11 +31,13 @@ EXPORTS = [
     "bdl_create", "bdl_insert", "bdl_erase", "bdl_knn", "bdl_clear", "bdl_sync", "bdl_destroy",
     "bdl_size", "bdl_level_info", "bdl_counters", "bdl_debug_export_level",
     "bdl_debug_export_buffer", "bdl_last_error", "bdl_profile", "bdl_level_sizes",
-    "bdl_set_param",
+    "bdl_set_param", "bdl_knn_batch",
 ]
 FLAG_PROFILE = 2
 PARAM_KNN_KERNEL = 1
 PARAM_SORT_MIN = 2
+PARAM_KNN_BLOCK = 3
+PARAM_USE_GRAPHS = 4
 KNN_LANE = 0
 KNN_WAVE = 1
 PHASES = ["gather", "passes", "finish", "layout", "erase", "order", "traverse", "other"]
@@ -60,6 +62,12 @@ NODE_DTYPE = np.dtype([
     ("pad_", np.int32),
     ("path", np.uint64),
 ], align=True)
+
+
+class KnnRequest(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_void_p), ("nq", ctypes.c_int64), ("k", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("out_ids", ctypes.c_void_p),
+                ("out_d2", ctypes.c_void_p)]
 
 
 class BdlError(RuntimeError):
@@ -101,6 +109,7 @@ def load_library(path: str = LIB_PATH):
     lib.bdl_sync.argtypes = [vp]
     lib.bdl_clear.argtypes = [vp]
     lib.bdl_set_param.argtypes = [vp, i32, i64]
+    lib.bdl_knn_batch.argtypes = [vp, ctypes.POINTER(KnnRequest), i32]
     lib.bdl_profile.argtypes = [vp, ctypes.POINTER(Profile), ctypes.c_int]
     lib.bdl_destroy.argtypes = [vp]
     lib.bdl_destroy.restype = None
@@ -114,7 +123,7 @@ def load_library(path: str = LIB_PATH):
     lib.bdl_debug_export_buffer.argtypes = [vp, u32p, f32p, i64p]
     lib.bdl_last_error.restype = ctypes.c_char_p
     for name in ("bdl_create", "bdl_insert", "bdl_erase", "bdl_knn", "bdl_clear", "bdl_sync",
-                 "bdl_profile", "bdl_level_sizes", "bdl_set_param",
+                 "bdl_profile", "bdl_level_sizes", "bdl_set_param", "bdl_knn_batch",
                  "bdl_level_info", "bdl_counters", "bdl_debug_export_level",
                  "bdl_debug_export_buffer"):
         getattr(lib, name).restype = ctypes.c_int
@@ -238,6 +247,29 @@ class Tree:
                                      ctypes.c_void_p(out_ids.data_ptr()),
                                      ctypes.c_void_p(out_d2.data_ptr())))
         return out_ids, out_d2
+
+    def knn_batch(self, requests, outputs=None):
+        """Batched kNN_L: requests is a list of (queries, k); returns a list of
+        (ids, d2) pairs, the same as knn() on each request in turn."""
+        torch = _torch()
+        reqs = (KnnRequest * max(1, len(requests)))()
+        keep = []
+        outs = []
+        for i, (q, k) in enumerate(requests):
+            qq = self._pts(q, "q")
+            nq = qq.shape[0]
+            if outputs is not None:
+                oi, od = outputs[i]
+            else:
+                oi = torch.empty((nq, k), dtype=torch.int32, device=self.device)
+                od = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+            keep.append(qq)
+            outs.append((oi, od))
+            reqs[i] = KnnRequest(qq.data_ptr(), nq, int(k), 0, oi.data_ptr(), od.data_ptr())
+        with torch.cuda.device(self.device):
+            _check(self._lib.bdl_knn_batch(self._h, reqs, len(requests)))
+        self._keep = keep  # queries stay alive until the stream passes them
+        return outs
 
     def sync(self) -> None:
         _check(self._lib.bdl_sync(self._h))

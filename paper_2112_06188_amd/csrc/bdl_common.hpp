@@ -29,6 +29,9 @@ constexpr uint32_t kBufferLevel = 63;  // map entries of buffered points
 constexpr int kTile = 4096;            // points per tile of a global pass
 constexpr int kPassThreads = 256;
 constexpr int kItems = kTile / kPassThreads;
+// spare records after every record array: the k-NN kernel reads leaves in
+// groups of four records and may read up to three past a leaf's end
+constexpr int kRecPad = 4;
 
 __host__ __device__ inline int rec_stride(int d) { return (d + 1 + 3) & ~3; }
 __host__ __device__ inline int node_stride(int d) { return (5 + 2 * d + 3) & ~3; }
@@ -169,6 +172,7 @@ struct LevelView {
 };
 
 constexpr int kMaxViews = kMaxLevels + 1;
+constexpr int kMaxBatchReqs = 65536;  // requests per batched k-NN launch
 struct LevelViews {
   int32_t n;
   int32_t pad_;

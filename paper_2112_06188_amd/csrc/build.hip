@@ -993,6 +993,12 @@ __global__ void k_store_vals(uint32_t* dst, U32x64 vals, int n) {
   if ((int)threadIdx.x < n) dst[threadIdx.x] = vals.v[threadIdx.x];
 }
 
+__global__ void k_store_views(LevelViews* dst, LevelViews v) {
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(&v);
+  uint32_t* out = reinterpret_cast<uint32_t*>(dst);
+  for (uint32_t i = threadIdx.x; i < sizeof(LevelViews) / 4; i += blockDim.x) out[i] = src[i];
+}
+
 __global__ void k_fill(uint32_t* dst, uint32_t v, uint64_t n) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x)
@@ -1084,6 +1090,10 @@ void launch_store_u32(uint32_t* dst, const uint32_t* vals, int n, hipStream_t s)
   hipLaunchKernelGGL(k_store_vals, dim3(1), dim3(64), 0, s, dst, v, n);
 }
 
+void launch_store_views(LevelViews* dst, const LevelViews& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_store_views, dim3(1), dim3(256), 0, s, dst, v);
+}
+
 void launch_fill_u32(uint32_t* dst, uint32_t v, uint64_t n, hipStream_t s) {
   if (!n) return;
   hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, v, n);
@@ -1122,7 +1132,9 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
   int depth = 0;
   int budget = 1;
   while (((uint64_t)T << budget) < maxcount && budget < 40) ++budget;
-  budget += 3;
+  // spatial-median splits of real data are not exactly balanced: allow a
+  // few depths beyond log2(n / T) before the first readback
+  budget += 5;
   const unsigned pass_grid = grid_for(R, kTile, 2048);
   while (true) {
     for (int b = 0; b < budget; ++b, ++depth) {

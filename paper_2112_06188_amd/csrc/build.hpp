@@ -63,5 +63,6 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
 // small utilities
 void launch_store_u32(uint32_t* dst, const uint32_t* vals, int n, hipStream_t s);
 void launch_fill_u32(uint32_t* dst, uint32_t v, uint64_t n, hipStream_t s);
+void launch_store_views(LevelViews* dst, const LevelViews& v, hipStream_t s);
 
 }  // namespace bdl

@@ -60,30 +60,35 @@ __device__ inline void topk_insert(uint64_t (&a)[KMAX], uint64_t c) {
 
 template <int D, int KMAX>
 __global__ void __launch_bounds__(256)
-k_knn(const float* __restrict__ q, uint64_t nq, int k, const uint32_t* __restrict__ order,
-      LevelViews views, uint32_t* __restrict__ out_ids, float* __restrict__ out_d2,
+k_knn(KnnQueries Q, const uint32_t* __restrict__ order, const LevelViews* __restrict__ views,
       uint32_t* __restrict__ err, unsigned long long* __restrict__ stats) {
   constexpr int S = (D + 1 + 3) & ~3;
   constexpr int NS = (5 + 2 * D + 3) & ~3;
   constexpr int SV = S / 4;
   constexpr int NV = NS / 4;
+  const uint64_t nq = Q.nq_dev ? *Q.nq_dev : Q.nq;
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nq) return;
-  const uint64_t qi = order ? (uint64_t)order[t] : t;
+  const uint64_t gi = order ? (uint64_t)order[t] : t;
+  // the request's output location is read after the traversal
+  const uint32_t rq = Q.qreq ? Q.qreq[gi] : 0u;
+  const int k = Q.qreq ? Q.reqs[rq].k : Q.one.k;
   float qq[D];
 #pragma unroll
-  for (int j = 0; j < D; ++j) qq[j] = q[qi * D + j];
+  for (int j = 0; j < D; ++j) qq[j] = Q.q[gi * D + j];
   const int skip = KMAX - k;
   uint64_t key[KMAX];
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) key[j] = j < skip ? 0ull : kPadKey;
 
   uint32_t c_nodes = 0, c_leaves = 0, c_points = 0;
-  for (int v = 0; v < views.n; ++v) {
-    const float4* __restrict__ nodes = reinterpret_cast<const float4*>(views.v[v].nodes);
-    const float4* __restrict__ rec = reinterpret_cast<const float4*>(views.v[v].rec);
-    const uint32_t nn = views.v[v].n_nodes;
-    const uint32_t ns = views.v[v].n_slots;
+  const int nviews = views->n;
+  for (int v = 0; v < nviews; ++v) {
+    const LevelView V = views->v[v];
+    const float4* __restrict__ nodes = reinterpret_cast<const float4*>(V.nodes);
+    const float4* __restrict__ rec = reinterpret_cast<const float4*>(V.rec);
+    const uint32_t nn = V.n_nodes;
+    const uint32_t ns = V.n_slots;
     int n = 0;
     bool up = false;
     // every node is entered once and left once; a longer walk means corrupt
@@ -175,12 +180,14 @@ k_knn(const float* __restrict__ q, uint64_t nq, int k, const uint32_t* __restric
     atomicAdd(&stats[1], (unsigned long long)c_leaves);
     atomicAdd(&stats[2], (unsigned long long)c_points);
   }
+  const KnnReqDev R = Q.qreq ? Q.reqs[rq] : Q.one;
+  const uint64_t qi = gi - R.qoff;
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) {
     if (j >= skip) {
       const uint64_t o = qi * (uint64_t)k + (uint64_t)(j - skip);
-      out_ids[o] = (uint32_t)key[j];
-      out_d2[o] = __uint_as_float((uint32_t)(key[j] >> 32));
+      R.out_ids[o] = (uint32_t)key[j];
+      R.out_d2[o] = __uint_as_float((uint32_t)(key[j] >> 32));
     }
   }
 }
@@ -195,15 +202,24 @@ __device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb) {
   return x * q + (x < r ? x : r) + (b >> 3);
 }
 
+// A pointer into the constant address space.  The tree does not change
+// during a k-NN launch, so its nodes and records may be read through such a
+// pointer; a load at a wave-uniform address through it is a scalar load whose
+// result lands in SGPRs.
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) vf4* cvf4_ptr;
+
+__device__ inline cvf4_ptr as_cvf4(const float* p) { return (cvf4_ptr)(p); }
+
 template <int NV>
-__device__ inline void load_node(const float4* __restrict__ nodes, int n, float (&f)[4 * NV]) {
+__device__ inline void load_node(cvf4_ptr nodes, int n, float (&f)[4 * NV]) {
 #pragma unroll
   for (int u = 0; u < NV; ++u) {
-    float4 x = nodes[(uint64_t)n * NV + u];
-    f[4 * u + 0] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x.x)));
-    f[4 * u + 1] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x.y)));
-    f[4 * u + 2] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x.z)));
-    f[4 * u + 3] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x.w)));
+    const vf4 x = nodes[(uint64_t)n * NV + u];
+    f[4 * u + 0] = x.x;
+    f[4 * u + 1] = x.y;
+    f[4 * u + 2] = x.z;
+    f[4 * u + 3] = x.w;
   }
 }
 
@@ -220,20 +236,25 @@ __device__ inline void load_node(const float4* __restrict__ nodes, int n, float 
 // nodes never changes a lane's result.
 template <int D, int KMAX>
 __global__ void __launch_bounds__(256)
-k_knn_wave(const float* __restrict__ q, uint64_t nq, int k, const uint32_t* __restrict__ order,
-           LevelViews views, uint32_t* __restrict__ out_ids, float* __restrict__ out_d2,
-           uint32_t* __restrict__ err, unsigned long long* __restrict__ stats) {
+k_knn_wave(KnnQueries Q, const uint32_t* __restrict__ order,
+           const LevelViews* __restrict__ views, uint32_t* __restrict__ err,
+           unsigned long long* __restrict__ stats) {
   constexpr int S = (D + 1 + 3) & ~3;
   constexpr int NS = (5 + 2 * D + 3) & ~3;
   constexpr int SV = S / 4;
   constexpr int NV = NS / 4;
+  const uint64_t nq = Q.nq_dev ? *Q.nq_dev : Q.nq;
   const uint64_t t = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool valid = t < nq;
   const int lane = __lane_id();
-  const uint64_t qi = valid ? (order ? (uint64_t)order[t] : t) : 0;
+  const uint64_t gi = valid ? (order ? (uint64_t)order[t] : t) : 0;
+  // only k is needed during the traversal; the request's output location is
+  // read afterwards, so that it does not occupy registers meanwhile
+  const uint32_t rq = (valid && Q.qreq) ? Q.qreq[gi] : 0u;
+  const int k = !valid ? KMAX : (Q.qreq ? Q.reqs[rq].k : Q.one.k);
   float qq[D];
 #pragma unroll
-  for (int j = 0; j < D; ++j) qq[j] = valid ? q[qi * D + j] : 0.0f;
+  for (int j = 0; j < D; ++j) qq[j] = valid ? Q.q[gi * D + j] : 0.0f;
   const int skip = KMAX - k;
   uint64_t key[KMAX];
   // a lane without a query never asks for a node: its keys are all 0, so no
@@ -250,11 +271,13 @@ k_knn_wave(const float* __restrict__ q, uint64_t nq, int k, const uint32_t* __re
     return __ballot(valid && !(box_dist2<D>(qq, f + NF_BOX) > worst)) != 0ull;
   };
 
-  for (int v = 0; v < views.n; ++v) {
-    const float4* __restrict__ nodes = reinterpret_cast<const float4*>(views.v[v].nodes);
-    const float4* __restrict__ rec = reinterpret_cast<const float4*>(views.v[v].rec);
-    const uint32_t nn = views.v[v].n_nodes;
-    const uint32_t ns = views.v[v].n_slots;
+  const int nviews = views->n;
+  for (int v = 0; v < nviews; ++v) {
+    const LevelView V = views->v[v];
+    const cvf4_ptr nodes = as_cvf4(V.nodes);
+    const cvf4_ptr rec = as_cvf4(V.rec);
+    const uint32_t nn = V.n_nodes;
+    const uint32_t ns = V.n_slots;
     if (nn == 0) continue;
     int stk = 0;  // lane i holds stack entry i
     int sp = 0;
@@ -289,11 +312,11 @@ k_knn_wave(const float* __restrict__ q, uint64_t nq, int k, const uint32_t* __re
               const int si = sl + i < end ? sl + i : sl;
 #pragma unroll
               for (int u = 0; u < SV; ++u) {
-                float4 x = rec[(uint64_t)si * SV + u];
-                r[i][4 * u + 0] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x.x)));
-                r[i][4 * u + 1] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x.y)));
-                r[i][4 * u + 2] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x.z)));
-                r[i][4 * u + 3] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x.w)));
+                const vf4 x = rec[(uint64_t)si * SV + u];
+                r[i][4 * u + 0] = x.x;
+                r[i][4 * u + 1] = x.y;
+                r[i][4 * u + 2] = x.z;
+                r[i][4 * u + 3] = x.w;
               }
             }
 #pragma unroll
@@ -363,12 +386,14 @@ k_knn_wave(const float* __restrict__ q, uint64_t nq, int k, const uint32_t* __re
     atomicAdd(&stats[2], (unsigned long long)c_points * nvalid);
   }
   if (!valid) return;
+  const KnnReqDev R = Q.qreq ? Q.reqs[rq] : Q.one;
+  const uint64_t qi = gi - R.qoff;
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) {
     if (j >= skip) {
       const uint64_t o = qi * (uint64_t)k + (uint64_t)(j - skip);
-      out_ids[o] = (uint32_t)key[j];
-      out_d2[o] = __uint_as_float((uint32_t)(key[j] >> 32));
+      R.out_ids[o] = (uint32_t)key[j];
+      R.out_d2[o] = __uint_as_float((uint32_t)(key[j] >> 32));
     }
   }
 }
@@ -382,8 +407,9 @@ __global__ void k_query_box_init(uint32_t* box) {
 }
 
 __global__ void __launch_bounds__(256)
-k_query_box(const float* q, uint64_t nq, int d, uint32_t* box) {
+k_query_box(const float* q, const uint64_t* nq_dev, uint64_t nq_host, int d, uint32_t* box) {
   __shared__ uint32_t red[8];
+  const uint64_t nq = nq_dev ? *nq_dev : nq_host;
   const int lane = __lane_id();
   const int w = threadIdx.x >> 6;
   for (int j = 0; j < d; ++j) {
@@ -418,13 +444,20 @@ k_query_box(const float* q, uint64_t nq, int d, uint32_t* box) {
   }
 }
 
-// Morton key with bits = floor(30 / d) bits per dimension.
-__global__ void k_morton(const float* q, uint64_t nq, int d, const uint32_t* box, uint32_t* keys,
-                         uint32_t* vals) {
+// Morton key with bits = floor(30 / d) bits per dimension; positions from nq
+// up to cap get the key 0xFFFFFFFF, which sorts after every real key.
+__global__ void k_morton(const float* q, const uint64_t* nq_dev, uint64_t nq_host, uint64_t cap,
+                         int d, const uint32_t* box, uint32_t* keys, uint32_t* vals) {
+  const uint64_t nq = nq_dev ? *nq_dev : nq_host;
   const int bits = 30 / d > 0 ? 30 / d : 1;
   const float cells = (float)(1u << bits);
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap;
        i += (uint64_t)gridDim.x * blockDim.x) {
+    vals[i] = (uint32_t)i;
+    if (i >= nq) {
+      keys[i] = 0xFFFFFFFFu;
+      continue;
+    }
     uint32_t cell[kMaxDim];
     for (int j = 0; j < d; ++j) {
       float lo = o2f(box[j]), hi = o2f(box[kMaxDim + j]);
@@ -438,39 +471,58 @@ __global__ void k_morton(const float* q, uint64_t nq, int d, const uint32_t* box
     for (int b = bits - 1; b >= 0; --b)
       for (int j = 0; j < d; ++j) key = (key << 1) | ((cell[j] >> b) & 1u);
     keys[i] = key;
-    vals[i] = (uint32_t)i;
+  }
+}
+
+// Concatenate the queries of a request table into one array and record the
+// request of every query (binary search over the requests' offsets).
+__global__ void k_gather_queries(const KnnReqDev* reqs, const uint64_t* counts, int d,
+                                 float* qall, uint32_t* qreq) {
+  const uint64_t nq = counts[0];
+  const uint32_t nreq = (uint32_t)counts[1];
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+      uint32_t mid = (lo + hi + 1) >> 1;
+      if (reqs[mid].qoff <= i) lo = mid; else hi = mid - 1;
+    }
+    const KnnReqDev& R = reqs[lo];
+    const uint64_t li = i - R.qoff;
+    for (int j = 0; j < d; ++j) qall[i * d + j] = R.q[li * d + j];
+    qreq[i] = lo;
   }
 }
 
 template <int D, int KMAX>
-void launch_one(int mode, int k, const float* q, uint64_t nq, const LevelViews& views,
-                const uint32_t* order, uint32_t* out_ids, float* out_d2, uint32_t* err,
-                unsigned long long* stats, hipStream_t s) {
-  const unsigned g = (unsigned)((nq + 255) / 256);
-  if (mode == kKnnWave)
-    hipLaunchKernelGGL((k_knn_wave<D, KMAX>), dim3(g), dim3(256), 0, s, q, nq, k, order, views,
-                       out_ids, out_d2, err, stats);
+void launch_one(const KnnLaunch& L, const KnnQueries& Q, uint64_t grid_q, const uint32_t* order,
+                const LevelViews* views, uint32_t* err, unsigned long long* stats,
+                hipStream_t s) {
+  const int bs = L.block;
+  const unsigned g = (unsigned)((grid_q + bs - 1) / bs);
+  if (L.mode == kKnnWave)
+    hipLaunchKernelGGL((k_knn_wave<D, KMAX>), dim3(g), dim3(bs), 0, s, Q, order, views, err,
+                       stats);
   else
-    hipLaunchKernelGGL((k_knn<D, KMAX>), dim3(g), dim3(256), 0, s, q, nq, k, order, views,
-                       out_ids, out_d2, err, stats);
+    hipLaunchKernelGGL((k_knn<D, KMAX>), dim3(g), dim3(bs), 0, s, Q, order, views, err, stats);
 }
 
 template <int D>
-void launch_d(int mode, int k, const float* q, uint64_t nq, const LevelViews& views,
-              const uint32_t* order, uint32_t* out_ids, float* out_d2, uint32_t* err,
+void launch_d(const KnnLaunch& L, int kmax, const KnnQueries& Q, uint64_t grid_q,
+              const uint32_t* order, const LevelViews* views, uint32_t* err,
               unsigned long long* st, hipStream_t s) {
-  if (mode == kKnnWave) {
+  if (L.mode == kKnnWave) {
     // register arrays sized to the common k exactly (no sentinel slots)
-    if (k == 1) return launch_one<D, 1>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
-    if (k == 2) return launch_one<D, 2>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
-    if (k == 5) return launch_one<D, 5>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
-    if (k == 10) return launch_one<D, 10>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
+    if (kmax == 1) return launch_one<D, 1>(L, Q, grid_q, order, views, err, st, s);
+    if (kmax == 2) return launch_one<D, 2>(L, Q, grid_q, order, views, err, st, s);
+    if (kmax == 5) return launch_one<D, 5>(L, Q, grid_q, order, views, err, st, s);
+    if (kmax == 10) return launch_one<D, 10>(L, Q, grid_q, order, views, err, st, s);
   }
-  if (k <= 4) launch_one<D, 4>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
-  else if (k <= 8) launch_one<D, 8>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
-  else if (k <= 16) launch_one<D, 16>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
-  else if (k <= 32) launch_one<D, 32>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
-  else launch_one<D, 64>(mode, k, q, nq, views, order, out_ids, out_d2, err, st, s);
+  if (kmax <= 4) launch_one<D, 4>(L, Q, grid_q, order, views, err, st, s);
+  else if (kmax <= 8) launch_one<D, 8>(L, Q, grid_q, order, views, err, st, s);
+  else if (kmax <= 16) launch_one<D, 16>(L, Q, grid_q, order, views, err, st, s);
+  else if (kmax <= 32) launch_one<D, 32>(L, Q, grid_q, order, views, err, st, s);
+  else launch_one<D, 64>(L, Q, grid_q, order, views, err, st, s);
 }
 
 }  // namespace
@@ -479,29 +531,36 @@ size_t query_scratch_bytes(uint64_t cap) {
   return 4 * (size_t)cap * 4 + radix_tmp_words(cap) * 4 + 2 * kMaxDim * 4;
 }
 
-const uint32_t* morton_order(int d, const float* q, uint64_t nq, QueryScratch& qs,
-                             hipStream_t s) {
+const uint32_t* morton_order(int d, const float* q, const uint64_t* nq_dev, uint64_t nq_host,
+                             uint64_t cap, QueryScratch& qs, hipStream_t s) {
   hipLaunchKernelGGL(k_query_box_init, dim3(1), dim3(64), 0, s, qs.box);
-  unsigned g = (unsigned)((nq + 255) / 256);
+  unsigned g = (unsigned)((cap + 255) / 256);
   if (g > 1024) g = 1024;
-  hipLaunchKernelGGL(k_query_box, dim3(g), dim3(256), 0, s, q, nq, d, qs.box);
-  unsigned g2 = (unsigned)((nq + 255) / 256);
+  hipLaunchKernelGGL(k_query_box, dim3(g), dim3(256), 0, s, q, nq_dev, nq_host, d, qs.box);
+  unsigned g2 = (unsigned)((cap + 255) / 256);
   if (g2 > 4096) g2 = 4096;
-  hipLaunchKernelGGL(k_morton, dim3(g2), dim3(256), 0, s, q, nq, d, qs.box, qs.keys[0],
-                     qs.vals[0]);
+  hipLaunchKernelGGL(k_morton, dim3(g2), dim3(256), 0, s, q, nq_dev, nq_host, cap, d, qs.box,
+                     qs.keys[0], qs.vals[0]);
   const int bits = (30 / d > 0 ? 30 / d : 1) * d;
-  int which = radix_sort_pairs_u32(qs.keys[0], qs.vals[0], qs.keys[1], qs.vals[1], nq, 0, bits,
+  int which = radix_sort_pairs_u32(qs.keys[0], qs.vals[0], qs.keys[1], qs.vals[1], cap, 0, bits,
                                    qs.tmp, s);
   return qs.vals[which];
 }
 
-int launch_knn(int mode, int d, int k, const float* q, uint64_t nq, const LevelViews& views,
-               const uint32_t* order, uint32_t* out_ids, float* out_d2, uint32_t* err,
+void launch_gather_queries(const KnnReqDev* reqs, const uint64_t* counts, uint64_t cap, int d,
+                           float* qall, uint32_t* qreq, hipStream_t s) {
+  unsigned g = (unsigned)((cap + 255) / 256);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_gather_queries, dim3(g), dim3(256), 0, s, reqs, counts, d, qall, qreq);
+}
+
+int launch_knn(const KnnLaunch& L, int d, int kmax, const KnnQueries& Q, uint64_t grid_q,
+               const uint32_t* order, const LevelViews* views, uint32_t* err,
                unsigned long long* stats, hipStream_t s) {
   switch (d) {
 #define BDL_KNN_CASE(DD) \
   case DD:               \
-    launch_d<DD>(mode, k, q, nq, views, order, out_ids, out_d2, err, stats, s); \
+    launch_d<DD>(L, kmax, Q, grid_q, order, views, err, stats, s); \
     break;
     BDL_KNN_CASE(1) BDL_KNN_CASE(2) BDL_KNN_CASE(3) BDL_KNN_CASE(4)
     BDL_KNN_CASE(5) BDL_KNN_CASE(6) BDL_KNN_CASE(7) BDL_KNN_CASE(8)

@@ -19,23 +19,58 @@ size_t query_scratch_bytes(uint64_t cap);
 // Batches of at least this many queries are visited in Morton order.
 constexpr uint64_t kSortQueriesMin = 4096;
 
-// kNN_L over the given trees (visited in the given order).  order may be
-// null (queries in input order).  Returns 0 or a BDL_E* code.
 // Traversal variants: one lane per query, or one wavefront per group of 64
 // neighbouring queries.
 constexpr int kKnnLane = 0;
 constexpr int kKnnWave = 1;
 
-// err (device) receives a nonzero bit if a tree index is out of range.
-// stats (device, may be null) accumulates, per query, nodes entered, leaves
-// scanned and points whose distance was evaluated.
-int launch_knn(int mode, int d, int k, const float* q, uint64_t nq, const LevelViews& views,
-               const uint32_t* order, uint32_t* out_ids, float* out_d2, uint32_t* err,
+// One k-NN request as the kernels see it: its queries, k and outputs, and
+// the position of its first query in the concatenated query array.
+struct KnnReqDev {
+  const float* q;
+  uint32_t* out_ids;
+  float* out_d2;
+  uint64_t qoff;
+  uint32_t nq;
+  int32_t k;
+};
+
+// A set of queries: q holds all of them contiguously ([nq][d]).  When qreq
+// is null every query belongs to `one`; otherwise qreq[i] indexes reqs.  The
+// count is read from nq_dev when it is not null (graph replays).
+struct KnnQueries {
+  const float* q;
+  const uint64_t* nq_dev;
+  uint64_t nq;
+  const uint32_t* qreq;
+  const KnnReqDev* reqs;
+  KnnReqDev one;
+};
+
+// Kernel choice and workgroup size (64, 128 or 256).
+struct KnnLaunch {
+  int mode;
+  int block;
+};
+
+// kNN_L over the trees listed in `views` (device memory, visited in order).
+// grid_q bounds the number of queries (sizes the grid); order may be null
+// (queries in array order).  err (device) receives a nonzero bit if a tree
+// index is out of range; stats (device, may be null) accumulates, per query,
+// nodes entered, leaves scanned and points evaluated.
+int launch_knn(const KnnLaunch& L, int d, int kmax, const KnnQueries& Q, uint64_t grid_q,
+               const uint32_t* order, const LevelViews* views, uint32_t* err,
                unsigned long long* stats, hipStream_t s);
 
-// Compute a Morton order of the queries; returns the device array holding
-// the permutation (inside qs).
-const uint32_t* morton_order(int d, const float* q, uint64_t nq, QueryScratch& qs,
-                             hipStream_t s);
+// Morton order of queries [0, nq) of q, sorting cap >= nq keys (positions
+// from nq on sort last).  Returns the device array holding the permutation.
+const uint32_t* morton_order(int d, const float* q, const uint64_t* nq_dev, uint64_t nq_host,
+                             uint64_t cap, QueryScratch& qs, hipStream_t s);
+
+// Concatenate the queries of counts[1] requests (offsets in reqs[i].qoff,
+// counts[0] <= cap queries in all; device memory) into qall and record each
+// query's request in qreq.
+void launch_gather_queries(const KnnReqDev* reqs, const uint64_t* counts, uint64_t cap, int d,
+                           float* qall, uint32_t* qreq, hipStream_t s);
 
 }  // namespace bdl

@@ -181,7 +181,7 @@ size_t scan_tmp_words(uint64_t n) { return (size_t)((n + kScanTile - 1) / kScanT
 void scan_exclusive_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
                         uint32_t* tmp, hipStream_t s) {
   if (n == 0) {
-    if (total) hipMemsetAsync(total, 0, sizeof(uint32_t), s);
+    if (total) hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, 0u, total);
     return;
   }
   const uint32_t nb = (uint32_t)((n + kScanTile - 1) / kScanTile);

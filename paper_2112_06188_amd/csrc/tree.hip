@@ -7,7 +7,9 @@
 // done by the kernels in build.hip, erase.hip and knn.hip, enqueued on the
 // tree's stream.
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -66,7 +68,23 @@ struct bdl_tree {
   int64_t rbuf_cap = 0;
   int64_t rebuilt = 0, reinserted = 0;
   int knn_mode = kKnnWave;
+  int knn_block = 256;
+  int use_graphs = 1;
   uint64_t sort_min = kSortQueriesMin;
+  LevelViews* d_views = nullptr;   // the trees kNN_L visits, in device memory
+  // batched kNN_L (bdl_knn_batch)
+  QueryScratch bqs;                // Morton scratch sized for bcap queries
+  uint64_t bcap = 0;
+  float* bq = nullptr;             // concatenated queries [bcap][d]
+  uint32_t* bqreq = nullptr;       // request of each query
+  KnnReqDev* breqs = nullptr;      // request table (kMaxBatchReqs)
+  uint64_t* bcount = nullptr;      // [0] total queries, [1] request count
+  KnnReqDev* h_breqs[2] = {nullptr, nullptr};  // pinned staging ring
+  uint64_t* h_bcount[2] = {nullptr, nullptr};
+  hipEvent_t bslot_ev[2] = {nullptr, nullptr};
+  int bslot = 0;
+  hipStream_t cap_stream = nullptr;  // private stream for graph capture
+  std::map<std::tuple<uint64_t, int, int, int>, hipGraphExec_t> graphs;
   size_t held = 0;
   std::unordered_map<void*, size_t> sizes;
   // phase timing (BDL_FLAG_PROFILE)
@@ -265,7 +283,7 @@ bool ensure_level(bdl_tree* t, int j) {
   LevelState& L = t->lev[j];
   if (L.rec) return true;
   const int64_t cap = level_cap(t, j);
-  float* rec = (float*)dmalloc(t, (size_t)cap * t->S * 4);
+  float* rec = (float*)dmalloc(t, (size_t)(cap + kRecPad) * t->S * 4);
   if (!rec) return false;
   float* nodes = (float*)dmalloc(t, (size_t)(2 * cap) * t->NS * 4);
   if (!nodes) {
@@ -282,6 +300,15 @@ void upload_live(bdl_tree* t) {
   uint32_t v[kMaxLevels];
   for (int i = 0; i < kMaxLevels; ++i) v[i] = t->lev[i].on ? (uint32_t)t->lev[i].live : 0u;
   launch_store_u32(t->d_live, v, kMaxLevels, t->s);
+}
+
+LevelViews make_views(const bdl_tree* t);
+
+// Refresh the device copy of the trees kNN_L visits (after every change of
+// the structure; stream-ordered before any later k-NN launch or replay).
+void upload_views(bdl_tree* t) {
+  LevelViews v = make_views(t);
+  launch_store_views(t->d_views, v, t->s);
 }
 
 // Insert_L (Alg. 3) over the pool = buffer (arrival order) ++ batch.  The
@@ -378,7 +405,7 @@ int insert_impl(bdl_tree* t, const float* batch, const uint32_t* batch_ids, int6
   if (!t->pool[0]) {
     t->pool[0] = (float*)dmalloc(t, (size_t)X * t->S * 4);
     t->pool[1] = (float*)dmalloc(t, (size_t)X * t->S * 4);
-    t->brec = (float*)dmalloc(t, (size_t)X * t->S * 4);
+    t->brec = (float*)dmalloc(t, (size_t)(X + kRecPad) * t->S * 4);
     t->bnodes = (float*)dmalloc(t, (size_t)(2 * X) * t->NS * 4);
     if (!t->pool[0] || !t->pool[1] || !t->brec || !t->bnodes) {
       dfree(t, t->pool[0]);
@@ -452,6 +479,7 @@ int insert_impl(bdl_tree* t, const float* batch, const uint32_t* batch_ids, int6
   t->bn = bn_new;
   t->F = Fn;
   upload_live(t);
+  upload_views(t);
   if (hipGetLastError() != hipSuccess) return fail(BDL_EHIP, "kernel launch failed in insert");
   return 0;
 }
@@ -478,11 +506,174 @@ LevelViews make_views(const bdl_tree* t) {
   return v;
 }
 
+void destroy_graphs(bdl_tree* t) {
+  for (auto& kv : t->graphs) (void)hipGraphExecDestroy(kv.second);
+  t->graphs.clear();
+}
+
+// Scratch of the batched path for cap queries; growing it invalidates the
+// captured graphs (they hold its addresses).
+bool ensure_batch_scratch(bdl_tree* t, uint64_t cap) {
+  if (cap <= t->bcap) return true;
+  QueryScratch n;
+  n.cap = cap;
+  bool ok = true;
+  auto A = [&](size_t bytes) -> void* {
+    void* p = ok ? dmalloc(t, bytes) : nullptr;
+    if (!p) ok = false;
+    return p;
+  };
+  float* bq = (float*)A((size_t)cap * t->d * 4);
+  uint32_t* bqreq = (uint32_t*)A((size_t)cap * 4);
+  for (int i = 0; i < 2; ++i) {
+    n.keys[i] = (uint32_t*)A(cap * 4);
+    n.vals[i] = (uint32_t*)A(cap * 4);
+  }
+  n.tmp = (uint32_t*)A(radix_tmp_words(cap) * 4);
+  n.box = (uint32_t*)A(2 * kMaxDim * 4);
+  if (!ok) {
+    void* ps[] = {bq, bqreq, n.keys[0], n.keys[1], n.vals[0], n.vals[1], n.tmp, n.box};
+    for (void* p : ps) dfree(t, p);
+    return false;
+  }
+  (void)hipStreamSynchronize(t->s);
+  destroy_graphs(t);
+  void* old[] = {t->bq, t->bqreq, t->bqs.keys[0], t->bqs.keys[1], t->bqs.vals[0],
+                 t->bqs.vals[1], t->bqs.tmp, t->bqs.box};
+  for (void* p : old) dfree(t, p);
+  t->bq = bq;
+  t->bqreq = bqreq;
+  t->bqs = n;
+  t->bcap = cap;
+  return true;
+}
+
+// Kernel template bucket of the register array for the largest k.
+int kmax_bucket(int mode, int kmax) {
+  if (mode == kKnnWave && (kmax == 1 || kmax == 2 || kmax == 5 || kmax == 10)) return kmax;
+  if (kmax <= 4) return 4;
+  if (kmax <= 8) return 8;
+  if (kmax <= 16) return 16;
+  if (kmax <= 32) return 32;
+  return 64;
+}
+
+// The batched sequence: gather the requests' queries, order them, traverse.
+// Every size it uses is fixed by cap, every count is read from device
+// memory, so the same sequence is valid for any batch that fits cap.
+int enqueue_batch(bdl_tree* t, hipStream_t s, uint64_t cap, int kt) {
+  launch_gather_queries(t->breqs, t->bcount, cap, t->d, t->bq, t->bqreq, s);
+  const uint32_t* order = morton_order(t->d, t->bq, t->bcount, 0, cap, t->bqs, s);
+  KnnQueries Q;
+  std::memset(&Q, 0, sizeof(Q));
+  Q.q = t->bq;
+  Q.nq_dev = t->bcount;
+  Q.qreq = t->bqreq;
+  Q.reqs = t->breqs;
+  KnnLaunch L{t->knn_mode, t->knn_block};
+  return launch_knn(L, t->d, kt, Q, cap, order, t->d_views, t->d_misc + 8,
+                    t->pt.mark ? t->d_stats : nullptr, s);
+}
+
+int run_batch(bdl_tree* t, const bdl_knn_request* reqs, int nreq) {
+  const int slot = t->bslot;
+  // the staging slot is free once its previous copy has executed
+  if (hipEventSynchronize(t->bslot_ev[slot]) != hipSuccess)
+    return fail(BDL_EHIP, "staging wait failed");
+  KnnReqDev* h = t->h_breqs[slot];
+  uint64_t total = 0;
+  int kmax = 0, m = 0;
+  for (int i = 0; i < nreq; ++i) {
+    const bdl_knn_request& r = reqs[i];
+    if (r.nq == 0) continue;
+    h[m].q = r.q;
+    h[m].out_ids = r.out_ids;
+    h[m].out_d2 = r.out_d2;
+    h[m].qoff = total;
+    h[m].nq = (uint32_t)r.nq;
+    h[m].k = r.k;
+    total += (uint64_t)r.nq;
+    if (r.k > kmax) kmax = r.k;
+    ++m;
+  }
+  if (m == 0) return 0;
+  uint64_t cap = 4096;
+  while (cap < total) cap <<= 1;
+  if (!ensure_batch_scratch(t, cap)) return fail(BDL_ENOMEM, "batch scratch");
+  t->h_bcount[slot][0] = total;
+  t->h_bcount[slot][1] = (uint64_t)m;
+  if (hipMemcpyAsync(t->breqs, h, sizeof(KnnReqDev) * m, hipMemcpyHostToDevice, t->s) !=
+          hipSuccess ||
+      hipMemcpyAsync(t->bcount, t->h_bcount[slot], 2 * sizeof(uint64_t), hipMemcpyHostToDevice,
+                     t->s) != hipSuccess ||
+      hipEventRecord(t->bslot_ev[slot], t->s) != hipSuccess)
+    return fail(BDL_EHIP, "request table copy failed");
+  t->bslot ^= 1;
+  const int kt = kmax_bucket(t->knn_mode, kmax);
+  t->pt.begin(BDL_PH_TRAVERSE);
+  if (t->use_graphs) {
+    const auto key = std::make_tuple(cap, kt, t->knn_mode, t->knn_block);
+    auto it = t->graphs.find(key);
+    if (it == t->graphs.end()) {
+      hipGraph_t g = nullptr;
+      hipGraphExec_t ex = nullptr;
+      if (hipStreamBeginCapture(t->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(BDL_EHIP, "graph capture failed to start");
+      int rc = enqueue_batch(t, t->cap_stream, cap, kt);
+      hipError_t e = hipStreamEndCapture(t->cap_stream, &g);
+      if (rc || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return fail(BDL_EHIP, "graph capture failed");
+      }
+      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(BDL_EHIP, "graph instantiation failed");
+      it = t->graphs.emplace(key, ex).first;
+    }
+    if (hipGraphLaunch(it->second, t->s) != hipSuccess)
+      return fail(BDL_EHIP, "graph launch failed");
+  } else {
+    int rc = enqueue_batch(t, t->s, cap, kt);
+    if (rc) return fail(rc, "batched k-NN launch failed");
+  }
+  t->pt.end(BDL_PH_TRAVERSE);
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char* bdl_last_error(void) { return g_err.c_str(); }
+
+int bdl_knn_batch(bdl_tree* t, const bdl_knn_request* reqs, int32_t nreq) {
+  if (!t) return fail(BDL_EINVAL, "null tree");
+  if (nreq < 0) return fail(BDL_EINVAL, "negative request count");
+  if (nreq == 0) return 0;
+  if (!reqs) return fail(BDL_EINVAL, "null request array");
+  for (int i = 0; i < nreq; ++i) {
+    const bdl_knn_request& r = reqs[i];
+    if (r.k < 1 || r.k > BDL_MAX_K) return fail(BDL_EINVAL, "k must be in 1..64");
+    if (r.nq < 0 || r.nq >= (1ll << 31)) return fail(BDL_EINVAL, "bad query count");
+    if (r.nq > 0 && (!r.q || !r.out_ids || !r.out_d2))
+      return fail(BDL_EINVAL, "null query or output");
+  }
+  // launches of at most kMaxBatchReqs requests and 2^31 queries each
+  int i = 0;
+  while (i < nreq) {
+    int j = i;
+    uint64_t tot = 0;
+    while (j < nreq && j - i < kMaxBatchReqs && tot + (uint64_t)reqs[j].nq < (1ull << 31)) {
+      tot += (uint64_t)reqs[j].nq;
+      ++j;
+    }
+    int rc = run_batch(t, reqs + i, j - i);
+    if (rc) return rc;
+    i = j;
+  }
+  return 0;
+}
 
 int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out) {
   if (!cfg || !out) return fail(BDL_EINVAL, "null argument");
@@ -509,9 +700,23 @@ int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out) {
   t->d_live = (uint32_t*)dmalloc(t, kMaxLevels * 4);
   t->d_misc = (uint32_t*)dmalloc(t, 16 * 4);
   t->d_stats = (unsigned long long*)dmalloc(t, 8 * 8);
+  t->d_views = (LevelViews*)dmalloc(t, sizeof(LevelViews));
+  t->breqs = (KnnReqDev*)dmalloc(t, sizeof(KnnReqDev) * kMaxBatchReqs);
+  t->bcount = (uint64_t*)dmalloc(t, 2 * sizeof(uint64_t));
   t->sc.ctr = (BuildCounters*)dmalloc(t, sizeof(BuildCounters));
   t->sc.jobs = (Job*)dmalloc(t, sizeof(Job) * kMaxJobs);
-  bool ok = t->map && t->d_live && t->d_misc && t->d_stats && t->sc.ctr && t->sc.jobs;
+  bool ok = t->map && t->d_live && t->d_misc && t->d_stats && t->d_views && t->breqs &&
+            t->bcount && t->sc.ctr && t->sc.jobs;
+  for (int i = 0; ok && i < 2; ++i) {
+    if (hipHostMalloc((void**)&t->h_breqs[i], sizeof(KnnReqDev) * kMaxBatchReqs,
+                      hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&t->h_bcount[i], 2 * sizeof(uint64_t), hipHostMallocDefault) !=
+            hipSuccess ||
+        hipEventCreateWithFlags(&t->bslot_ev[i], hipEventDisableTiming) != hipSuccess)
+      ok = false;
+  }
+  if (ok && hipStreamCreateWithFlags(&t->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    ok = false;
   if (ok && hipHostMalloc((void**)&t->h_pin, (kMaxLevels + 16) * 4, hipHostMallocDefault) !=
                 hipSuccess)
     ok = false;
@@ -526,6 +731,7 @@ int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out) {
   launch_fill_u32(t->d_live, 0u, kMaxLevels, t->s);
   launch_fill_u32(t->d_misc, 0u, 16, t->s);
   launch_fill_u32((uint32_t*)t->d_stats, 0u, 16, t->s);
+  if (ok) upload_views(t);
   if (hipStreamSynchronize(t->s) != hipSuccess) {
     bdl_destroy(t);
     return fail(BDL_EHIP, "stream synchronisation failed");
@@ -541,6 +747,13 @@ void bdl_destroy(bdl_tree* t) {
   for (auto& kv : t->sizes) ps.push_back(kv.first);
   for (void* p : ps) dfree(t, p);
   resolve_events(t);
+  destroy_graphs(t);
+  for (int i = 0; i < 2; ++i) {
+    if (t->h_breqs[i]) (void)hipHostFree(t->h_breqs[i]);
+    if (t->h_bcount[i]) (void)hipHostFree(t->h_bcount[i]);
+    if (t->bslot_ev[i]) (void)hipEventDestroy(t->bslot_ev[i]);
+  }
+  if (t->cap_stream) (void)hipStreamDestroy(t->cap_stream);
   for (hipEvent_t e : t->ev_free) (void)hipEventDestroy(e);
   for (hipEvent_t e : t->ev_open)
     if (e) (void)hipEventDestroy(e);
@@ -560,6 +773,15 @@ int bdl_set_param(bdl_tree* t, int32_t param, int64_t value) {
       if (value < 1) return fail(BDL_EINVAL, "sort threshold must be >= 1");
       t->sort_min = (uint64_t)value;
       return 0;
+    case BDL_PARAM_KNN_BLOCK:
+      if (value != 64 && value != 128 && value != 256)
+        return fail(BDL_EINVAL, "k-NN workgroup size must be 64, 128 or 256");
+      t->knn_block = (int)value;
+      return 0;
+    case BDL_PARAM_USE_GRAPHS:
+      if (value != 0 && value != 1) return fail(BDL_EINVAL, "use_graphs is 0 or 1");
+      t->use_graphs = (int)value;
+      return 0;
     default:
       return fail(BDL_EINVAL, "unknown parameter");
   }
@@ -578,6 +800,7 @@ int bdl_clear(bdl_tree* t) {
   t->rebuilt = t->reinserted = 0;
   launch_fill_u32((uint32_t*)t->map, 0xFFFFFFFFu, (uint64_t)t->cfg.id_capacity * 2, t->s);
   launch_fill_u32(t->d_live, 0u, kMaxLevels, t->s);
+  upload_views(t);
   if (hipGetLastError() != hipSuccess) return fail(BDL_EHIP, "clear failed");
   return 0;
 }
@@ -716,6 +939,7 @@ int bdl_erase(bdl_tree* t, const float* pts, const uint32_t* ids, int64_t n, int
     t->reinserted += rn;
   } else {
     upload_live(t);
+    upload_views(t);
   }
   if (hipGetLastError() != hipSuccess) return fail(BDL_EHIP, "kernel launch failed in erase");
   return 0;
@@ -732,13 +956,23 @@ int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_id
   if ((uint64_t)nq >= t->sort_min) {
     if (!ensure_query_scratch(t, (uint64_t)nq)) return fail(BDL_ENOMEM, "query scratch");
     t->pt.begin(BDL_PH_ORDER);
-    order = morton_order(t->d, q, (uint64_t)nq, t->qs, t->s);
+    order = morton_order(t->d, q, nullptr, (uint64_t)nq, (uint64_t)nq, t->qs, t->s);
     t->pt.end(BDL_PH_ORDER);
   }
-  LevelViews v = make_views(t);
+  KnnQueries Q;
+  std::memset(&Q, 0, sizeof(Q));
+  Q.q = q;
+  Q.nq = (uint64_t)nq;
+  Q.one.q = q;
+  Q.one.out_ids = out_ids;
+  Q.one.out_d2 = out_d2;
+  Q.one.qoff = 0;
+  Q.one.nq = (uint32_t)nq;
+  Q.one.k = k;
+  KnnLaunch L{t->knn_mode, t->knn_block};
   t->pt.begin(BDL_PH_TRAVERSE);
-  int rc = launch_knn(t->knn_mode, t->d, k, q, (uint64_t)nq, v, order, out_ids, out_d2,
-                      t->d_misc + 8, t->pt.mark ? t->d_stats : nullptr, t->s);
+  int rc = launch_knn(L, t->d, k, Q, (uint64_t)nq, order, t->d_views, t->d_misc + 8,
+                      t->pt.mark ? t->d_stats : nullptr, t->s);
   t->pt.end(BDL_PH_TRAVERSE);
   if (rc) return fail(rc, "k-NN launch failed");
   return 0;
