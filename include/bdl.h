@@ -112,7 +112,35 @@ int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_id
 #define BDL_PARAM_KNN_BLOCK 3  /* k-NN workgroup size: 64, 128 or 256 (default) */
 #define BDL_PARAM_USE_GRAPHS 4 /* 1 (default): bdl_knn_batch replays captured
                                   hipGraphs; 0: it launches eagerly */
+#define BDL_PARAM_PERSISTENT 5 /* 1: a k-NN batch larger than the device holds at
+                                  once runs on a resident grid that draws groups
+                                  of 64 queries from per-XCD work counters;
+                                  0 (default): one wavefront per group */
 int bdl_set_param(bdl_tree* t, int32_t param, int64_t value);
+
+/* One row of a launch-shape table for kNN_L (bdl_knn and bdl_knn_batch).  A
+ * launch whose largest k lies in [k_lo, k_hi] and whose query count lies in
+ * [nq_lo, nq_hi] uses this row's kernel, workgroup size, persistence and
+ * (bdl_knn only) Morton ordering; the first matching row wins and a launch
+ * no row matches uses the values of bdl_set_param.  Rows come from an
+ * autotuner that times the candidates on the device.  Shapes change speed,
+ * never results. */
+typedef struct {
+  int32_t k_lo, k_hi;   /* 1..64 */
+  int64_t nq_lo, nq_hi; /* query counts, inclusive */
+  int32_t kernel;       /* 0 lane, 1 wave (as BDL_PARAM_KNN_KERNEL) */
+  int32_t block;        /* 64, 128 or 256 */
+  int32_t persistent;   /* 0 or 1 */
+  int32_t sort;         /* 0 or 1: Morton-order the queries of a bdl_knn call
+                           (bdl_knn_batch always orders them) */
+} bdl_knn_shape;
+
+#define BDL_MAX_SHAPES 256
+
+/* Install a copy of rows[0..n) (n <= BDL_MAX_SHAPES) as the tree's shape
+ * table, replacing the previous one; n = 0 removes it.  BDL_EINVAL on a row
+ * with a value out of range (the table is then unchanged). */
+int bdl_set_knn_shapes(bdl_tree* t, const bdl_knn_shape* rows, int32_t n);
 
 /* Remove every point.  Device memory stays allocated for reuse; the tree
  * is then as if just created.  Asynchronous. */

@@ -31,13 +31,15 @@ EXPORTS = [
     "bdl_create", "bdl_insert", "bdl_erase", "bdl_knn", "bdl_clear", "bdl_sync", "bdl_destroy",
     "bdl_size", "bdl_level_info", "bdl_counters", "bdl_debug_export_level",
     "bdl_debug_export_buffer", "bdl_last_error", "bdl_profile", "bdl_level_sizes",
-    "bdl_set_param", "bdl_knn_batch",
+    "bdl_set_param", "bdl_knn_batch", "bdl_set_knn_shapes",
 ]
 FLAG_PROFILE = 2
 PARAM_KNN_KERNEL = 1
 PARAM_SORT_MIN = 2
 PARAM_KNN_BLOCK = 3
 PARAM_USE_GRAPHS = 4
+PARAM_PERSISTENT = 5
+MAX_SHAPES = 256
 KNN_LANE = 0
 KNN_WAVE = 1
 PHASES = ["gather", "passes", "finish", "layout", "erase", "order", "traverse", "other"]
@@ -68,6 +70,14 @@ class KnnRequest(ctypes.Structure):
     _fields_ = [("q", ctypes.c_void_p), ("nq", ctypes.c_int64), ("k", ctypes.c_int32),
                 ("pad_", ctypes.c_int32), ("out_ids", ctypes.c_void_p),
                 ("out_d2", ctypes.c_void_p)]
+
+
+class KnnShape(ctypes.Structure):
+    """One row of the k-NN launch-shape table (bdl_knn_shape)."""
+    _fields_ = [("k_lo", ctypes.c_int32), ("k_hi", ctypes.c_int32),
+                ("nq_lo", ctypes.c_int64), ("nq_hi", ctypes.c_int64),
+                ("kernel", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("sort", ctypes.c_int32)]
 
 
 class BdlError(RuntimeError):
@@ -110,6 +120,7 @@ def load_library(path: str = LIB_PATH):
     lib.bdl_clear.argtypes = [vp]
     lib.bdl_set_param.argtypes = [vp, i32, i64]
     lib.bdl_knn_batch.argtypes = [vp, ctypes.POINTER(KnnRequest), i32]
+    lib.bdl_set_knn_shapes.argtypes = [vp, ctypes.POINTER(KnnShape), i32]
     lib.bdl_profile.argtypes = [vp, ctypes.POINTER(Profile), ctypes.c_int]
     lib.bdl_destroy.argtypes = [vp]
     lib.bdl_destroy.restype = None
@@ -124,6 +135,7 @@ def load_library(path: str = LIB_PATH):
     lib.bdl_last_error.restype = ctypes.c_char_p
     for name in ("bdl_create", "bdl_insert", "bdl_erase", "bdl_knn", "bdl_clear", "bdl_sync",
                  "bdl_profile", "bdl_level_sizes", "bdl_set_param", "bdl_knn_batch",
+                 "bdl_set_knn_shapes",
                  "bdl_level_info", "bdl_counters", "bdl_debug_export_level",
                  "bdl_debug_export_buffer"):
         getattr(lib, name).restype = ctypes.c_int
@@ -285,6 +297,21 @@ class Tree:
     def set_param(self, param: int, value: int) -> None:
         """Tuning knobs (PARAM_*); they change speed, never results."""
         _check(self._lib.bdl_set_param(self._h, int(param), int(value)))
+
+    def set_knn_shapes(self, rows) -> None:
+        """Install a k-NN launch-shape table: rows of dicts (or tuples in
+        KnnShape field order) with k_lo, k_hi, nq_lo, nq_hi, kernel, block,
+        persistent, sort.  An empty list removes the table."""
+        rows = list(rows)
+        arr = (KnnShape * max(1, len(rows)))()
+        names = [f for f, _ in KnnShape._fields_]
+        for i, r in enumerate(rows):
+            vals = [r[n] for n in names] if isinstance(r, dict) else list(r)
+            for n, v in zip(names, vals):
+                setattr(arr[i], n, int(v))
+        _check(self._lib.bdl_set_knn_shapes(self._h, arr, len(rows)))
+        self._shapes = [dict(zip(names, (getattr(arr[i], n) for n in names)))
+                        for i in range(len(rows))]
 
     def clear(self) -> None:
         """Remove every point; device memory is kept for reuse."""

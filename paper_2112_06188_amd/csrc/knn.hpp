@@ -47,11 +47,23 @@ struct KnnQueries {
   KnnReqDev one;
 };
 
-// Kernel choice and workgroup size (64, 128 or 256).
+// Kernel choice and workgroup size (64, 128 or 256).  With `persistent` set
+// and a queue given (kKnnQueueWords words of device memory owned by the
+// caller, not in use by another launch on another stream), a batch larger
+// than the device holds at once runs on a resident grid whose waves draw
+// groups of 64 queries from per-XCD counters.  dry_run only prepares the
+// launch (occupancy lookups), so that a later launch under stream capture
+// makes no such query.
 struct KnnLaunch {
-  int mode;
-  int block;
+  int mode = kKnnWave;
+  int block = 256;
+  int persistent = 0;
+  uint32_t* queue = nullptr;
+  bool dry_run = false;
 };
+
+constexpr int kKnnQueueStride = 64;  // words between the per-XCD counters
+constexpr int kKnnQueueWords = 8 * kKnnQueueStride;
 
 // kNN_L over the trees listed in `views` (device memory, visited in order).
 // grid_q bounds the number of queries (sizes the grid); order may be null

@@ -70,7 +70,10 @@ struct bdl_tree {
   int knn_mode = kKnnWave;
   int knn_block = 256;
   int use_graphs = 1;
+  int persistent = 0;
   uint64_t sort_min = kSortQueriesMin;
+  std::vector<bdl_knn_shape> shapes;  // launch-shape table (autotuned)
+  uint32_t* d_queue = nullptr;        // work counters of persistent k-NN launches
   LevelViews* d_views = nullptr;   // the trees kNN_L visits, in device memory
   // batched kNN_L (bdl_knn_batch)
   QueryScratch bqs;                // Morton scratch sized for bcap queries
@@ -84,7 +87,7 @@ struct bdl_tree {
   hipEvent_t bslot_ev[2] = {nullptr, nullptr};
   int bslot = 0;
   hipStream_t cap_stream = nullptr;  // private stream for graph capture
-  std::map<std::tuple<uint64_t, int, int, int>, hipGraphExec_t> graphs;
+  std::map<std::tuple<uint64_t, int, int, int, int>, hipGraphExec_t> graphs;
   size_t held = 0;
   std::unordered_map<void*, size_t> sizes;
   // phase timing (BDL_FLAG_PROFILE)
@@ -561,7 +564,30 @@ int kmax_bucket(int mode, int kmax) {
 // The batched sequence: gather the requests' queries, order them, traverse.
 // Every size it uses is fixed by cap, every count is read from device
 // memory, so the same sequence is valid for any batch that fits cap.
-int enqueue_batch(bdl_tree* t, hipStream_t s, uint64_t cap, int kt) {
+// Launch shape of a k-NN launch with largest k `kmax` over nq queries: the
+// first matching row of the shape table, else the tree's parameters.  *sort
+// (may be null) tells whether a bdl_knn call orders its queries.
+KnnLaunch choose_launch(const bdl_tree* t, int kmax, uint64_t nq, bool* sort) {
+  KnnLaunch L;
+  L.mode = t->knn_mode;
+  L.block = t->knn_block;
+  L.persistent = t->persistent;
+  L.queue = t->d_queue;
+  bool srt = nq >= t->sort_min;
+  for (const bdl_knn_shape& r : t->shapes) {
+    if (kmax < r.k_lo || kmax > r.k_hi || (int64_t)nq < r.nq_lo || (int64_t)nq > r.nq_hi)
+      continue;
+    L.mode = r.kernel;
+    L.block = r.block;
+    L.persistent = r.persistent;
+    srt = r.sort != 0;
+    break;
+  }
+  if (sort) *sort = srt;
+  return L;
+}
+
+int enqueue_batch(bdl_tree* t, hipStream_t s, uint64_t cap, int kt, const KnnLaunch& L) {
   launch_gather_queries(t->breqs, t->bcount, cap, t->d, t->bq, t->bqreq, s);
   const uint32_t* order = morton_order(t->d, t->bq, t->bcount, 0, cap, t->bqs, s);
   KnnQueries Q;
@@ -570,7 +596,6 @@ int enqueue_batch(bdl_tree* t, hipStream_t s, uint64_t cap, int kt) {
   Q.nq_dev = t->bcount;
   Q.qreq = t->bqreq;
   Q.reqs = t->breqs;
-  KnnLaunch L{t->knn_mode, t->knn_block};
   return launch_knn(L, t->d, kt, Q, cap, order, t->d_views, t->d_misc + 8,
                     t->pt.mark ? t->d_stats : nullptr, s);
 }
@@ -609,17 +634,23 @@ int run_batch(bdl_tree* t, const bdl_knn_request* reqs, int nreq) {
       hipEventRecord(t->bslot_ev[slot], t->s) != hipSuccess)
     return fail(BDL_EHIP, "request table copy failed");
   t->bslot ^= 1;
-  const int kt = kmax_bucket(t->knn_mode, kmax);
+  // the shape is chosen for the bucket, so that one graph serves it
+  const KnnLaunch L = choose_launch(t, kmax, cap, nullptr);
+  const int kt = kmax_bucket(L.mode, kmax);
   t->pt.begin(BDL_PH_TRAVERSE);
   if (t->use_graphs) {
-    const auto key = std::make_tuple(cap, kt, t->knn_mode, t->knn_block);
+    const auto key = std::make_tuple(cap, kt, L.mode, L.block, L.persistent);
     auto it = t->graphs.find(key);
     if (it == t->graphs.end()) {
       hipGraph_t g = nullptr;
       hipGraphExec_t ex = nullptr;
+      KnnLaunch dry = L;
+      dry.dry_run = true;
+      (void)launch_knn(dry, t->d, kt, KnnQueries{}, cap, nullptr, nullptr, nullptr, nullptr,
+                       t->cap_stream);
       if (hipStreamBeginCapture(t->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(BDL_EHIP, "graph capture failed to start");
-      int rc = enqueue_batch(t, t->cap_stream, cap, kt);
+      int rc = enqueue_batch(t, t->cap_stream, cap, kt, L);
       hipError_t e = hipStreamEndCapture(t->cap_stream, &g);
       if (rc || e != hipSuccess || !g) {
         if (g) (void)hipGraphDestroy(g);
@@ -634,7 +665,7 @@ int run_batch(bdl_tree* t, const bdl_knn_request* reqs, int nreq) {
     if (hipGraphLaunch(it->second, t->s) != hipSuccess)
       return fail(BDL_EHIP, "graph launch failed");
   } else {
-    int rc = enqueue_batch(t, t->s, cap, kt);
+    int rc = enqueue_batch(t, t->s, cap, kt, L);
     if (rc) return fail(rc, "batched k-NN launch failed");
   }
   t->pt.end(BDL_PH_TRAVERSE);
@@ -701,11 +732,12 @@ int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out) {
   t->d_misc = (uint32_t*)dmalloc(t, 16 * 4);
   t->d_stats = (unsigned long long*)dmalloc(t, 8 * 8);
   t->d_views = (LevelViews*)dmalloc(t, sizeof(LevelViews));
+  t->d_queue = (uint32_t*)dmalloc(t, kKnnQueueWords * 4);
   t->breqs = (KnnReqDev*)dmalloc(t, sizeof(KnnReqDev) * kMaxBatchReqs);
   t->bcount = (uint64_t*)dmalloc(t, 2 * sizeof(uint64_t));
   t->sc.ctr = (BuildCounters*)dmalloc(t, sizeof(BuildCounters));
   t->sc.jobs = (Job*)dmalloc(t, sizeof(Job) * kMaxJobs);
-  bool ok = t->map && t->d_live && t->d_misc && t->d_stats && t->d_views && t->breqs &&
+  bool ok = t->map && t->d_live && t->d_misc && t->d_stats && t->d_views && t->d_queue && t->breqs &&
             t->bcount && t->sc.ctr && t->sc.jobs;
   for (int i = 0; ok && i < 2; ++i) {
     if (hipHostMalloc((void**)&t->h_breqs[i], sizeof(KnnReqDev) * kMaxBatchReqs,
@@ -782,9 +814,28 @@ int bdl_set_param(bdl_tree* t, int32_t param, int64_t value) {
       if (value != 0 && value != 1) return fail(BDL_EINVAL, "use_graphs is 0 or 1");
       t->use_graphs = (int)value;
       return 0;
+    case BDL_PARAM_PERSISTENT:
+      if (value != 0 && value != 1) return fail(BDL_EINVAL, "persistent is 0 or 1");
+      t->persistent = (int)value;
+      return 0;
     default:
       return fail(BDL_EINVAL, "unknown parameter");
   }
+}
+int bdl_set_knn_shapes(bdl_tree* t, const bdl_knn_shape* rows, int32_t n) {
+  if (!t) return fail(BDL_EINVAL, "null tree");
+  if (n < 0 || n > BDL_MAX_SHAPES) return fail(BDL_EINVAL, "shape table size out of range");
+  if (n > 0 && !rows) return fail(BDL_EINVAL, "null shape table");
+  for (int32_t i = 0; i < n; ++i) {
+    const bdl_knn_shape& r = rows[i];
+    if (r.k_lo < 1 || r.k_hi > BDL_MAX_K || r.k_lo > r.k_hi || r.nq_lo < 0 || r.nq_lo > r.nq_hi ||
+        (r.kernel != kKnnLane && r.kernel != kKnnWave) ||
+        (r.block != 64 && r.block != 128 && r.block != 256) || (r.persistent & ~1) ||
+        (r.sort & ~1))
+      return fail(BDL_EINVAL, "shape row " + std::to_string(i) + " out of range");
+  }
+  t->shapes.assign(rows, rows + n);
+  return 0;
 }
 
 int bdl_clear(bdl_tree* t) {
@@ -952,8 +1003,10 @@ int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_id
   if (nq == 0) return 0;
   if (!q || !out_ids || !out_d2) return fail(BDL_EINVAL, "null query or output");
   if (nq >= (1ll << 32)) return fail(BDL_EINVAL, "query batch too large");
+  bool sort = false;
+  const KnnLaunch L = choose_launch(t, k, (uint64_t)nq, &sort);
   const uint32_t* order = nullptr;
-  if ((uint64_t)nq >= t->sort_min) {
+  if (sort) {
     if (!ensure_query_scratch(t, (uint64_t)nq)) return fail(BDL_ENOMEM, "query scratch");
     t->pt.begin(BDL_PH_ORDER);
     order = morton_order(t->d, q, nullptr, (uint64_t)nq, (uint64_t)nq, t->qs, t->s);
@@ -969,7 +1022,6 @@ int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_id
   Q.one.qoff = 0;
   Q.one.nq = (uint32_t)nq;
   Q.one.k = k;
-  KnnLaunch L{t->knn_mode, t->knn_block};
   t->pt.begin(BDL_PH_TRAVERSE);
   int rc = launch_knn(L, t->d, k, Q, (uint64_t)nq, order, t->d_views, t->d_misc + 8,
                       t->pt.mark ? t->d_stats : nullptr, t->s);

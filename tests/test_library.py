@@ -127,3 +127,41 @@ int main() {
     for line in out.strip().splitlines():
         H, dep, p, k = (int(x) for x in line.split())
         assert k == veb_key(H, dep, p), (H, dep, p)
+
+
+def test_abi_struct_layouts_match_header():
+    """The ctypes mirrors of the structs in bdl.h have the C compiler's sizes
+    and field offsets (a host C build of the header prints them)."""
+    import subprocess
+    import tempfile
+    import paper_2112_06188_amd as pkg
+    structs = {"bdl_config": pkg.Config, "bdl_profile_t": pkg.Profile,
+               "bdl_knn_request": pkg.KnnRequest, "bdl_knn_shape": pkg.KnnShape}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bdl.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    with tempfile.TemporaryDirectory() as td:
+        c = os.path.join(td, "l.c")
+        exe = os.path.join(td, "l")
+        open(c, "w").write("\n".join(lines) + "\n")
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), c, "-o", exe],
+                       check=True, capture_output=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    seen = 0
+    for line in out.strip().splitlines():
+        cname, field, val = line.split()
+        py = structs[cname]
+        want = ctypes.sizeof(py) if field == "sizeof" else getattr(py, field).offset
+        assert int(val) == want, (cname, field)
+        seen += 1
+    assert seen == sum(len(p._fields_) + 1 for p in structs.values())
+
+
+def test_shape_table_rejects_bad_rows_on_the_host(lib):
+    import paper_2112_06188_amd as pkg
+    L = pkg.load_library()
+    assert L.bdl_set_knn_shapes(None, None, 0) == pkg.BDL_EINVAL
+    assert L.bdl_set_param(None, pkg.PARAM_PERSISTENT, 1) == pkg.BDL_EINVAL
