@@ -81,6 +81,13 @@ class Workload:
     id_capacity: int
     ops: List[Op]
     description: str = ""
+    n_setup: int = 0   # leading ops that only build the resident set
+
+
+def log_uniform_sizes(rng: np.random.Generator, n: int, lo: float, hi: float) -> np.ndarray:
+    """n integer sizes exp(U(ln lo, ln hi)) rounded to nearest, clamped to [lo, hi]."""
+    v = np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), size=n)))
+    return np.clip(v, lo, hi).astype(np.int64)
 
 
 class _LiveIds:
@@ -183,8 +190,48 @@ def _clustered7d(scale: float = 1.0, seed: int = 0) -> Workload:
                     f"7D clustered, {n} points via 100 inserts, erase {m}, k=10 all live")
 
 
+def _batched5d_20m(scale: float = 1.0, seed: int = 0) -> Workload:
+    """Batched-form op log: a 5D uniform resident set of 20M points built by
+    20 inserts of 1M (setup), then 4096 kNN batches whose sizes are
+    log-uniform in [1, 1e5] with k uniform over {1, 5, 10} and fresh uniform
+    queries, and after every 32nd kNN batch one insert of a log-uniform
+    [1e3, 1e6] number of fresh uniform points.  `scale` shrinks the resident
+    set, the number of kNN batches and the insert sizes together."""
+    d = 5
+    n_res = int(round(20_000_000 * scale))
+    nb = max(1, n_res // 20)
+    n_res = nb * 20
+    n_knn = max(32, int(round(4096 * scale)))
+    rng = np.random.default_rng(seed + 10)
+    sizes = log_uniform_sizes(rng, n_knn, 1, max(1, int(round(100_000 * min(1.0, scale * 4)))))
+    ks = rng.choice(np.array([1, 5, 10]), size=n_knn)
+    n_ins = n_knn // 32
+    ins_sizes = log_uniform_sizes(rng, n_ins, max(1, int(1e3 * scale)), max(1, int(1e6 * scale)))
+    pts = uniform_points(n_res + int(ins_sizes.sum()), d, seed)
+    ids = np.arange(pts.shape[0], dtype=np.uint32)
+    q = uniform_points(int(sizes.sum()), d, seed + 20)
+    ops: List[Op] = []
+    for b in range(20):
+        sl = slice(b * nb, (b + 1) * nb)
+        ops.append(Op("insert", pts[sl], ids[sl]))
+    qo = 0
+    po = n_res
+    for b in range(n_knn):
+        ops.append(Op("knn", q[qo:qo + sizes[b]], k=int(ks[b])))
+        qo += int(sizes[b])
+        if b % 32 == 31 and b // 32 < n_ins:
+            m = int(ins_sizes[b // 32])
+            ops.append(Op("insert", pts[po:po + m], ids[po:po + m]))
+            po += m
+    return Workload("batched5d_20m", d, 16, 1024, int(pts.shape[0]), ops,
+                    f"5D uniform, {n_res} resident, {n_knn} kNN batches "
+                    f"({int(sizes.sum())} queries, k in {{1,5,10}}), {n_ins} inserts "
+                    f"({int(ins_sizes.sum())} points)", n_setup=20)
+
+
 WORKLOADS = {
     "uniform2d_small": _uniform_small,
+    "batched5d_20m": _batched5d_20m,
     "uniform3d_10m": _uniform3d_10m,
     "clustered7d_10m": _clustered7d,
 }

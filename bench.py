@@ -1,12 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the BDL-tree hot path on one MI355X.
 
-A step is one pass of the whole path over the 3D workload: Insert_L of 10
-batches of 1M uniform points into an empty tree, one Erase_L of 1M random
-live points, then kNN_L with k = 5 for every one of the 9M live points.  All
-inputs are resident in HBM before the timed region.  Prints one JSON line.
+Default form (plain): a step is one pass of the whole path over the 3D
+workload: Insert_L of 10 batches of 1M uniform points into an empty tree,
+one Erase_L of 1M random live points, then kNN_L with k = 5 for every one of
+the 9M live points.  All inputs are resident in HBM before the timed region.
+Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+--form batched: the op log of 4096 uneven 5D kNN_L batches (k in {1,5,10})
+and 128 Insert_L batches over a 20M-point resident set, run once call by
+call (bdl_knn per batch) and once in the batched form (bdl_knn_batch over
+the kNN batches between two inserts, replayed hipGraphs), both with the
+autotuned launch shapes; results must be identical.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--form plain|batched]
 """
 from __future__ import annotations
 
@@ -162,6 +169,171 @@ def gpu_bench(args):
     return res, w, (q, out_ids, out_d2)
 
 
+def _dv(torch, a):
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).to("cuda")
+
+
+def batched_bench(args):
+    """Plain per-call path vs the batched form on the same op log."""
+    import torch
+
+    import paper_2112_06188_amd as bdl
+    from bdl_inputs import uniform_points, workload
+    from paper_2112_06188_amd import autotune
+
+    torch.cuda.set_device(0)
+    w = workload("batched5d_20m", scale=args.scale)
+    setup = [(_dv(torch, op.pts), _dv(torch, op.ids)) for op in w.ops[:w.n_setup]]
+    log = []
+    for op in w.ops[w.n_setup:]:
+        if op.kind == "knn":
+            log.append(("knn", _dv(torch, op.pts), op.k))
+        else:
+            log.append(("insert", _dv(torch, op.pts), _dv(torch, op.ids)))
+    n_q = sum(x[1].shape[0] for x in log if x[0] == "knn")
+    n_ins = sum(x[1].shape[0] for x in log if x[0] == "insert")
+    n_kb = sum(1 for x in log if x[0] == "knn")
+
+    def outputs():
+        return [(torch.empty((x[1].shape[0], x[2]), dtype=torch.int32, device="cuda"),
+                 torch.empty((x[1].shape[0], x[2]), dtype=torch.float32, device="cuda"))
+                if x[0] == "knn" else None for x in log]
+
+    out_plain, out_batch = outputs(), outputs()
+    tree = bdl.Tree(w.dim, leaf_size=w.leaf_size, buffer_size=w.buffer_size,
+                    id_capacity=w.id_capacity)
+
+    def build_resident():
+        tree.clear()
+        for p, i in setup:
+            tree.insert(p, i)
+        tree.sync()
+
+    build_resident()
+    # launch shapes: tuned on the resident set with fresh queries (not timed)
+    tq = _dv(torch, uniform_points(1 << 20, w.dim, 999))
+    t0 = time.perf_counter()
+    tuned = autotune.tune(tree, lambda n: tq[:n], k_bands=((1, 1), (2, 5), (6, 10)),
+                          nq_bands=((1, 2048), (2049, 32768), (32769, 1 << 40)),
+                          max_nq=1 << 20, reps=2)
+    tune_s = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+
+    def timed_insert(x, ins):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        tree.insert(x[1], x[2])
+        b.record(stream)
+        ins.append((a, b))
+
+    def run_plain():
+        lat, ins = [], []
+        for x, o in zip(log, out_plain):
+            if x[0] == "knn":
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                tree.knn(x[1], x[2], o[0], o[1])
+                b.record(stream)
+                lat.append((a, b))
+            else:
+                timed_insert(x, ins)
+        return lat, ins
+
+    def run_batched():
+        pend, po, ins = [], [], []
+        for x, o in zip(log, out_batch):
+            if x[0] == "knn":
+                pend.append((x[1], x[2]))
+                po.append(o)
+            else:
+                if pend:
+                    tree.knn_batch(pend, po)
+                    pend, po = [], []
+                timed_insert(x, ins)
+        if pend:
+            tree.knn_batch(pend, po)
+        return [], ins
+
+    res = {}
+    for name, fn in (("plain", run_plain), ("batched", run_batched)):
+        for _ in range(args.warmup):
+            build_resident()
+            fn()
+            tree.sync()
+        times, lats, ins_s = [], [], []
+        for _ in range(args.steps):
+            build_resident()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lat, ins = fn()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            tree.sync()
+            lats += [a.elapsed_time(b) for a, b in lat]
+            ins_s.append(sum(a.elapsed_time(b) for a, b in ins) / 1e3)
+        sec = float(np.median(times))
+        ins_sec = float(np.median(ins_s))
+        res[name] = {"seconds": sec, "ops_per_s": (n_q + n_ins) / sec,
+                     "insert_seconds": ins_sec,
+                     "knn_queries_per_s": n_q / max(1e-9, sec - ins_sec)}
+        if lats:
+            res[name]["knn_call_latency_ms"] = {"p50": _pct(lats, 50), "p99": _pct(lats, 99)}
+    same = all(torch.equal(a[0], b[0]) and torch.equal(a[1].view(torch.int32), b[1].view(torch.int32))
+               for a, b in zip(out_plain, out_batch) if a is not None)
+    # sampled parity against the definition: 2 queries of every 64th kNN
+    # batch, brute force over the live set at that point of the log
+    check = None
+    if args.cpu_sample > 0:
+        import oracle
+        # the workload's points are one array in insertion order and nothing
+        # is erased, so the live set at any point of the log is a prefix
+        allp = np.concatenate([op.pts for op in w.ops if op.kind == "insert"])
+        alli = np.concatenate([op.ids for op in w.ops if op.kind == "insert"])
+        n_live = sum(op.n for op in w.ops[:w.n_setup])
+        ok = True
+        nchk = 0
+        t0 = time.perf_counter()
+        kb = 0
+        for op, o in zip(w.ops[w.n_setup:], out_batch):
+            if op.kind == "insert":
+                n_live += op.n
+                continue
+            if kb % 64 == 0:
+                sel = np.unique(np.array([0, op.n - 1]))
+                oi, od = oracle.bruteforce_knn(allp[:n_live], alli[:n_live], op.pts[sel], op.k)
+                gi = o[0].cpu().numpy().view(np.uint32)[sel]
+                gd = o[1].cpu().numpy()[sel]
+                ok &= bool(np.array_equal(gi, oi) and
+                           np.array_equal(gd.view(np.uint32), od.view(np.uint32)))
+                nchk += len(sel)
+            kb += 1
+        check = {"queries_checked": nchk, "equal_to_bruteforce": ok,
+                 "seconds": time.perf_counter() - t0}
+    tree.close()
+    sp = res["plain"]["seconds"] / res["batched"]["seconds"]
+    return {
+        "metric": "batched form vs plain path: kNN_L + Insert_L ops/s on one op log "
+                  "(4096 uneven 5D kNN batches, 128 inserts, 20M resident)",
+        "value": res["batched"]["ops_per_s"],
+        "unit": "ops/s (kNN queries + inserted points per second)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["batched"]["seconds"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded uniform float32 points in [0,1)^5)",
+        "config": {"workload": w.name, "dim": w.dim, "knn_batches": n_kb, "queries": n_q,
+                   "insert_batches": len(log) - n_kb, "inserted_points": n_ins,
+                   "resident_points": sum(p.shape[0] for p, _ in setup)},
+        "plain": res["plain"], "batched": res["batched"],
+        "speedup_batched_over_plain": sp,
+        "results_identical": same,
+        "oracle_check": check,
+        "autotune": {"seconds": tune_s, "rows": tuned["rows"]},
+    }
+
+
 def cpu_baseline(w, gpu_out, n_sample: int):
     """The oracle on the host: the full update sequence, then kNN_L on a
     sample of the queries; throughput in the benchmark's unit (the kNN time
@@ -223,11 +395,15 @@ def main():
                     help="0: one lane per query, 1: one wavefront per 64 queries")
     ap.add_argument("--cpu-sample", type=int, default=200_000,
                     help="queries the CPU oracle answers for the baseline (0: skip)")
+    ap.add_argument("--form", default="plain", choices=["plain", "batched"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how the structure would shard)", file=sys.stderr)
         sys.exit(2)
+    if args.form == "batched":
+        print(json.dumps(batched_bench(args)), flush=True)
+        return
     res, w, gpu_out = gpu_bench(args)
     if args.cpu_sample > 0:
         res["cpu_baseline"] = cpu_baseline(w, gpu_out, args.cpu_sample)

@@ -26,13 +26,17 @@ MAX_K = 64
 INVALID_ID = 0xFFFFFFFF
 FLAG_CHECK_INPUTS = 1
 
-# Every symbol include/bdl.h declares.
+# Every symbol include/bdl.h and include/bdl_server.h declare.
 EXPORTS = [
     "bdl_create", "bdl_insert", "bdl_erase", "bdl_knn", "bdl_clear", "bdl_sync", "bdl_destroy",
     "bdl_size", "bdl_level_info", "bdl_counters", "bdl_debug_export_level",
     "bdl_debug_export_buffer", "bdl_last_error", "bdl_profile", "bdl_level_sizes",
     "bdl_set_param", "bdl_knn_batch", "bdl_set_knn_shapes",
+    "bdl_server_create", "bdl_server_submit", "bdl_server_wait", "bdl_server_poll",
+    "bdl_server_drain", "bdl_server_destroy",
 ]
+REQ_KNN, REQ_INSERT, REQ_ERASE = 0, 1, 2
+SERVE_FIFO, SERVE_BATCHED = 0, 1
 FLAG_PROFILE = 2
 PARAM_KNN_KERNEL = 1
 PARAM_SORT_MIN = 2
@@ -78,6 +82,26 @@ class KnnShape(ctypes.Structure):
                 ("nq_lo", ctypes.c_int64), ("nq_hi", ctypes.c_int64),
                 ("kernel", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("sort", ctypes.c_int32)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("max_batch_requests", ctypes.c_int32), ("max_launches", ctypes.c_int32),
+                ("max_batch_queries", ctypes.c_int64), ("mem_budget", ctypes.c_uint64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("k", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("pts", ctypes.c_void_p), ("ids", ctypes.c_void_p),
+                ("out_ids", ctypes.c_void_p), ("out_d2", ctypes.c_void_p)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("admit_seq", ctypes.c_uint64),
+                ("kind", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("n_erased", ctypes.c_int64), ("launch", ctypes.c_int64),
+                ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double),
+                ("t_start_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double)]
 
 
 class BdlError(RuntimeError):
@@ -133,9 +157,18 @@ def load_library(path: str = LIB_PATH):
     lib.bdl_debug_export_level.argtypes = [vp, i32, u32p, f32p, vp, i64p, i64p]
     lib.bdl_debug_export_buffer.argtypes = [vp, u32p, f32p, i64p]
     lib.bdl_last_error.restype = ctypes.c_char_p
+    lib.bdl_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    lib.bdl_server_submit.argtypes = [vp, ctypes.POINTER(Request),
+                                      ctypes.POINTER(ctypes.c_uint64)]
+    lib.bdl_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Completion)]
+    lib.bdl_server_poll.argtypes = [vp, ctypes.POINTER(Completion), i32, ctypes.POINTER(i32)]
+    lib.bdl_server_drain.argtypes = [vp]
+    lib.bdl_server_destroy.argtypes = [vp]
+    lib.bdl_server_destroy.restype = None
     for name in ("bdl_create", "bdl_insert", "bdl_erase", "bdl_knn", "bdl_clear", "bdl_sync",
                  "bdl_profile", "bdl_level_sizes", "bdl_set_param", "bdl_knn_batch",
-                 "bdl_set_knn_shapes",
+                 "bdl_set_knn_shapes", "bdl_server_create", "bdl_server_submit",
+                 "bdl_server_wait", "bdl_server_poll", "bdl_server_drain",
                  "bdl_level_info", "bdl_counters", "bdl_debug_export_level",
                  "bdl_debug_export_buffer"):
         getattr(lib, name).restype = ctypes.c_int
@@ -383,3 +416,91 @@ class Tree:
 def build(verbose: bool = False) -> str:
     from .build_lib import build as _b
     return _b(verbose=verbose)
+
+
+def _completion_dict(c: "Completion") -> Dict:
+    return {f: getattr(c, f) for f, _ in Completion._fields_}
+
+
+class Server:
+    """Served form (include/bdl_server.h): a native request loop over `tree`.
+
+    Requests carry host (numpy) arrays; submit_* return a ticket, wait()
+    returns the completion (and, for k-NN, the (ids, d2) arrays).  While the
+    server exists only its loop uses the tree.
+    """
+
+    def __init__(self, tree: "Tree", mode: int = SERVE_BATCHED, max_inflight: int = 4096,
+                 max_batch_requests: int = 4096, max_batch_queries: int = 1 << 22,
+                 max_launches: int = 2, mem_budget: int = 0):
+        self._lib = load_library()
+        self.tree = tree
+        self.dim = tree.dim
+        cfg = ServerConfig(int(mode), int(max_inflight), int(max_batch_requests),
+                           int(max_launches), int(max_batch_queries), int(mem_budget))
+        h = ctypes.c_void_p()
+        _check(self._lib.bdl_server_create(tree._h, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._held = {}
+
+    def _submit(self, kind, pts, ids=None, k=0):
+        pts = np.ascontiguousarray(pts, dtype=np.float32).reshape(-1, self.dim)
+        n = pts.shape[0]
+        r = Request(kind, int(k), n, pts.ctypes.data, None, None, None)
+        keep = [pts]
+        if kind == REQ_KNN:
+            oi = np.empty((n, k), np.uint32)
+            od = np.empty((n, k), np.float32)
+            r.out_ids, r.out_d2 = oi.ctypes.data, od.ctypes.data
+            keep += [oi, od]
+        else:
+            ids = np.ascontiguousarray(ids, dtype=np.uint32).reshape(-1)
+            if ids.shape[0] != n:
+                raise ValueError("ids and points differ in length")
+            r.ids = ids.ctypes.data
+            keep.append(ids)
+        t = ctypes.c_uint64()
+        _check(self._lib.bdl_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        self._held[t.value] = keep
+        return t.value
+
+    def submit_knn(self, q, k: int) -> int:
+        return self._submit(REQ_KNN, q, k=k)
+
+    def submit_insert(self, pts, ids) -> int:
+        return self._submit(REQ_INSERT, pts, ids)
+
+    def submit_erase(self, pts, ids) -> int:
+        return self._submit(REQ_ERASE, pts, ids)
+
+    def _finish(self, c: "Completion") -> Dict:
+        out = _completion_dict(c)
+        keep = self._held.pop(c.ticket, None)
+        if c.kind == REQ_KNN and keep is not None:
+            out["ids"], out["d2"] = keep[1], keep[2]
+        return out
+
+    def wait(self, ticket: int) -> Dict:
+        c = Completion()
+        _check(self._lib.bdl_server_wait(self._h, int(ticket), ctypes.byref(c)))
+        return self._finish(c)
+
+    def poll(self, max_n: int = 1024):
+        arr = (Completion * max_n)()
+        n = ctypes.c_int32()
+        _check(self._lib.bdl_server_poll(self._h, arr, max_n, ctypes.byref(n)))
+        return [self._finish(arr[i]) for i in range(n.value)]
+
+    def drain(self) -> None:
+        _check(self._lib.bdl_server_drain(self._h))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.bdl_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -19,6 +19,7 @@
 #include "erase.hpp"
 #include "knn.hpp"
 #include "primitives.hpp"
+#include "tree_access.hpp"
 
 using namespace bdl;
 
@@ -673,6 +674,12 @@ int run_batch(bdl_tree* t, const bdl_knn_request* reqs, int nreq) {
 }
 
 }  // namespace
+
+namespace bdl {
+hipStream_t tree_stream(const bdl_tree* t) { return t->s; }
+int tree_dim(const bdl_tree* t) { return t->d; }
+int tree_fail(int code, const char* msg) { return fail(code, msg); }
+}  // namespace bdl
 
 extern "C" {
 

@@ -1,0 +1,182 @@
+"""The served form (bdl_server.h): a native request loop with admission by
+slots and memory budget and continuous batching.
+
+The central check: every result is the same alone and in the mix.  Requests
+submitted concurrently from several client threads are served with batching
+and overlap; replaying them one at a time, in the admission order the server
+reports, through the plain calls on a fresh tree must give bit-identical
+k-NN results and the same erase counts (and the oracle's, on samples)."""
+from __future__ import annotations
+
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from bdl_inputs import clustered_points, uniform_points
+from gpu_util import assert_knn_equal, log, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    t.cuda.set_device(0)
+    return t
+
+
+@pytest.fixture(scope="module")
+def bdl():
+    import paper_2112_06188_amd as m
+    m.load_library()
+    return m
+
+
+D = 3
+
+
+def _resident(bdl, torch, n=200_000, seed=1):
+    p = clustered_points(n, D, seed)
+    ids = np.arange(n, dtype=np.uint32)
+    t = bdl.Tree(D, leaf_size=16, buffer_size=1024, id_capacity=1 << 21)
+    t.insert(to_dev(p, torch), to_dev(ids, torch))
+    t.sync()
+    return t, p, ids
+
+
+def _request_streams(n_threads, n_per, seed, p0, id0):
+    """Per client thread: a list of (kind, pts, ids_or_k).  Inserts use fresh
+    ids; erases name points of the resident set or of the same thread's
+    earlier inserts (some already erased, some with wrong coordinates)."""
+    streams = []
+    for th in range(n_threads):
+        rng = np.random.default_rng(seed + th)
+        mine_p, mine_i = [p0], [np.arange(len(p0), dtype=np.uint32)]
+        nid = id0 + th * 250_000
+        out = []
+        for j in range(n_per):
+            u = rng.random()
+            if u < 0.6:
+                n = int(np.exp(rng.uniform(0, np.log(5000))))
+                q = clustered_points(n, D, int(rng.integers(1 << 30)))
+                out.append(("knn", q, int(rng.choice([1, 5, 10, 17]))))
+            elif u < 0.85:
+                n = int(np.exp(rng.uniform(0, np.log(20000))))
+                pts = uniform_points(n, D, int(rng.integers(1 << 30)))
+                ids = np.arange(nid, nid + n, dtype=np.uint32)
+                nid += n
+                mine_p.append(pts)
+                mine_i.append(ids)
+                out.append(("insert", pts, ids))
+            else:
+                allp = np.concatenate(mine_p)
+                alli = np.concatenate(mine_i)
+                m = int(min(len(alli), np.exp(rng.uniform(0, np.log(20000)))))
+                sel = rng.choice(len(alli), size=m, replace=False)
+                pts = allp[sel].copy()
+                pts[: m // 20] += 1.0  # some with wrong coordinates: no-ops
+                out.append(("erase", pts, alli[sel]))
+        streams.append(out)
+    return streams
+
+
+def _serve(bdl, srv, streams, jitter_s):
+    results = {}
+    lock = threading.Lock()
+
+    def client(ci, reqs):
+        rng = np.random.default_rng(100 + ci)
+        for j, (kind, pts, x) in enumerate(reqs):
+            if kind == "knn":
+                tk = srv.submit_knn(pts, x)
+            elif kind == "insert":
+                tk = srv.submit_insert(pts, x)
+            else:
+                tk = srv.submit_erase(pts, x)
+            with lock:
+                results[tk] = (ci, j)
+            if jitter_s:
+                time.sleep(float(rng.uniform(0, jitter_s)))
+
+    ths = [threading.Thread(target=client, args=(i, s)) for i, s in enumerate(streams)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    srv.drain()
+    comps = {}
+    while True:
+        got = srv.poll(4096)
+        if not got:
+            break
+        for c in got:
+            comps[c["ticket"]] = c
+    assert len(comps) == len(results)
+    return [(comps[tk], streams[ci][j]) for tk, (ci, j) in results.items()]
+
+
+@pytest.mark.parametrize("mode,jitter", [(1, 0.0), (1, 0.0005), (0, 0.0)])
+def test_each_result_is_the_same_alone_and_in_the_mix(torch, bdl, mode, jitter):
+    log(f"case: served mix mode={mode} jitter={jitter}")
+    t, p0, ids0 = _resident(bdl, torch)
+    srv = bdl.Server(t, mode=mode, max_inflight=64, max_batch_requests=32,
+                     max_launches=2, mem_budget=64 << 20)
+    streams = _request_streams(3, 40, 7, p0, 1 << 20)
+    served = _serve(bdl, srv, streams, jitter)
+    srv.close()
+    t.close()
+    served.sort(key=lambda x: x[0]["admit_seq"])
+    assert [c["admit_seq"] for c, _ in served] == list(range(len(served)))
+    assert all(c["status"] == 0 for c, _ in served)
+    if mode == 1:
+        # batching happened: fewer launches than k-NN requests
+        knn = [c for c, _ in served if c["kind"] == 0]
+        assert len({c["launch"] for c in knn}) < len(knn) or jitter > 0
+    # replay alone, in admission order, through the plain calls
+    r, _, _ = _resident(bdl, torch)
+    o = oracle.OracleBDL(D, 16, 1024)
+    o.insert(p0, ids0)
+    for i, (c, (kind, pts, x)) in enumerate(served):
+        if kind == "insert":
+            r.insert(to_dev(pts, torch), to_dev(x, torch))
+            o.insert(pts, x)
+        elif kind == "erase":
+            ne = r.erase(to_dev(pts, torch), to_dev(x, torch))
+            assert ne == c["n_erased"] == o.erase(pts, x), f"erase at admission {i}"
+        else:
+            gi, gd = r.knn(to_dev(pts, torch), x)
+            r.sync()
+            gi = gi.cpu().numpy().view(np.uint32)
+            gd = gd.cpu().numpy()
+            assert np.array_equal(gi, c["ids"]), f"knn ids at admission {i}"
+            assert np.array_equal(gd.view(np.uint32), c["d2"].view(np.uint32)), f"knn d2 {i}"
+            if i % 5 == 0:
+                sel = slice(0, min(40, len(pts)))
+                oi, od = o.knn(pts[sel], x)
+                assert_knn_equal(c["ids"][sel], c["d2"][sel], oi, od, f"oracle at {i}")
+    r.close()
+
+
+def test_budget_admission_and_limits(torch, bdl):
+    log("case: served budget")
+    t, p0, _ = _resident(bdl, torch, n=50_000)
+    # room for about two requests' staging at a time
+    srv = bdl.Server(t, mode=1, max_inflight=2, max_batch_requests=4, mem_budget=1 << 20)
+    q = uniform_points(3000, D, 5)
+    tickets = [srv.submit_knn(q[i * 100:(i + 1) * 100], 5) for i in range(30)]
+    with pytest.raises(bdl.BdlError):
+        srv.submit_knn(uniform_points(200_000, D, 6), 5)  # larger than the whole budget
+    outs = [srv.wait(tk) for tk in tickets]
+    with pytest.raises(bdl.BdlError):
+        srv.wait(tickets[0])  # handed out already
+    srv.close()
+    ref_i, ref_d = t.knn(to_dev(q, torch), 5)
+    t.sync()
+    gi = np.concatenate([o["ids"] for o in outs])
+    assert np.array_equal(gi, ref_i.cpu().numpy().view(np.uint32))
+    assert [o["admit_seq"] for o in outs] == list(range(30))
+    t.close()

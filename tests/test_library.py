@@ -12,11 +12,12 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "bdl.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("bdl.h", "bdl_server.h")]
 LIB = os.path.join(ROOT, "paper_2112_06188_amd", "libbdl.so")
 
 
 def _declared():
-    src = open(HEADER).read()
+    src = "".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     names = set(re.findall(r"\b(bdl_[a-z_]+)\s*\(", src))
     return names
@@ -136,8 +137,11 @@ def test_abi_struct_layouts_match_header():
     import tempfile
     import paper_2112_06188_amd as pkg
     structs = {"bdl_config": pkg.Config, "bdl_profile_t": pkg.Profile,
-               "bdl_knn_request": pkg.KnnRequest, "bdl_knn_shape": pkg.KnnShape}
-    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bdl.h"', "int main(void) {"]
+               "bdl_knn_request": pkg.KnnRequest, "bdl_knn_shape": pkg.KnnShape,
+               "bdl_server_config": pkg.ServerConfig, "bdl_request": pkg.Request,
+               "bdl_completion": pkg.Completion}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bdl_server.h"',
+             "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
@@ -165,3 +169,13 @@ def test_shape_table_rejects_bad_rows_on_the_host(lib):
     L = pkg.load_library()
     assert L.bdl_set_knn_shapes(None, None, 0) == pkg.BDL_EINVAL
     assert L.bdl_set_param(None, pkg.PARAM_PERSISTENT, 1) == pkg.BDL_EINVAL
+
+
+def test_server_rejects_bad_arguments_on_the_host(lib):
+    import paper_2112_06188_amd as pkg
+    L = pkg.load_library()
+    h = ctypes.c_void_p()
+    cfg = pkg.ServerConfig(1, 16, 64, 2, 1 << 20, 0)
+    assert L.bdl_server_create(None, ctypes.byref(cfg), ctypes.byref(h)) == pkg.BDL_EINVAL
+    assert L.bdl_server_submit(None, None, None) == pkg.BDL_EINVAL
+    assert L.bdl_server_drain(None) == pkg.BDL_EINVAL
