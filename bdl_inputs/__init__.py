@@ -35,19 +35,23 @@ def uniform_points(n: int, d: int, seed: int) -> np.ndarray:
 
 def clustered_points(n: int, d: int, seed: int, n_clusters: int = 100,
                      log10_sigma: Tuple[float, float] = (-4.0, -1.0),
-                     zipf_s: float = 1.2) -> np.ndarray:
+                     zipf_s: float = 1.2, draw_seed: Optional[int] = None) -> np.ndarray:
     """Variable-density clusters: n points from n_clusters Gaussian blobs.
 
     Centres are uniform in [0,1)^d, each blob's standard deviation is
     10**U(log10_sigma), and blob r (1-based) is chosen with probability
     proportional to r**-zipf_s.  Points are drawn in float64 and cast to
-    float32; nothing is clipped.
+    float32; nothing is clipped.  The mixture comes from `seed`; with
+    draw_seed given, the points are drawn from it instead (more points of
+    the same mixture).
     """
     rng = np.random.default_rng(seed)
     centres = rng.random((n_clusters, d))
     sigma = 10.0 ** rng.uniform(log10_sigma[0], log10_sigma[1], size=n_clusters)
     w = np.arange(1, n_clusters + 1, dtype=np.float64) ** (-zipf_s)
     w /= w.sum()
+    if draw_seed is not None:
+        rng = np.random.default_rng(draw_seed)
     which = rng.choice(n_clusters, size=n, p=w)
     out = np.empty((n, d), dtype=np.float32)
     chunk = 1 << 22
@@ -229,8 +233,64 @@ def _batched5d_20m(scale: float = 1.0, seed: int = 0) -> Workload:
                     f"({int(ins_sizes.sum())} points)", n_setup=20)
 
 
+def _served3d_50m(scale: float = 1.0, seed: int = 0) -> Workload:
+    """Served-form request log: a 3D clustered resident set of 50M points
+    (the 7D generator's mixture at d=3) built by 50 inserts of 1M (setup),
+    then 2000 requests in arrival order: 70% kNN (k=5, log-uniform 1..65536
+    fresh queries of the same mixture), 20% inserts (log-uniform 1e3..1e6
+    fresh points), 10% erases (log-uniform 1e3..1e6 ids drawn among the live
+    ones at that point of the log).  `scale` shrinks every size."""
+    d = 3
+    n_res = int(round(50_000_000 * scale))
+    nb = max(1, n_res // 50)
+    n_res = nb * 50
+    n_req = max(40, int(round(2000 * min(1.0, scale * 20))))
+    rng = np.random.default_rng(seed + 30)
+    kinds = rng.choice(np.array(["knn", "insert", "erase"]), size=n_req, p=[0.7, 0.2, 0.1])
+    lo, hi = max(1, int(1e3 * scale)), max(2, int(1e6 * scale))
+    sizes = {"knn": log_uniform_sizes(rng, n_req, 1, max(2, int(65536 * min(1.0, scale * 20)))),
+             "insert": log_uniform_sizes(rng, n_req, lo, hi),
+             "erase": log_uniform_sizes(rng, n_req, lo, hi)}
+    n_new = int(sum(sizes["insert"][i] for i in range(n_req) if kinds[i] == "insert"))
+    pts = clustered_points(n_res + n_new, d, seed)
+    ids = np.arange(pts.shape[0], dtype=np.uint32)
+    n_q = int(sum(sizes["knn"][i] for i in range(n_req) if kinds[i] == "knn"))
+    q = clustered_points(n_q, d, seed, draw_seed=seed + 40)
+    alive = np.zeros(pts.shape[0], dtype=bool)
+    alive[:n_res] = True
+    ops: List[Op] = [Op("insert", pts[b * nb:(b + 1) * nb], ids[b * nb:(b + 1) * nb])
+                     for b in range(50)]
+    qo, po = 0, n_res
+    for i in range(n_req):
+        kind = str(kinds[i])
+        if kind == "knn":
+            m = int(sizes["knn"][i])
+            ops.append(Op("knn", q[qo:qo + m], k=5))
+            qo += m
+        elif kind == "insert":
+            m = int(sizes["insert"][i])
+            ops.append(Op("insert", pts[po:po + m], ids[po:po + m]))
+            alive[po:po + m] = True
+            po += m
+        else:
+            m = int(sizes["erase"][i])
+            # draw among the inserted ids, keep live ones (resampling a few
+            # times), so that the erase names m live points where possible
+            cand = np.unique(rng.integers(0, po, size=int(m * 1.3) + 16))
+            cand = cand[alive[cand]]
+            rng.shuffle(cand)
+            e = cand[:m].astype(np.uint32)
+            alive[e.astype(np.int64)] = False
+            ops.append(Op("erase", pts[e.astype(np.int64)], e))
+    return Workload("served3d_50m", d, 16, 1024, int(pts.shape[0]), ops,
+                    f"3D clustered, {n_res} resident, {n_req} requests "
+                    f"(70/20/10 kNN/insert/erase), {n_q} queries k=5, {n_new} inserted",
+                    n_setup=50)
+
+
 WORKLOADS = {
     "uniform2d_small": _uniform_small,
+    "served3d_50m": _served3d_50m,
     "batched5d_20m": _batched5d_20m,
     "uniform3d_10m": _uniform3d_10m,
     "clustered7d_10m": _clustered7d,

@@ -13,7 +13,13 @@ call (bdl_knn per batch) and once in the batched form (bdl_knn_batch over
 the kNN batches between two inserts, replayed hipGraphs), both with the
 autotuned launch shapes; results must be identical.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--form plain|batched]
+--form served: a 50M-point 3D clustered resident set and 2000 requests
+(70% kNN_L k=5, 20% Insert_L, 10% Erase_L) arriving as a Poisson stream at
+0.5, 0.8 and 0.95 of the FIFO loop's saturation rate, served by the native
+request loop in FIFO mode and with continuous batching; p50/p99 latency and
+throughput of both, and the k-NN results of the two compared.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--form plain|batched|served]
 """
 from __future__ import annotations
 
@@ -145,7 +151,7 @@ def gpu_bench(args):
         "dtype": "f32",
         "data": "synthetic (seeded uniform float32 points in [0,1)^3)",
         "config": {"workload": w.name, "n_points": n_ins, "dim": w.dim, "k": k,
-                   "knn_kernel": ["lane", "wave"][args.knn_kernel],
+                   "knn_kernel": ["lane", "wave", "auto"][args.knn_kernel],
                    "insert_batches": len(inserts), "erase_points": n_er, "queries": nq,
                    "leaf_size": w.leaf_size, "buffer_size": w.buffer_size},
         "knn_queries_per_s": nq / (knn_ms * 1e-3),
@@ -334,6 +340,117 @@ def batched_bench(args):
     }
 
 
+def served_bench(args):
+    """FIFO loop vs continuous batching on one Poisson request stream."""
+    import torch
+
+    import paper_2112_06188_amd as bdl
+    from bdl_inputs import workload
+
+    torch.cuda.set_device(0)
+    t_gen = time.perf_counter()
+    w = workload("served3d_50m", scale=args.scale)
+    t_gen = time.perf_counter() - t_gen
+    setup = [(_dv(torch, op.pts), _dv(torch, op.ids)) for op in w.ops[:w.n_setup]]
+    reqs = w.ops[w.n_setup:]
+    tree = bdl.Tree(w.dim, leaf_size=w.leaf_size, buffer_size=w.buffer_size,
+                    id_capacity=w.id_capacity)
+
+    def rebuild():
+        tree.clear()
+        for p, i in setup:
+            tree.insert(p, i)
+        tree.sync()
+
+    rebuild()
+    budget = int(torch.cuda.mem_get_info()[0] // 2)
+    print(f"served: {w.description}; staging budget {budget >> 20} MiB", file=sys.stderr,
+          flush=True)
+
+    def run(mode, rate, seed=5):
+        rebuild()
+        srv = bdl.Server(tree, mode=mode, max_inflight=4096, max_batch_requests=4096,
+                         max_batch_queries=1 << 22, max_launches=2, mem_budget=budget)
+        n = len(reqs)
+        if rate:
+            at = np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, size=n))
+        else:
+            at = np.zeros(n)
+        tickets = []
+        t0 = time.perf_counter()
+        for a, op in zip(at, reqs):
+            while True:
+                dt = t0 + a - time.perf_counter()
+                if dt <= 0:
+                    break
+                time.sleep(dt if dt > 2e-3 else 0)
+            if len(tickets) % 500 == 499:
+                print(f"served: {len(tickets) + 1} submitted at {time.perf_counter() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
+            if op.kind == "knn":
+                tickets.append(srv.submit_knn(op.pts, op.k))
+            elif op.kind == "insert":
+                tickets.append(srv.submit_insert(op.pts, op.ids))
+            else:
+                tickets.append(srv.submit_erase(op.pts, op.ids))
+        comps = [srv.wait(tk) for tk in tickets]
+        srv.close()
+        lat = np.array([c["t_done_ms"] - c["t_submit_ms"] for c in comps])
+        klat = np.array([c["t_done_ms"] - c["t_submit_ms"] for c in comps if c["kind"] == 0])
+        span_s = (max(c["t_done_ms"] for c in comps) - min(c["t_submit_ms"] for c in comps)) / 1e3
+        st = {"requests_per_s": n / span_s, "seconds": span_s,
+              "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                             "p99": float(np.percentile(lat, 99))},
+              "knn_latency_ms": {"p50": float(np.percentile(klat, 50)),
+                                 "p99": float(np.percentile(klat, 99))},
+              "launches": int(len({c["launch"] for c in comps})),
+              "failed": int(sum(c["status"] != 0 for c in comps))}
+        if rate:
+            st["offered_requests_per_s"] = rate
+        print(f"served: mode {mode} rate {rate}: {json.dumps(st)}", file=sys.stderr, flush=True)
+        return st, comps
+
+    out = {}
+    print("served: saturation runs", file=sys.stderr, flush=True)
+    sat_fifo, comps_fifo = run(bdl.SERVE_FIFO, None)
+    sat_bat, comps_bat = run(bdl.SERVE_BATCHED, None)
+    same = all(np.array_equal(a["ids"], b["ids"]) and
+               np.array_equal(a["d2"].view(np.uint32), b["d2"].view(np.uint32))
+               for a, b in zip(comps_fifo, comps_bat) if a["kind"] == 0)
+    erased_same = all(a["n_erased"] == b["n_erased"] for a, b in zip(comps_fifo, comps_bat))
+    del comps_fifo, comps_bat
+    out["saturation"] = {"fifo": sat_fifo, "batched": sat_bat}
+    rate = sat_fifo["requests_per_s"]
+    for lam in (0.5, 0.8, 0.95):
+        row = {}
+        for name, mode in (("fifo", bdl.SERVE_FIFO), ("batched", bdl.SERVE_BATCHED)):
+            print(f"served: lambda {lam} {name}", file=sys.stderr, flush=True)
+            row[name], _ = run(mode, lam * rate)
+        out[f"lambda_{lam}"] = row
+    tree.close()
+    hi = out["lambda_0.95"]
+    return {
+        "metric": "served form: request throughput and p50/p99 latency under a Poisson "
+                  "stream (3D clustered, 50M resident, 70/20/10 kNN/insert/erase)",
+        "value": sat_bat["requests_per_s"],
+        "unit": "requests/s (saturation, continuous batching)",
+        "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": sat_bat["seconds"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded 3D Gaussian-blob mixture, float32)",
+        "config": {"workload": w.name, "requests": len(reqs),
+                   "resident_points": sum(p.shape[0] for p, _ in setup),
+                   "staging_budget_bytes": budget},
+        "saturation_speedup_batched_over_fifo":
+            sat_bat["requests_per_s"] / sat_fifo["requests_per_s"],
+        "p99_ratio_fifo_over_batched_at_0.95": hi["fifo"]["latency_ms"]["p99"] /
+            hi["batched"]["latency_ms"]["p99"],
+        "results_identical_fifo_vs_batched": bool(same and erased_same),
+        "runs": out,
+        "generation_seconds": t_gen,
+    }
+
+
 def cpu_baseline(w, gpu_out, n_sample: int):
     """The oracle on the host: the full update sequence, then kNN_L on a
     sample of the queries; throughput in the benchmark's unit (the kNN time
@@ -391,11 +508,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="uniform3d_10m")
     ap.add_argument("--scale", type=float, default=1.0)
-    ap.add_argument("--knn-kernel", type=int, default=1, choices=[0, 1],
-                    help="0: one lane per query, 1: one wavefront per 64 queries")
+    ap.add_argument("--knn-kernel", type=int, default=2, choices=[0, 1, 2],
+                    help="0: one lane per query, 1: one wavefront per 64 queries, "
+                         "2: chosen per launch from the query density")
     ap.add_argument("--cpu-sample", type=int, default=200_000,
                     help="queries the CPU oracle answers for the baseline (0: skip)")
-    ap.add_argument("--form", default="plain", choices=["plain", "batched"])
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "served"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -403,6 +521,9 @@ def main():
         sys.exit(2)
     if args.form == "batched":
         print(json.dumps(batched_bench(args)), flush=True)
+        return
+    if args.form == "served":
+        print(json.dumps(served_bench(args)), flush=True)
         return
     res, w, gpu_out = gpu_bench(args)
     if args.cpu_sample > 0:

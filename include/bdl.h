@@ -106,7 +106,10 @@ int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_id
 
 /* Tuning parameters (bdl_set_param).  They change speed, never results. */
 #define BDL_PARAM_KNN_KERNEL 1 /* 0: one lane per query; 1: one wavefront per
-                                  64 neighbouring queries (default) */
+                                  64 neighbouring queries; 2 (default): the
+                                  wavefront kernel when a launch has at least
+                                  65536 queries and half as many as live
+                                  points, else one lane per query */
 #define BDL_PARAM_SORT_MIN 2   /* query batches of at least this many queries
                                   are visited in Morton order (default 4096) */
 #define BDL_PARAM_KNN_BLOCK 3  /* k-NN workgroup size: 64, 128 or 256 (default) */
@@ -115,7 +118,8 @@ int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_id
 #define BDL_PARAM_PERSISTENT 5 /* 1: a k-NN batch larger than the device holds at
                                   once runs on a resident grid that draws groups
                                   of 64 queries from per-XCD work counters;
-                                  0 (default): one wavefront per group */
+                                  0: one wavefront per group; 2 (default): 1 for
+                                  the wavefront kernel, 0 for the lane kernel */
 int bdl_set_param(bdl_tree* t, int32_t param, int64_t value);
 
 /* One row of a launch-shape table for kNN_L (bdl_knn and bdl_knn_batch).  A

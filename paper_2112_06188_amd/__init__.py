@@ -46,6 +46,7 @@ PARAM_PERSISTENT = 5
 MAX_SHAPES = 256
 KNN_LANE = 0
 KNN_WAVE = 1
+KNN_AUTO = 2
 PHASES = ["gather", "passes", "finish", "layout", "erase", "order", "traverse", "other"]
 
 

@@ -23,6 +23,7 @@ constexpr uint64_t kSortQueriesMin = 4096;
 // neighbouring queries.
 constexpr int kKnnLane = 0;
 constexpr int kKnnWave = 1;
+constexpr int kKnnAuto = 2;  // chosen per launch from the query density
 
 // One k-NN request as the kernels see it: its queries, k and outputs, and
 // the position of its first query in the concatenated query array.

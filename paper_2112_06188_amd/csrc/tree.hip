@@ -68,10 +68,10 @@ struct bdl_tree {
   float* rbuf = nullptr;        // Erase_L's gathered points R (records)
   int64_t rbuf_cap = 0;
   int64_t rebuilt = 0, reinserted = 0;
-  int knn_mode = kKnnWave;
+  int knn_mode = kKnnAuto;
   int knn_block = 256;
   int use_graphs = 1;
-  int persistent = 0;
+  int persistent = 2;  // 2: on for the wavefront kernel
   uint64_t sort_min = kSortQueriesMin;
   std::vector<bdl_knn_shape> shapes;  // launch-shape table (autotuned)
   uint32_t* d_queue = nullptr;        // work counters of persistent k-NN launches
@@ -571,8 +571,15 @@ int kmax_bucket(int mode, int kmax) {
 KnnLaunch choose_launch(const bdl_tree* t, int kmax, uint64_t nq, bool* sort) {
   KnnLaunch L;
   L.mode = t->knn_mode;
+  if (L.mode == kKnnAuto) {
+    // the wavefront kernel pays off when the queries are dense among the
+    // points (Morton-adjacent queries then share most of their paths);
+    // sparse queries take one lane each
+    const int64_t live = bdl_size(t);
+    L.mode = (nq >= 65536 && (int64_t)nq * 2 >= live) ? kKnnWave : kKnnLane;
+  }
   L.block = t->knn_block;
-  L.persistent = t->persistent;
+  L.persistent = t->persistent == 2 ? (L.mode == kKnnWave ? 1 : 0) : t->persistent;
   L.queue = t->d_queue;
   bool srt = nq >= t->sort_min;
   for (const bdl_knn_shape& r : t->shapes) {
@@ -805,7 +812,8 @@ int bdl_set_param(bdl_tree* t, int32_t param, int64_t value) {
   if (!t) return fail(BDL_EINVAL, "null tree");
   switch (param) {
     case BDL_PARAM_KNN_KERNEL:
-      if (value != kKnnLane && value != kKnnWave) return fail(BDL_EINVAL, "unknown k-NN kernel");
+      if (value != kKnnLane && value != kKnnWave && value != kKnnAuto)
+        return fail(BDL_EINVAL, "unknown k-NN kernel");
       t->knn_mode = (int)value;
       return 0;
     case BDL_PARAM_SORT_MIN:
@@ -822,7 +830,7 @@ int bdl_set_param(bdl_tree* t, int32_t param, int64_t value) {
       t->use_graphs = (int)value;
       return 0;
     case BDL_PARAM_PERSISTENT:
-      if (value != 0 && value != 1) return fail(BDL_EINVAL, "persistent is 0 or 1");
+      if (value < 0 || value > 2) return fail(BDL_EINVAL, "persistent is 0, 1 or 2");
       t->persistent = (int)value;
       return 0;
     default:

@@ -72,9 +72,9 @@ def test_persistent_grid_matches_plain_launch(torch, bdl, loaded, k):
                 else:
                     assert torch.equal(gi, base[0])
                     assert torch.equal(gd.view(torch.int32), base[1].view(torch.int32))
-    t.set_param(bdl.PARAM_KNN_KERNEL, 1)
+    t.set_param(bdl.PARAM_KNN_KERNEL, bdl.KNN_AUTO)
     t.set_param(bdl.PARAM_KNN_BLOCK, 256)
-    t.set_param(bdl.PARAM_PERSISTENT, 0)
+    t.set_param(bdl.PARAM_PERSISTENT, 2)
 
 
 def test_batched_persistent_with_graph_replays(torch, bdl, loaded):
@@ -92,7 +92,7 @@ def test_batched_persistent_with_graph_replays(torch, bdl, loaded):
         t.sync()
         for (ri, rd), (gi, gd) in zip(ref, outs):
             assert torch.equal(gi, ri) and torch.equal(gd.view(torch.int32), rd.view(torch.int32))
-    t.set_param(bdl.PARAM_PERSISTENT, 0)
+    t.set_param(bdl.PARAM_PERSISTENT, 2)
 
 
 def test_shape_table_routes_by_k_and_count(torch, bdl, loaded):
