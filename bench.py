@@ -38,6 +38,33 @@ if ROOT not in sys.path:
 
 METRIC = "kNN queries/s + update pts/s, 10M 3D pts k=5; p50/p99 latency under mixed load"
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of the traversal kernel measured with rocprofv3 counters
+# (FETCH_SIZE, WRITE_SIZE) and the sources it was measured on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "knn_traversal_traffic.json")
+TRAVERSAL_SOURCES = [os.path.join(ROOT, "paper_2112_06188_amd", "csrc", f)
+                     for f in ("knn_traverse.hpp", "knn_d1_4.hip")]
+
+
+def traversal_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAVERSAL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Bytes per traversal launch from the committed counter measurement, or
+    None when there is none or the kernel's sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != traversal_source_hash():
+        return None
+    return t.get("bytes_per_launch")
 
 
 def _pct(xs, p):
@@ -53,6 +80,15 @@ def gpu_bench(args):
     torch.cuda.set_device(0)
     w = workload(args.workload, scale=args.scale)
     dev = torch.device("cuda", 0)
+    if args.copy_probe_mib:
+        # a plain copy of known size, for scaling the HBM counters of a
+        # profiled run (reads and writes copy_probe_mib MiB once)
+        n = args.copy_probe_mib << 18
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
 
     def dv(a):
         a = np.ascontiguousarray(a)
@@ -165,9 +201,10 @@ def gpu_bench(args):
         "final_levels": [i for i in range(64) if (info["F"] >> i) & 1],
         "buffer_points": info["buf_live"],
         "self_match_all_queries": self_ok,
-        "roofline": {"kernel": "k_knn (kNN_L traversal)", "bound": "hbm",
+        "roofline": {"kernel": ("k_knn" if args.knn_kernel == 0 else "k_knn_wave")
+                     + " (kNN_L traversal)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": trav_ms},
     }
@@ -224,7 +261,8 @@ def batched_bench(args):
     t0 = time.perf_counter()
     tuned = autotune.tune(tree, lambda n: tq[:n], k_bands=((1, 1), (2, 5), (6, 10)),
                           nq_bands=((1, 2048), (2049, 32768), (32769, 1 << 40)),
-                          max_nq=1 << 20, reps=2)
+                          max_nq=1 << 20, reps=2,
+                          log=lambda m: print(f"batched: tune {m}", file=sys.stderr, flush=True))
     tune_s = time.perf_counter() - t0
     stream = torch.cuda.current_stream()
 
@@ -282,6 +320,7 @@ def batched_bench(args):
             ins_s.append(sum(a.elapsed_time(b) for a, b in ins) / 1e3)
         sec = float(np.median(times))
         ins_sec = float(np.median(ins_s))
+        print(f"batched: {name} {sec:.3f} s (inserts {ins_sec:.3f} s)", file=sys.stderr, flush=True)
         res[name] = {"seconds": sec, "ops_per_s": (n_q + n_ins) / sec,
                      "insert_seconds": ins_sec,
                      "knn_queries_per_s": n_q / max(1e-9, sec - ins_sec)}
@@ -514,6 +553,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=200_000,
                     help="queries the CPU oracle answers for the baseline (0: skip)")
     ap.add_argument("--form", default="plain", choices=["plain", "batched", "served"])
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
