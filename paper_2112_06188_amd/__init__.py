@@ -125,11 +125,13 @@ class Config(ctypes.Structure):
 _lib = None
 
 
-def load_library(path: str = LIB_PATH):
-    """Load libbdl.so and declare its signatures (no GPU needed)."""
+def load_library(path: Optional[str] = None):
+    """Load libbdl.so (or the library BDL_LIBRARY names) and declare its
+    signatures (no GPU needed)."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("BDL_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise FileNotFoundError(
             f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")

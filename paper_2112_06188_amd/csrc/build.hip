@@ -91,16 +91,6 @@ __device__ inline uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
-// largest s with segtb[s] <= t (segtb strictly increasing, segtb[0] = 0)
-__device__ inline uint32_t find_seg(const uint32_t* segtb, uint32_t ns, uint32_t t) {
-  uint32_t lo = 0, hi = ns - 1;
-  while (lo < hi) {
-    uint32_t mid = (lo + hi + 1) >> 1;
-    if (segtb[mid] <= t) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 // ------------------------------------------------------------------------
 // gather
 // ------------------------------------------------------------------------
@@ -338,12 +328,17 @@ __global__ void k_init_lists(const Job* jobs, int njobs, BuildCounters* c, Seg* 
 // ------------------------------------------------------------------------
 
 // Decide every segment of this depth: emit its node, pick its split (or mark
-// it a leaf copied out whole), and number its tiles.
+// it a leaf copied out whole), number its tiles, and record the segment of
+// every tile (tile_seg) so that the tile kernels need no search.
+constexpr uint32_t kSetupLds = 4096;  // segments whose tile starts stay in LDS
+
 __global__ void __launch_bounds__(1024)
-k_setup(Seg* cur, uint32_t* segtb, BuildCounters* c, int par, const Job* jobs, uint32_t* emit,
-        int es, int d, uint32_t leaf, uint64_t max_emit, uint64_t max_seg, uint64_t max_tiles) {
+k_setup(Seg* cur, uint32_t* segtb, uint32_t* tile_seg, BuildCounters* c, int par,
+        const Job* jobs, uint32_t* emit, int es, int d, uint32_t leaf, uint64_t max_emit,
+        uint64_t max_seg, uint64_t max_tiles) {
   __shared__ uint32_t wsum[17];
   __shared__ uint32_t s_base, s_n;
+  __shared__ uint32_t s_tb[kSetupLds];
   if (threadIdx.x == 0) {
     uint32_t nn = c->nseg[par];
     if (nn > max_seg || c->err) {
@@ -397,28 +392,41 @@ k_setup(Seg* cur, uint32_t* segtb, BuildCounters* c, int par, const Job* jobs, u
       cur[s].tile_begin = carry + ex;
       cur[s].ntiles = ntl;
       segtb[s] = carry + ex;
+      if (s < kSetupLds) s_tb[s] = carry + ex;
     }
     carry += tot;
   }
+  const bool over = carry > max_tiles;
   if (threadIdx.x == 0) {
-    if (carry > max_tiles) {
+    if (over) {
       c->err |= 256u;
       c->nseg[par] = 0;
-      carry = 0;
     }
-    c->ntiles = carry;
+    c->ntiles = over ? 0u : carry;
     c->nemit = s_base + n;
+  }
+  if (over || n == 0) return;
+  __threadfence_block();
+  __syncthreads();
+  // segment of every tile: the largest s with tile start <= t
+  const uint32_t* tb = n <= kSetupLds ? s_tb : segtb;
+  for (uint32_t t = threadIdx.x; t < carry; t += blockDim.x) {
+    uint32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (tb[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    tile_seg[t] = lo;
   }
 }
 
 __global__ void __launch_bounds__(kPassThreads)
-k_count(const Seg* cur, const uint32_t* segtb, const BuildCounters* c, int par,
+k_count(const Seg* cur, const uint32_t* tile_seg, const BuildCounters* c,
         const float* src, uint64_t cap, uint32_t* tile_left) {
   __shared__ uint32_t red[4];
   const uint32_t nt = c->ntiles;
-  const uint32_t ns = c->nseg[par];
   for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
-    const uint32_t s = find_seg(segtb, ns, t);
+    const uint32_t s = tile_seg[t];
     const Seg& g = cur[s];
     const int dim = g.dim;
     if (dim < 0) {
@@ -522,20 +530,19 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
 // the tight boxes of children that stay in the global passes; leaves that
 // are too large for the finisher (coincident points) are copied out whole.
 __global__ void __launch_bounds__(kPassThreads)
-k_scatter(const Seg* cur, const uint32_t* segtb, Seg* nxt, const BuildCounters* c, int par,
+k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounters* c,
           const float* src, float* dst, uint64_t cap, int d, const uint32_t* tile_off,
           const Job* jobs, uint64_t* map, uint32_t idcap) {
   __shared__ uint32_t lt[kItems][4];
   __shared__ uint32_t red[4][4];
   const uint32_t nt = c->ntiles;
-  const uint32_t ns = c->nseg[par];
   const int lane = __lane_id();
   const int w = threadIdx.x >> 6;
   const uint64_t ltm = lanemask_lt();
   const uint32_t* sid = soa_ids(src, d, cap);
   uint32_t* did = soa_ids_w(dst, d, cap);
   for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
-    const uint32_t s = find_seg(segtb, ns, t);
+    const uint32_t s = tile_seg[t];
     const Seg& g = cur[s];
     const uint64_t gbegin = g.begin;
     const uint64_t tstart = gbegin + (uint64_t)(t - g.tile_begin) * kTile;
@@ -663,15 +670,14 @@ struct Act {
   uint64_t path;
 };
 
-template <int DMAX, int TCAP, int MAXACT>
-__global__ void __launch_bounds__(256)
+template <int DMAX, int TCAP, int MAXACT, int NT>
+__global__ void __launch_bounds__(NT)
 k_finish(const Fin* fin, uint32_t nfin, const float* soa0, const float* soa1, uint64_t cap,
          int d, uint32_t leaf, const Job* jobs, uint32_t* emit, int es, BuildCounters* c,
          uint64_t* map, uint32_t idcap, uint64_t max_emit) {
-  constexpr int PT = TCAP / 256;
+  constexpr int PT = (TCAP + NT - 1) / NT;
   constexpr int MAXCH = 2 * MAXACT;
-  static_assert(MAXCH <= 256, "one child per thread");
-  static_assert(TCAP % 256 == 0, "blocked scan");
+  static_assert(MAXCH <= NT, "one child per thread");
   __shared__ float xs[DMAX][TCAP];
   __shared__ uint32_t ids[TCAP];
   __shared__ uint16_t pos[2][TCAP];
@@ -697,7 +703,7 @@ k_finish(const Fin* fin, uint32_t nfin, const float* soa0, const float* soa1, ui
     const float* src = F.bufsel ? soa1 : soa0;
     const uint32_t* srcid = soa_ids(src, d, cap);
     const Job J = jobs[F.job];
-    for (uint32_t i = tid; i < n; i += 256) {
+    for (uint32_t i = tid; i < n; i += NT) {
       for (int j = 0; j < d; ++j) xs[j][i] = src[(uint64_t)j * cap + F.begin + i];
       ids[i] = srcid[F.begin + i];
       pos[0][i] = (uint16_t)i;
@@ -714,7 +720,7 @@ k_finish(const Fin* fin, uint32_t nfin, const float* soa0, const float* soa1, ui
     // child boxes by a segmented min/max over positions (children are
     // contiguous runs of equal sid)
     auto child_boxes = [&](int buf) {
-      for (uint32_t b0 = 0; b0 < n; b0 += 256) {
+      for (uint32_t b0 = 0; b0 < n; b0 += NT) {
         const uint32_t i = b0 + tid;
         const bool valid = i < n;
         const uint32_t key = valid ? (uint32_t)sidv[buf][i] : (uint32_t)kFrozen;
@@ -835,7 +841,7 @@ k_finish(const Fin* fin, uint32_t nfin, const float* soa0, const float* soa1, ui
           (s_base == 0xFFFFFFFFu || s_nact > (uint32_t)MAXACT) ? 0u : s_nact;
       if (nact == 0) break;
       // ---- point each position at its node in the new table ----
-      for (uint32_t i = tid; i < n; i += 256) {
+      for (uint32_t i = tid; i < n; i += NT) {
         uint16_t s = sidv[cur][i];
         if (s != kFrozen) sidv[cur][i] = remap[s];
       }
@@ -866,13 +872,13 @@ k_finish(const Fin* fin, uint32_t nfin, const float* soa0, const float* soa1, ui
       }
       if (tid == 0) L[n] = (uint16_t)tot;
       __syncthreads();
-      for (uint32_t a = tid; a < nact; a += 256) {
+      for (uint32_t a = tid; a < nact; a += NT) {
         Act& A = act[ca][a];
         A.nleft = (uint16_t)(L[A.begin + A.count] - L[A.begin]);
       }
       __syncthreads();
       // ---- stable scatter into the other position buffer ----
-      for (uint32_t i = tid; i < n; i += 256) {
+      for (uint32_t i = tid; i < n; i += NT) {
         const uint16_t s = sidv[cur][i];
         const uint16_t p = pos[cur][i];
         if (s == kFrozen) {
@@ -889,7 +895,7 @@ k_finish(const Fin* fin, uint32_t nfin, const float* soa0, const float* soa1, ui
         }
       }
       nch = 2 * nact;
-      for (uint32_t e = tid; e < nch * 2 * DMAX; e += 256) {
+      for (uint32_t e = tid; e < nch * 2 * DMAX; e += NT) {
         const uint32_t j = e % (2 * DMAX);
         cbox[e / (2 * DMAX)][j] = j < (uint32_t)DMAX ? 0xFFFFFFFFu : 0u;
       }
@@ -899,7 +905,7 @@ k_finish(const Fin* fin, uint32_t nfin, const float* soa0, const float* soa1, ui
       __syncthreads();
     }
     // ---- write the subtree's points in final slot order ----
-    for (uint32_t i = tid; i < n; i += 256) {
+    for (uint32_t i = tid; i < n; i += NT) {
       const uint16_t p = pos[cur][i];
       const uint64_t slot = (uint64_t)F.begin + i - J.base;
       float* rr = J.rec + slot * S;
@@ -1012,11 +1018,11 @@ inline unsigned grid_for(uint64_t n, unsigned threads, unsigned cap = 4096) {
   return (unsigned)g;
 }
 
-template <int DMAX, int TCAP, int MAXACT>
+template <int DMAX, int TCAP, int MAXACT, int NT>
 void launch_finish(uint32_t nfin, const BuildScratch& sc, int d, uint32_t leaf, uint64_t* map,
                    uint32_t idcap, hipStream_t s) {
   unsigned g = nfin < 65535u ? nfin : 65535u;
-  hipLaunchKernelGGL((k_finish<DMAX, TCAP, MAXACT>), dim3(g), dim3(256), 0, s, sc.fin, nfin,
+  hipLaunchKernelGGL((k_finish<DMAX, TCAP, MAXACT, NT>), dim3(g), dim3(NT), 0, s, sc.fin, nfin,
                      sc.soa[0], sc.soa[1], sc.cap, d, leaf, sc.jobs, sc.emit, emit_stride(d),
                      sc.ctr, map, idcap, sc.max_emit);
 }
@@ -1024,11 +1030,14 @@ void launch_finish(uint32_t nfin, const BuildScratch& sc, int d, uint32_t leaf, 
 }  // namespace
 
 // Finisher configurations: (max dim, LDS point capacity, max internal nodes
-// per depth).  The threshold also guarantees that one depth of a finisher
-// subtree has at most MAXACT internal nodes (each holds > leaf points).
+// per depth, threads).  The threshold also guarantees that one depth of a
+// finisher subtree has at most MAXACT internal nodes (each holds > leaf
+// points).  For d <= 3 a workgroup takes 74 KB of LDS, so two share a CU
+// (12 waves each); the finisher is bound by LDS latency and barriers, and
+// measured faster this way than with one larger workgroup per CU.
 uint32_t finisher_threshold(int d, int leaf_size) {
   uint32_t tcap, maxact;
-  if (d <= 3) { tcap = 1792; maxact = 128; }
+  if (d <= 3) { tcap = 2304; maxact = 144; }
   else if (d <= 8) { tcap = 1024; maxact = 64; }
   else { tcap = 512; maxact = 32; }
   uint64_t t = (uint64_t)maxact * (uint64_t)(leaf_size + 1);
@@ -1043,7 +1052,7 @@ size_t build_scratch_bytes(uint64_t cap, int d, uint32_t T) {
   size_t b = 0;
   b += 2 * (size_t)(d + 1) * cap * 4;
   b += 2 * max_seg * (sizeof(Seg) + 4);
-  b += 2 * max_tiles * 4;
+  b += 3 * max_tiles * 4;
   b += max_fin * sizeof(Fin);
   b += max_emit * (size_t)emit_stride(d) * 4;
   b += 2 * max_emit * 12 + max_emit * 4;
@@ -1139,17 +1148,17 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
   while (true) {
     for (int b = 0; b < budget; ++b, ++depth) {
       const int par = depth & 1;
-      hipLaunchKernelGGL(k_setup, dim3(1), dim3(1024), 0, s, sc.seg[par], sc.segtb[par], sc.ctr,
-                         par, sc.jobs, sc.emit, es, d, leaf, sc.max_emit, sc.max_seg,
-                         sc.max_tiles);
+      hipLaunchKernelGGL(k_setup, dim3(1), dim3(1024), 0, s, sc.seg[par], sc.segtb[par],
+                         sc.tile_seg, sc.ctr, par, sc.jobs, sc.emit, es, d, leaf, sc.max_emit,
+                         sc.max_seg, sc.max_tiles);
       hipLaunchKernelGGL(k_count, dim3(pass_grid), dim3(kPassThreads), 0, s, sc.seg[par],
-                         sc.segtb[par], sc.ctr, par, sc.soa[par], sc.cap, sc.tile_left);
+                         sc.tile_seg, sc.ctr, sc.soa[par], sc.cap, sc.tile_left);
       hipLaunchKernelGGL(k_tilescan, dim3(1), dim3(1024), 0, s, sc.seg[par], sc.seg[par ^ 1],
                          sc.ctr, par, sc.tile_left, sc.tile_off, sc.fin, T, sc.max_seg,
                          sc.max_fin);
       hipLaunchKernelGGL(k_scatter, dim3(pass_grid), dim3(kPassThreads), 0, s, sc.seg[par],
-                         sc.segtb[par], sc.seg[par ^ 1], sc.ctr, par, sc.soa[par],
-                         sc.soa[par ^ 1], sc.cap, d, sc.tile_off, sc.jobs, map, idcap);
+                         sc.tile_seg, sc.seg[par ^ 1], sc.ctr, sc.soa[par], sc.soa[par ^ 1],
+                         sc.cap, d, sc.tile_off, sc.jobs, map, idcap);
     }
     pt.end(BDL_PH_PASSES);
     if (hipMemcpyAsync(sc.host_ctr, sc.ctr, sizeof(BuildCounters), hipMemcpyDeviceToHost, s) !=
@@ -1171,9 +1180,9 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
   const uint32_t nfin = sc.host_ctr->nfin;
   pt.begin(BDL_PH_FINISH);
   if (nfin) {
-    if (d <= 3) launch_finish<3, 1792, 128>(nfin, sc, d, leaf, map, idcap, s);
-    else if (d <= 8) launch_finish<8, 1024, 64>(nfin, sc, d, leaf, map, idcap, s);
-    else launch_finish<16, 512, 32>(nfin, sc, d, leaf, map, idcap, s);
+    if (d <= 3) launch_finish<3, 2304, 144, 768>(nfin, sc, d, leaf, map, idcap, s);
+    else if (d <= 8) launch_finish<8, 1024, 64, 256>(nfin, sc, d, leaf, map, idcap, s);
+    else launch_finish<16, 512, 32, 256>(nfin, sc, d, leaf, map, idcap, s);
   }
   pt.end(BDL_PH_FINISH);
   if (hipMemcpyAsync(sc.host_ctr, sc.ctr, sizeof(BuildCounters), hipMemcpyDeviceToHost, s) !=
