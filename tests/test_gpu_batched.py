@@ -113,3 +113,47 @@ def test_graph_replays_across_updates(torch, bdl):
             oi, od = o.knn(q, k)
             assert_knn_equal(gi.cpu().numpy(), gd.cpu().numpy(), oi, od, f"replay rnd={rnd}")
     t.close()
+
+
+def test_batched_oplog_matches_plain_and_oracle(torch, bdl):
+    """The batched-form op log (5D, uneven kNN batches with k in {1,5,10},
+    an insert after every 32nd batch) at reduced scale: the batched calls
+    (one per run of kNN batches between inserts) give the plain per-call
+    results bit for bit, and the oracle's on the first rows of every batch."""
+    from bdl_inputs import workload
+    w = workload("batched5d_20m", scale=0.02)
+    log(f"case: batched op log: {w.description}")
+    trees = [bdl.Tree(w.dim, leaf_size=w.leaf_size, buffer_size=w.buffer_size,
+                      id_capacity=w.id_capacity) for _ in range(2)]
+    o = oracle.OracleBDL(w.dim, w.leaf_size, w.buffer_size)
+    for op in w.ops[:w.n_setup]:
+        for t in trees:
+            t.insert(to_dev(op.pts, torch), to_dev(op.ids, torch))
+        o.insert(op.pts, op.ids)
+    plain, batched, pend = [], [], []
+
+    def flush():
+        if pend:
+            batched.extend(trees[1].knn_batch([(to_dev(q, torch), k) for q, k in pend]))
+            pend.clear()
+
+    for op in w.ops[w.n_setup:]:
+        if op.kind == "knn":
+            plain.append(trees[0].knn(to_dev(op.pts, torch), op.k))
+            pend.append((op.pts, op.k))
+            oi, od = o.knn(op.pts[:16], op.k)
+            plain[-1] = plain[-1] + ((oi, od),)
+        else:
+            flush()
+            for t in trees:
+                t.insert(to_dev(op.pts, torch), to_dev(op.ids, torch))
+            o.insert(op.pts, op.ids)
+    flush()
+    for t in trees:
+        t.sync()
+    assert len(plain) == len(batched)
+    for (pi, pd, (oi, od)), (bi, bd) in zip(plain, batched):
+        assert torch.equal(pi, bi) and torch.equal(pd.view(torch.int32), bd.view(torch.int32))
+        assert_knn_equal(bi.cpu().numpy()[:16], bd.cpu().numpy()[:16], oi, od, "batched op log")
+    for t in trees:
+        t.close()

@@ -61,3 +61,56 @@ def test_uniform3d_10m_full_size():
     oi, od = oracle.bruteforce_knn(all_pts[live], qids, qop.pts[sel], qop.k)
     assert_knn_equal(gi.cpu().numpy()[sel], gd.cpu().numpy()[sel], oi, od, "full size sample")
     t.close()
+
+
+def test_clustered7d_10m_full_size():
+    """The 7D clustered workload at full size: 100 Insert_L batches of 100K,
+    one Erase_L of 1M live ids, kNN_L k=10 for every live point.  Checked:
+    the schedule against the binary-counter closed form (insert-only up to
+    the erase), the half rule after the erase, the self-match property where
+    coordinates are unique, and sampled rows against brute force."""
+    import torch
+
+    import paper_2112_06188_amd as bdl
+
+    torch.cuda.set_device(0)
+    log("case: clustered7d_10m full size")
+    w = workload("clustered7d_10m")
+    t = bdl.Tree(w.dim, leaf_size=w.leaf_size, buffer_size=w.buffer_size,
+                 id_capacity=w.id_capacity)
+    live = np.ones(w.id_capacity, dtype=bool)
+    all_pts = np.concatenate([op.pts for op in w.ops if op.kind == "insert"])
+    n = len(all_pts)
+    for op in w.ops:
+        if op.kind == "insert":
+            t.insert(to_dev(op.pts, torch), to_dev(op.ids, torch))
+        elif op.kind == "erase":
+            info = t.level_info()
+            m = n // w.buffer_size
+            assert info["F"] == m and info["buf_live"] == n - m * w.buffer_size
+            assert t.erase(to_dev(op.pts, torch), to_dev(op.ids, torch)) == op.n
+            live[op.ids.astype(np.int64)] = False
+        else:
+            qop = op
+    info = t.level_info()
+    cap = info["cap"]
+    for i in bits(info["F"]):
+        assert 2 * info["live"][i] >= cap[i], f"tree {i} below half after the erase"
+    assert t.size() == int(live.sum())
+    gi, gd = t.knn(to_dev(qop.pts, torch), qop.k)
+    t.sync()
+    qids = np.nonzero(live)[0].astype(np.uint32)
+    # a query whose coordinates occur once among the live points finds
+    # itself first at distance 0
+    _, first, counts = np.unique(qop.pts, axis=0, return_index=True, return_counts=True)
+    uniq = np.zeros(len(qids), dtype=bool)
+    uniq[first[counts == 1]] = True
+    g0 = gi[:, 0].cpu().numpy().view(np.uint32)
+    assert np.array_equal(g0[uniq], qids[uniq])
+    assert bool((gd[:, 0] == 0).all())
+    assert bool((gd[:, 1:] >= gd[:, :-1]).all())
+    rng = np.random.default_rng(8)
+    sel = np.sort(rng.choice(qop.n, size=160, replace=False))
+    oi, od = oracle.bruteforce_knn(all_pts[live], qids, qop.pts[sel], qop.k)
+    assert_knn_equal(gi.cpu().numpy()[sel], gd.cpu().numpy()[sel], oi, od, "7D full size sample")
+    t.close()

@@ -180,3 +180,60 @@ def test_budget_admission_and_limits(torch, bdl):
     assert np.array_equal(gi, ref_i.cpu().numpy().view(np.uint32))
     assert [o["admit_seq"] for o in outs] == list(range(30))
     t.close()
+
+
+def test_served_request_log_scaled(torch, bdl):
+    """The served-form request log (3D clustered resident set; 70/20/10
+    kNN/insert/erase with log-uniform sizes) at reduced scale, submitted as
+    a Poisson stream to the batching server: each result equals the plain
+    replay in admission order, and the oracle's on sampled rows."""
+    from bdl_inputs import workload
+    w = workload("served3d_50m", scale=0.01)
+    log(f"case: served log: {w.description}")
+    mk = lambda: bdl.Tree(w.dim, leaf_size=w.leaf_size, buffer_size=w.buffer_size,
+                          id_capacity=w.id_capacity)
+    t, r = mk(), mk()
+    o = oracle.OracleBDL(w.dim, w.leaf_size, w.buffer_size)
+    for op in w.ops[:w.n_setup]:
+        t.insert(to_dev(op.pts, torch), to_dev(op.ids, torch))
+        r.insert(to_dev(op.pts, torch), to_dev(op.ids, torch))
+        o.insert(op.pts, op.ids)
+    t.sync()
+    srv = bdl.Server(t, mode=1, max_inflight=256, mem_budget=256 << 20)
+    reqs = w.ops[w.n_setup:]
+    at = np.cumsum(np.random.default_rng(3).exponential(1.0 / 2000.0, size=len(reqs)))
+    t0 = time.perf_counter()
+    tickets = []
+    for a, op in zip(at, reqs):
+        while time.perf_counter() < t0 + a:
+            pass
+        if op.kind == "knn":
+            tickets.append(srv.submit_knn(op.pts, op.k))
+        elif op.kind == "insert":
+            tickets.append(srv.submit_insert(op.pts, op.ids))
+        else:
+            tickets.append(srv.submit_erase(op.pts, op.ids))
+    comps = [srv.wait(tk) for tk in tickets]
+    srv.close()
+    order = np.argsort([c["admit_seq"] for c in comps])
+    assert [comps[i]["admit_seq"] for i in order] == list(range(len(comps)))
+    assert len({c["launch"] for c in comps}) < len(comps)
+    for j, i in enumerate(order):
+        c, op = comps[i], reqs[i]
+        assert c["status"] == 0
+        if op.kind == "insert":
+            r.insert(to_dev(op.pts, torch), to_dev(op.ids, torch))
+            o.insert(op.pts, op.ids)
+        elif op.kind == "erase":
+            ne = r.erase(to_dev(op.pts, torch), to_dev(op.ids, torch))
+            assert ne == c["n_erased"] == o.erase(op.pts, op.ids)
+        else:
+            gi, gd = r.knn(to_dev(op.pts, torch), op.k)
+            r.sync()
+            assert np.array_equal(gi.cpu().numpy().view(np.uint32), c["ids"]), j
+            assert np.array_equal(gd.cpu().numpy().view(np.uint32), c["d2"].view(np.uint32)), j
+            if j % 4 == 0:
+                oi, od = o.knn(op.pts[:8], op.k)
+                assert_knn_equal(c["ids"][:8], c["d2"][:8], oi, od, f"served log {j}")
+    t.close()
+    r.close()
