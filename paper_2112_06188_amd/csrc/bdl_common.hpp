@@ -26,7 +26,7 @@ constexpr uint32_t kTomb = 0xFFFFFFFFu;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint64_t kMapInvalid = ~0ull;
 constexpr uint32_t kBufferLevel = 63;  // map entries of buffered points
-constexpr int kTile = 4096;            // points per tile of a global pass
+constexpr int kTile = 2048;            // points per tile of a global pass
 constexpr int kPassThreads = 256;
 constexpr int kItems = kTile / kPassThreads;
 // spare records after every record array: the k-NN kernel reads leaves in

@@ -6,7 +6,7 @@
 //     structure-of-arrays build buffer (Insert_L's "deconstruct and gather");
 //  2. global passes, one depth per pass, for nodes with more points than the
 //     LDS finisher holds: split choice per node, a count of left points per
-//     4096-point tile, a prefix sum over tiles and a stable scatter into the
+//     2048-point tile, a prefix sum over tiles and a stable scatter into the
 //     other build buffer that also accumulates the children's tight boxes;
 //  3. the LDS finisher: one workgroup builds a whole small subtree in LDS and
 //     writes its points as records in final slot order;
@@ -529,18 +529,22 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
 // Stable partition of every tile into the other build buffer; accumulates
 // the tight boxes of children that stay in the global passes; leaves that
 // are too large for the finisher (coincident points) are copied out whole.
+// D is the dimension: every column is moved with the same destinations and
+// the children's boxes are kept in registers for all dimensions, so a tile
+// needs three barriers whatever D is.
+template <int D>
 __global__ void __launch_bounds__(kPassThreads)
 k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounters* c,
-          const float* src, float* dst, uint64_t cap, int d, const uint32_t* tile_off,
+          const float* src, float* dst, uint64_t cap, const uint32_t* tile_off,
           const Job* jobs, uint64_t* map, uint32_t idcap) {
   __shared__ uint32_t lt[kItems][4];
-  __shared__ uint32_t red[4][4];
+  __shared__ uint32_t red[4][4 * D];
   const uint32_t nt = c->ntiles;
   const int lane = __lane_id();
   const int w = threadIdx.x >> 6;
   const uint64_t ltm = lanemask_lt();
-  const uint32_t* sid = soa_ids(src, d, cap);
-  uint32_t* did = soa_ids_w(dst, d, cap);
+  const uint32_t* sid = soa_ids(src, D, cap);
+  uint32_t* did = soa_ids_w(dst, D, cap);
   for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
     const uint32_t s = tile_seg[t];
     const Seg& g = cur[s];
@@ -551,17 +555,19 @@ k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounter
     const int dim = g.dim;
     if (dim < 0) {
       const Job J = jobs[g.job];
-      const int S = rec_stride(d);
+      constexpr int S = (D + 1 + 3) & ~3;
       for (int r = 0; r < kItems; ++r) {
         uint32_t i = r * kPassThreads + threadIdx.x;
         if (i >= tcnt) continue;
         uint64_t p = tstart + i;
         uint64_t slot = p - J.base;
         float* rr = J.rec + slot * S;
-        for (int j = 0; j < d; ++j) rr[j] = src[(uint64_t)j * cap + p];
+#pragma unroll
+        for (int j = 0; j < D; ++j) rr[j] = src[(uint64_t)j * cap + p];
         uint32_t id = sid[p];
-        rr[d] = __uint_as_float(id);
-        for (int j = d + 1; j < S; ++j) rr[j] = 0.0f;
+        rr[D] = __uint_as_float(id);
+#pragma unroll
+        for (int j = D + 1; j < S; ++j) rr[j] = 0.0f;
         if (J.write_map && id < idcap) map[id] = ((uint64_t)J.level << 32) | slot;
       }
       continue;
@@ -590,6 +596,7 @@ k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounter
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       uint32_t before = 0, row = 0;
+#pragma unroll
       for (int v = 0; v < 4; ++v) {
         uint32_t xv = lt[r][v];
         before += v < w ? xv : 0u;
@@ -600,8 +607,9 @@ k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounter
       dpos[r] = ((fl >> r) & 1u) ? (uint32_t)(lbase + lr) : (uint32_t)(rbase + (i - lr));
       run += row;
     }
-    const uint32_t c0 = g.child[0], c1 = g.child[1];
-    for (int j = 0; j < d; ++j) {
+    uint32_t bx[D][4];  // left min, left max, right min, right max (ordered u32)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
       const float* sj = src + (uint64_t)j * cap;
       float* dj = dst + (uint64_t)j * cap;
       uint32_t lmn = 0xFFFFFFFFu, lmx = 0u, rmn = 0xFFFFFFFFu, rmx = 0u;
@@ -621,37 +629,48 @@ k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounter
           }
         }
       }
-      wave_minmax(lmn, lmx);
-      wave_minmax(rmn, rmx);
-      if (lane == 0) {
-        red[w][0] = lmn;
-        red[w][1] = lmx;
-        red[w][2] = rmn;
-        red[w][3] = rmx;
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        for (int v = 1; v < 4; ++v) {
-          lmn = red[v][0] < lmn ? red[v][0] : lmn;
-          lmx = red[v][1] > lmx ? red[v][1] : lmx;
-          rmn = red[v][2] < rmn ? red[v][2] : rmn;
-          rmx = red[v][3] > rmx ? red[v][3] : rmx;
-        }
-        if (c0 != kNone && lmn <= lmx) {
-          atomicMin(&nxt[c0].box[j], lmn);
-          atomicMax(&nxt[c0].box[kMaxDim + j], lmx);
-        }
-        if (c1 != kNone && rmn <= rmx) {
-          atomicMin(&nxt[c1].box[j], rmn);
-          atomicMax(&nxt[c1].box[kMaxDim + j], rmx);
-        }
-      }
-      __syncthreads();
+      bx[j][0] = lmn;
+      bx[j][1] = lmx;
+      bx[j][2] = rmn;
+      bx[j][3] = rmx;
     }
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       uint32_t i = r * kPassThreads + threadIdx.x;
       if (i < tcnt) did[dpos[r]] = sid[tstart + i];
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      wave_minmax(bx[j][0], bx[j][1]);
+      wave_minmax(bx[j][2], bx[j][3]);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[w][4 * j + q] = bx[j][q];
+    }
+    __syncthreads();
+    // one thread per (dimension, bound, side): combine the four waves
+    if (threadIdx.x < 4 * D) {
+      const int j = threadIdx.x >> 2, q = threadIdx.x & 3;
+      const bool is_max = q & 1;
+      uint32_t v = red[0][threadIdx.x];
+#pragma unroll
+      for (int u = 1; u < 4; ++u) {
+        const uint32_t o = red[u][threadIdx.x];
+        v = is_max ? (o > v ? o : v) : (o < v ? o : v);
+      }
+      const uint32_t ch = q < 2 ? g.child[0] : g.child[1];
+      // a side with no point in this tile keeps the neutral values
+      // (0xFFFFFFFF, 0), which no finite coordinate maps to; skip it
+      if (ch != kNone) {
+        if (is_max) {
+          if (v != 0u) atomicMax(&nxt[ch].box[kMaxDim + j], v);
+        } else {
+          if (v != 0xFFFFFFFFu) atomicMin(&nxt[ch].box[j], v);
+        }
+      }
     }
     __syncthreads();
   }
@@ -1018,6 +1037,30 @@ inline unsigned grid_for(uint64_t n, unsigned threads, unsigned cap = 4096) {
   return (unsigned)g;
 }
 
+template <int D>
+void launch_scatter_d(unsigned grid, const BuildScratch& sc, int par, uint64_t* map,
+                      uint32_t idcap, hipStream_t s) {
+  hipLaunchKernelGGL((k_scatter<D>), dim3(grid), dim3(kPassThreads), 0, s, sc.seg[par],
+                     sc.tile_seg, sc.seg[par ^ 1], sc.ctr, sc.soa[par], sc.soa[par ^ 1], sc.cap,
+                     sc.tile_off, sc.jobs, map, idcap);
+}
+
+void launch_scatter(int d, unsigned grid, const BuildScratch& sc, int par, uint64_t* map,
+                    uint32_t idcap, hipStream_t s) {
+  switch (d) {
+#define BDL_SCATTER_CASE(DD) \
+  case DD:                   \
+    return launch_scatter_d<DD>(grid, sc, par, map, idcap, s);
+    BDL_SCATTER_CASE(1) BDL_SCATTER_CASE(2) BDL_SCATTER_CASE(3) BDL_SCATTER_CASE(4)
+    BDL_SCATTER_CASE(5) BDL_SCATTER_CASE(6) BDL_SCATTER_CASE(7) BDL_SCATTER_CASE(8)
+    BDL_SCATTER_CASE(9) BDL_SCATTER_CASE(10) BDL_SCATTER_CASE(11) BDL_SCATTER_CASE(12)
+    BDL_SCATTER_CASE(13) BDL_SCATTER_CASE(14) BDL_SCATTER_CASE(15) BDL_SCATTER_CASE(16)
+#undef BDL_SCATTER_CASE
+    default:
+      return;
+  }
+}
+
 template <int DMAX, int TCAP, int MAXACT, int NT>
 void launch_finish(uint32_t nfin, const BuildScratch& sc, int d, uint32_t leaf, uint64_t* map,
                    uint32_t idcap, hipStream_t s) {
@@ -1156,9 +1199,7 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
       hipLaunchKernelGGL(k_tilescan, dim3(1), dim3(1024), 0, s, sc.seg[par], sc.seg[par ^ 1],
                          sc.ctr, par, sc.tile_left, sc.tile_off, sc.fin, T, sc.max_seg,
                          sc.max_fin);
-      hipLaunchKernelGGL(k_scatter, dim3(pass_grid), dim3(kPassThreads), 0, s, sc.seg[par],
-                         sc.tile_seg, sc.seg[par ^ 1], sc.ctr, sc.soa[par], sc.soa[par ^ 1],
-                         sc.cap, d, sc.tile_off, sc.jobs, map, idcap);
+      launch_scatter(d, pass_grid, sc, par, map, idcap, s);
     }
     pt.end(BDL_PH_PASSES);
     if (hipMemcpyAsync(sc.host_ctr, sc.ctr, sizeof(BuildCounters), hipMemcpyDeviceToHost, s) !=

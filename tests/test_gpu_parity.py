@@ -80,7 +80,7 @@ def test_random_ops(torch, bdl, seed, d, X, leaf, clustered):
 @pytest.mark.parametrize("d,n", [(3, 200_000), (2, 150_001), (7, 90_000), (16, 40_000)])
 def test_large_levels_use_global_passes(torch, bdl, d, n, kern):
     """Trees larger than the LDS finisher go through the per-depth global
-    passes (several 4096-point tiles per node) before the finisher."""
+    passes (several 2048-point tiles per node) before the finisher."""
     log(f"case: large level d={d} n={n} kernel={kern}")
     t, o = _pair(bdl, d, 16, 1024, knn_kernel=kern)
     p = uniform_points(n, d, 10 + d)
