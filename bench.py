@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE, WRITE_SIZE) and the sources it was measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "knn_traversal_traffic.json")
 TRAVERSAL_SOURCES = [os.path.join(ROOT, "paper_2112_06188_amd", "csrc", f)
-                     for f in ("knn_traverse.hpp", "knn_d1_4.hip")]
+                     for f in ("knn_traverse.hpp", "knn_d1_4.hip", "knn.hip", "tree.hip")]
 
 
 def traversal_source_hash() -> str:
@@ -166,7 +166,7 @@ def gpu_bench(args):
     tree_bytes += info["buf_live"] * S * 4 + sizes["buf_nodes"] * NS * 4
     trav = prof["traverse"]
     trav_ms = trav["ms"] / max(1, trav["calls"])
-    # algorithmic bytes of one traversal launch: queries read, the Morton
+    # algorithmic bytes of one traversal launch: queries read, the Hilbert
     # order read, results written, every live tree read once
     alg_bytes = nq * (4 * w.dim + 4 + 8 * k) + tree_bytes
     achieved = alg_bytes / (trav_ms * 1e-3) / 1e9

@@ -57,7 +57,7 @@ extern "C" {
 #define BDL_PH_FINISH 2    /* Insert_L: LDS subtree finisher */
 #define BDL_PH_LAYOUT 3    /* Insert_L: vEB ordering and node write-out */
 #define BDL_PH_ERASE 4     /* Erase_L: locate and tombstone */
-#define BDL_PH_ORDER 5     /* kNN_L: Morton ordering of the queries */
+#define BDL_PH_ORDER 5     /* kNN_L: Hilbert-curve ordering of the queries */
 #define BDL_PH_TRAVERSE 6  /* kNN_L: the traversal kernel */
 #define BDL_NPHASES 8
 
@@ -111,7 +111,7 @@ int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_id
                                   65536 queries and half as many as live
                                   points, else one lane per query */
 #define BDL_PARAM_SORT_MIN 2   /* query batches of at least this many queries
-                                  are visited in Morton order (default 4096) */
+                                  are visited in Hilbert-curve order (default 4096) */
 #define BDL_PARAM_KNN_BLOCK 3  /* k-NN workgroup size: 64, 128 or 256 (default) */
 #define BDL_PARAM_USE_GRAPHS 4 /* 1 (default): bdl_knn_batch replays captured
                                   hipGraphs; 0: it launches eagerly */
@@ -125,7 +125,7 @@ int bdl_set_param(bdl_tree* t, int32_t param, int64_t value);
 /* One row of a launch-shape table for kNN_L (bdl_knn and bdl_knn_batch).  A
  * launch whose largest k lies in [k_lo, k_hi] and whose query count lies in
  * [nq_lo, nq_hi] uses this row's kernel, workgroup size, persistence and
- * (bdl_knn only) Morton ordering; the first matching row wins and a launch
+ * (bdl_knn only) Hilbert-curve ordering; the first matching row wins and a launch
  * no row matches uses the values of bdl_set_param.  Rows come from an
  * autotuner that times the candidates on the device.  Shapes change speed,
  * never results. */
@@ -135,7 +135,7 @@ typedef struct {
   int32_t kernel;       /* 0 lane, 1 wave (as BDL_PARAM_KNN_KERNEL) */
   int32_t block;        /* 64, 128 or 256 */
   int32_t persistent;   /* 0 or 1 */
-  int32_t sort;         /* 0 or 1: Morton-order the queries of a bdl_knn call
+  int32_t sort;         /* 0 or 1: order the queries of a bdl_knn call along the Hilbert curve
                            (bdl_knn_batch always orders them) */
 } bdl_knn_shape;
 

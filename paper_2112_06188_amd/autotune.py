@@ -1,7 +1,7 @@
 """Launch-shape autotuner for kNN_L on the device at hand.
 
 For each band of k and of query counts it times every candidate shape
-(traversal kernel, workgroup size, persistent grid, Morton ordering of a
+(traversal kernel, workgroup size, persistent grid, Hilbert-curve ordering of a
 plain call) on the caller's own resident tree with queries the caller
 draws, keeps the fastest by median device time, and installs the winners as
 the tree's shape table (bdl_set_knn_shapes).  Shapes change speed, never

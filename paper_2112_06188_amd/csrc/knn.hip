@@ -1,4 +1,4 @@
-// Host side of the batched k-NN query (kNN_L, Alg. 5): Morton ordering of
+// Host side of the batched k-NN query (kNN_L, Alg. 5): Hilbert-curve ordering of
 // query batches, concatenation of request tables, and the dispatch of
 // traversal launches to the kernel instantiations (knn_traverse.hpp).
 #include <map>
@@ -92,9 +92,40 @@ k_query_box(const float* q, const uint64_t* nq_dev, uint64_t nq_host, int d, uin
   }
 }
 
-// Morton key with bits = floor(30 / d) bits per dimension; positions from nq
+// Position along the Hilbert curve of the cell x[0..d) (bits per
+// coordinate), by Skilling's transform of the axes into the curve's
+// "transposed" index (J. Skilling, Programming the Hilbert curve, AIP Conf.
+// Proc. 707, 2004) followed by bit interleaving.  Unlike Morton order the
+// curve has no jumps: consecutive keys are neighbouring cells, so a group of
+// consecutive queries covers a compact region.  x is overwritten.
+__device__ inline uint32_t hilbert_key(uint32_t* x, int d, int bits) {
+  const uint32_t top = 1u << (bits - 1);
+  for (uint32_t q = top; q > 1; q >>= 1) {
+    const uint32_t low = q - 1;
+    for (int j = 0; j < d; ++j) {
+      if (x[j] & q) {
+        x[0] ^= low;
+      } else {
+        const uint32_t t = (x[0] ^ x[j]) & low;
+        x[0] ^= t;
+        x[j] ^= t;
+      }
+    }
+  }
+  for (int j = 1; j < d; ++j) x[j] ^= x[j - 1];
+  uint32_t t = 0;
+  for (uint32_t q = top; q > 1; q >>= 1)
+    if (x[d - 1] & q) t ^= q - 1;
+  for (int j = 0; j < d; ++j) x[j] ^= t;
+  uint32_t key = 0;
+  for (int b = bits - 1; b >= 0; --b)
+    for (int j = 0; j < d; ++j) key = (key << 1) | ((x[j] >> b) & 1u);
+  return key;
+}
+
+// Hilbert key with bits = floor(30 / d) bits per dimension; positions from nq
 // up to cap get the key 0xFFFFFFFF, which sorts after every real key.
-__global__ void k_morton(const float* q, const uint64_t* nq_dev, uint64_t nq_host, uint64_t cap,
+__global__ void k_hilbert(const float* q, const uint64_t* nq_dev, uint64_t nq_host, uint64_t cap,
                          int d, const uint32_t* box, uint32_t* keys, uint32_t* vals) {
   const uint64_t nq = nq_dev ? *nq_dev : nq_host;
   const int bits = 30 / d > 0 ? 30 / d : 1;
@@ -115,10 +146,7 @@ __global__ void k_morton(const float* q, const uint64_t* nq_dev, uint64_t nq_hos
       c = c < 0 ? 0 : (c >= (int)(1u << bits) ? (int)(1u << bits) - 1 : c);
       cell[j] = (uint32_t)c;
     }
-    uint32_t key = 0;
-    for (int b = bits - 1; b >= 0; --b)
-      for (int j = 0; j < d; ++j) key = (key << 1) | ((cell[j] >> b) & 1u);
-    keys[i] = key;
+    keys[i] = hilbert_key(cell, d, bits);
   }
 }
 
@@ -151,7 +179,7 @@ size_t query_scratch_bytes(uint64_t cap) {
   return 4 * (size_t)cap * 4 + radix_tmp_words(cap) * 4 + 2 * kMaxDim * 4;
 }
 
-const uint32_t* morton_order(int d, const float* q, const uint64_t* nq_dev, uint64_t nq_host,
+const uint32_t* spatial_order(int d, const float* q, const uint64_t* nq_dev, uint64_t nq_host,
                              uint64_t cap, QueryScratch& qs, hipStream_t s) {
   hipLaunchKernelGGL(k_query_box_init, dim3(1), dim3(64), 0, s, qs.box);
   unsigned g = (unsigned)((cap + 255) / 256);
@@ -159,7 +187,7 @@ const uint32_t* morton_order(int d, const float* q, const uint64_t* nq_dev, uint
   hipLaunchKernelGGL(k_query_box, dim3(g), dim3(256), 0, s, q, nq_dev, nq_host, d, qs.box);
   unsigned g2 = (unsigned)((cap + 255) / 256);
   if (g2 > 4096) g2 = 4096;
-  hipLaunchKernelGGL(k_morton, dim3(g2), dim3(256), 0, s, q, nq_dev, nq_host, cap, d, qs.box,
+  hipLaunchKernelGGL(k_hilbert, dim3(g2), dim3(256), 0, s, q, nq_dev, nq_host, cap, d, qs.box,
                      qs.keys[0], qs.vals[0]);
   const int bits = (30 / d > 0 ? 30 / d : 1) * d;
   int which = radix_sort_pairs_u32(qs.keys[0], qs.vals[0], qs.keys[1], qs.vals[1], cap, 0, bits,

@@ -5,7 +5,7 @@
 
 namespace bdl {
 
-// Scratch for ordering a query batch spatially (Morton order).
+// Scratch for ordering a query batch spatially (Hilbert-curve order).
 struct QueryScratch {
   uint64_t cap = 0;
   uint32_t* keys[2] = {nullptr, nullptr};
@@ -16,7 +16,7 @@ struct QueryScratch {
 
 size_t query_scratch_bytes(uint64_t cap);
 
-// Batches of at least this many queries are visited in Morton order.
+// Batches of at least this many queries are visited in Hilbert-curve order.
 constexpr uint64_t kSortQueriesMin = 4096;
 
 // Traversal variants: one lane per query, or one wavefront per group of 64
@@ -75,9 +75,9 @@ int launch_knn(const KnnLaunch& L, int d, int kmax, const KnnQueries& Q, uint64_
                const uint32_t* order, const LevelViews* views, uint32_t* err,
                unsigned long long* stats, hipStream_t s);
 
-// Morton order of queries [0, nq) of q, sorting cap >= nq keys (positions
+// Hilbert-curve order of queries [0, nq) of q, sorting cap >= nq keys (positions
 // from nq on sort last).  Returns the device array holding the permutation.
-const uint32_t* morton_order(int d, const float* q, const uint64_t* nq_dev, uint64_t nq_host,
+const uint32_t* spatial_order(int d, const float* q, const uint64_t* nq_dev, uint64_t nq_host,
                              uint64_t cap, QueryScratch& qs, hipStream_t s);
 
 // Concatenate the queries of counts[1] requests (offsets in reqs[i].qoff,

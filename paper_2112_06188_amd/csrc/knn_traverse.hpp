@@ -77,7 +77,7 @@ __device__ inline void topk_insert(uint64_t (&a)[KMAX], uint64_t c) {
 
 // XCD-aware block order: gfx950 hands consecutive workgroups to its 8 XCDs
 // round robin, each with its own L2.  Remap so that XCD x runs one contiguous
-// range of the (Morton-ordered) query blocks; neighbouring waves then share
+// range of the (Hilbert-ordered) query blocks; neighbouring waves then share
 // tree nodes in the same L2.
 __device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb) {
   const uint32_t x = b & 7u;
@@ -85,7 +85,7 @@ __device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb) {
   return x * q + (x < r ? x : r) + (b >> 3);
 }
 
-// Work distribution in groups of 64 consecutive (Morton-ordered) queries,
+// Work distribution in groups of 64 consecutive (Hilbert-ordered) queries,
 // one group per wavefront at a time.
 //
 // Without a queue, wave w of the launch takes group w once (blocks remapped
@@ -310,7 +310,7 @@ __device__ inline void load_node(cvf4_ptr nodes, int n, float (&f)[4 * NV]) {
 }
 
 // Wavefront-cooperative variant: the 64 lanes of a wave hold 64 queries that
-// are neighbours in Morton order and walk each tree together, depth first.
+// are neighbours in Hilbert-curve order and walk each tree together, depth first.
 // At an internal node both children are read at once and each is tested by a
 // ballot over the lanes' strict prune tests: a child is entered when ANY lane
 // may still find a neighbour in it.  The near child (the side of the split

@@ -77,7 +77,7 @@ struct bdl_tree {
   uint32_t* d_queue = nullptr;        // work counters of persistent k-NN launches
   LevelViews* d_views = nullptr;   // the trees kNN_L visits, in device memory
   // batched kNN_L (bdl_knn_batch)
-  QueryScratch bqs;                // Morton scratch sized for bcap queries
+  QueryScratch bqs;                // ordering scratch sized for bcap queries
   uint64_t bcap = 0;
   float* bq = nullptr;             // concatenated queries [bcap][d]
   uint32_t* bqreq = nullptr;       // request of each query
@@ -576,7 +576,7 @@ KnnLaunch choose_launch(const bdl_tree* t, int kmax, uint64_t nq, bool* sort) {
   L.mode = t->knn_mode;
   if (L.mode == kKnnAuto) {
     // the wavefront kernel pays off when the queries are dense among the
-    // points (Morton-adjacent queries then share most of their paths);
+    // points (queries adjacent on the Hilbert curve then share most of their paths);
     // sparse queries take one lane each
     const int64_t live = bdl_size(t);
     L.mode = (nq >= 65536 && (int64_t)nq * 2 >= live) ? kKnnWave : kKnnLane;
@@ -600,7 +600,7 @@ KnnLaunch choose_launch(const bdl_tree* t, int kmax, uint64_t nq, bool* sort) {
 
 int enqueue_batch(bdl_tree* t, hipStream_t s, uint64_t cap, int kt, const KnnLaunch& L) {
   launch_gather_queries(t->breqs, t->bcount, cap, t->d, t->bq, t->bqreq, s);
-  const uint32_t* order = morton_order(t->d, t->bq, t->bcount, 0, cap, t->bqs, s);
+  const uint32_t* order = spatial_order(t->d, t->bq, t->bcount, 0, cap, t->bqs, s);
   KnnQueries Q;
   std::memset(&Q, 0, sizeof(Q));
   Q.q = t->bq;
@@ -1027,7 +1027,7 @@ int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_id
   if (sort) {
     if (!ensure_query_scratch(t, (uint64_t)nq)) return fail(BDL_ENOMEM, "query scratch");
     t->pt.begin(BDL_PH_ORDER);
-    order = morton_order(t->d, q, nullptr, (uint64_t)nq, (uint64_t)nq, t->qs, t->s);
+    order = spatial_order(t->d, q, nullptr, (uint64_t)nq, (uint64_t)nq, t->qs, t->s);
     t->pt.end(BDL_PH_ORDER);
   }
   KnnQueries Q;

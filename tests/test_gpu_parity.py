@@ -94,7 +94,7 @@ def test_large_levels_use_global_passes(torch, bdl, d, n, kern):
 
 
 def test_unsorted_small_batches_both_kernels(torch, bdl):
-    """Batches below the Morton-order threshold run in input order; a batch
+    """Batches below the ordering threshold run in input order; a batch
     whose size is not a multiple of the wavefront leaves idle lanes."""
     log("case: small unsorted batches")
     d = 3
