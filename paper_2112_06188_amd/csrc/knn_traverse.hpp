@@ -386,17 +386,20 @@ __device__ __forceinline__ void knn_wave_group(const KnnQueries& Q, const uint32
           }
           ++c_leaves;
           c_points += (uint32_t)b;
-          // the leaf's records are read at wave-uniform addresses (scalar
-          // loads, four records per step) and used straight from SGPRs
+          // the leaf's records are read four at a time at wave-uniform
+          // addresses (scalar loads into SGPRs).  Record arrays carry
+          // kRecPad spare records, so reading up to three past the leaf's end
+          // stays in bounds; a record past the end or erased gets the
+          // padding key, which never enters the k best.
           const int end = a + b;
           for (int sl = a; sl < end; sl += 4) {
             float r[4][S];
+            const cvf4_ptr rp = rec + (uint64_t)sl * SV;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const int si = sl + i < end ? sl + i : sl;
 #pragma unroll
               for (int u = 0; u < SV; ++u) {
-                const vf4 x = rec[(uint64_t)si * SV + u];
+                const vf4 x = rp[i * SV + u];
                 r[i][4 * u + 0] = x.x;
                 r[i][4 * u + 1] = x.y;
                 r[i][4 * u + 2] = x.z;
@@ -406,14 +409,15 @@ __device__ __forceinline__ void knn_wave_group(const KnnQueries& Q, const uint32
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const uint32_t id = __float_as_uint(r[i][D]);
-              if (sl + i >= end || id == kTomb) continue;
               float acc = 0.0f;
 #pragma unroll
               for (int j = 0; j < D; ++j) {
                 float tt = qq[j] - r[i][j];
                 acc = __builtin_fmaf(tt, tt, acc);
               }
-              const uint64_t ck = ((uint64_t)__float_as_uint(acc) << 32) | id;
+              const bool skip_rec = sl + i >= end || id == kTomb;
+              const uint64_t ck =
+                  skip_rec ? kPadKey : (((uint64_t)__float_as_uint(acc) << 32) | id);
               if (ck < key[KMAX - 1]) topk_insert<KMAX>(key, ck);
             }
           }
