@@ -106,10 +106,12 @@ int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_id
 
 /* Tuning parameters (bdl_set_param).  They change speed, never results. */
 #define BDL_PARAM_KNN_KERNEL 1 /* 0: one lane per query; 1: one wavefront per
-                                  64 neighbouring queries; 2 (default): the
-                                  wavefront kernel when a launch has at least
-                                  65536 queries and half as many as live
-                                  points, else one lane per query */
+                                  64 neighbouring queries; 3: one wavefront
+                                  per query; 2 (default): 3 for launches of
+                                  at most BDL_PARAM_QUERY_MAX queries, 1 when
+                                  a launch has at least 65536 queries and half
+                                  as many as live points, else 0.  3 needs
+                                  every tree below 2^26 nodes, else 0 runs */
 #define BDL_PARAM_SORT_MIN 2   /* query batches of at least this many queries
                                   are visited in Hilbert-curve order (default 4096) */
 #define BDL_PARAM_KNN_BLOCK 3  /* k-NN workgroup size: 64, 128 or 256 (default) */
@@ -120,6 +122,13 @@ int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_id
                                   of 64 queries from per-XCD work counters;
                                   0: one wavefront per group; 2 (default): 1 for
                                   the wavefront kernel, 0 for the lane kernel */
+#define BDL_PARAM_QUERY_MAX 6  /* launches of at most this many queries use one
+                                  wavefront per query under kernel 2 (default
+                                  131072; 0 disables) */
+#define BDL_PARAM_QUERY_STACK 7 /* pending-node entries per wavefront of kernel
+                                   3, at least 130 (default and maximum 2048);
+                                   a smaller stack walks more subtrees through
+                                   parent links instead */
 int bdl_set_param(bdl_tree* t, int32_t param, int64_t value);
 
 /* One row of a launch-shape table for kNN_L (bdl_knn and bdl_knn_batch).  A
@@ -132,7 +141,8 @@ int bdl_set_param(bdl_tree* t, int32_t param, int64_t value);
 typedef struct {
   int32_t k_lo, k_hi;   /* 1..64 */
   int64_t nq_lo, nq_hi; /* query counts, inclusive */
-  int32_t kernel;       /* 0 lane, 1 wave (as BDL_PARAM_KNN_KERNEL) */
+  int32_t kernel;       /* 0 lane, 1 wave, 3 wavefront per query (as
+                           BDL_PARAM_KNN_KERNEL) */
   int32_t block;        /* 64, 128 or 256 */
   int32_t persistent;   /* 0 or 1 */
   int32_t sort;         /* 0 or 1: order the queries of a bdl_knn call along the Hilbert curve

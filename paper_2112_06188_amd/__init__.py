@@ -43,10 +43,13 @@ PARAM_SORT_MIN = 2
 PARAM_KNN_BLOCK = 3
 PARAM_USE_GRAPHS = 4
 PARAM_PERSISTENT = 5
+PARAM_QUERY_MAX = 6
+PARAM_QUERY_STACK = 7
 MAX_SHAPES = 256
 KNN_LANE = 0
 KNN_WAVE = 1
 KNN_AUTO = 2
+KNN_QUERY = 3
 PHASES = ["gather", "passes", "finish", "layout", "erase", "order", "traverse", "other"]
 
 

@@ -18,7 +18,7 @@ import json
 import statistics
 from typing import Callable, Dict, Iterable, List, Optional, Sequence
 
-KERNELS = (0, 1)         # lane per query, wavefront per 64 queries
+KERNELS = (0, 1, 3)      # lane per query, wavefront per 64 queries, wavefront per query
 BLOCKS = (64, 128, 256)
 PERSISTENT = (0, 1)
 SORT = (0, 1)

@@ -24,6 +24,9 @@ constexpr uint64_t kSortQueriesMin = 4096;
 constexpr int kKnnLane = 0;
 constexpr int kKnnWave = 1;
 constexpr int kKnnAuto = 2;  // chosen per launch from the query density
+constexpr int kKnnQuery = 3;  // one wavefront per query (small batches)
+// a tree with this many nodes or more cannot be searched by kKnnQuery
+constexpr uint64_t kKnnQueryMaxNodes = 1ull << 26;
 
 // One k-NN request as the kernels see it: its queries, k and outputs, and
 // the position of its first query in the concatenated query array.
@@ -61,6 +64,7 @@ struct KnnLaunch {
   int persistent = 0;
   uint32_t* queue = nullptr;
   bool dry_run = false;
+  int qstack = 1 << 30;  // kKnnQuery: pending-node entries per wave (clamped)
 };
 
 constexpr int kKnnQueueStride = 64;  // words between the per-XCD counters

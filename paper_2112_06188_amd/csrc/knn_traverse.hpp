@@ -498,6 +498,325 @@ k_knn_wave(KnnQueries Q, const uint32_t* __restrict__ order,
     knn_wave_group<D, KMAX>(Q, order, views, err, stats, (uint64_t)g * 64 + __lane_id(), nq);
 }
 
+// ---------------------------------------------------------------------------
+// One wavefront per query, for small batches where one lane per query
+// leaves the device idle and a query's own chain of dependent node reads
+// sets the latency.
+//
+// The 64 lanes search every tree of the query at once.  The query's k best
+// keys are spread over the lanes (lane i holds the i-th best; a candidate is
+// placed with one ballot and one shuffle), so the prune bound is one
+// wave-uniform value.  The search:
+//  1. descends the largest tree along the query's side of each split and
+//     scans the leaf it reaches, which gives a first bound;
+//  2. repeatedly pops up to 64 pending nodes (all trees' roots to begin
+//     with) from a stack in LDS, one per lane; a node whose box lies
+//     strictly farther than the bound is dropped, an internal node pushes
+//     its far and then its near child, and the leaves' records are scanned
+//     by the whole wave;
+//  3. if the stack is close to full (`cap` entries are usable, at most
+//     kQStack), the top pending subtree is walked by
+//     the whole wave without a stack, through parent links (descend,
+//     unwind, enter the far side when its box may hold a better point).
+// A key already held is not inserted again, so a leaf met twice is
+// harmless.  Any visiting order gives the exact k nearest, as in the other
+// kernels.
+constexpr int kQStack = 2048;        // pending nodes per wave (LDS)
+constexpr int kQViewShift = 26;      // stack entry: view << 26 | node
+constexpr uint32_t kQNodeMask = (1u << kQViewShift) - 1u;
+
+// qq[dim] for a per-lane dim, by masks (a chain of selects here would be
+// turned into an indexed load from private memory)
+template <int D>
+__device__ __forceinline__ float select_dim_masked(const float (&qq)[D], int dim) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) r |= (dim == j ? 0xFFFFFFFFu : 0u) & __float_as_uint(qq[j]);
+  return __uint_as_float(r);
+}
+
+__device__ inline uint64_t lanemask_lt64() {
+  const int l = __lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ inline uint64_t shfl_up64(uint64_t v, int d) {
+  const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, d, 64);
+  const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), d, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t readlane64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// The wave's k best keys, lane i holding the i-th (lanes >= k hold keys that
+// never decide a position below k).
+struct WaveTopK {
+  uint64_t key;
+  uint64_t worst;  // the k-th best key (wave-uniform)
+  int k;
+
+  __device__ __forceinline__ void init(int kk) {
+    k = kk;
+    key = kPadKey;
+    worst = kPadKey;
+  }
+  // c: wave-uniform candidate
+  __device__ __forceinline__ void insert(uint64_t c) {
+    if (!(c < worst)) return;
+    if (__ballot(key == c)) return;  // held already
+    const uint64_t gt = __ballot(key > c);
+    const int p = gt ? __builtin_ctzll(gt) : 64;
+    if (p >= k) return;
+    const uint64_t up = shfl_up64(key, 1);
+    const int lane = __lane_id();
+    key = lane == p ? c : (lane > p ? up : key);
+    worst = readlane64(key, k - 1);
+  }
+};
+
+template <int D>
+__device__ __forceinline__ void scan_leaf_wave(const float (&qq)[D], const float* __restrict__ rec,
+                                      uint32_t a, uint32_t b, WaveTopK& T) {
+  constexpr int S = (D + 1 + 3) & ~3;
+  const int lane = __lane_id();
+  for (uint32_t base = a; base < a + b; base += 64) {
+    const uint32_t idx = base + (uint32_t)lane;
+    uint64_t cand = kPadKey;
+    if (idx < a + b) {
+      const float* r = rec + (uint64_t)idx * S;
+      const uint32_t id = __float_as_uint(r[D]);
+      if (id != kTomb) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          const float tt = qq[j] - r[j];
+          acc = __builtin_fmaf(tt, tt, acc);
+        }
+        cand = ((uint64_t)__float_as_uint(acc) << 32) | id;
+      }
+    }
+    uint64_t m = __ballot(cand < T.worst);
+    while (m) {
+      const int l = __builtin_ctzll(m);
+      m &= m - 1;
+      T.insert(readlane64(cand, l));
+    }
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256)
+k_knn_query(KnnQueries Q, const uint32_t* __restrict__ order, const LevelViews* __restrict__ views,
+            uint32_t* __restrict__ err, unsigned long long* __restrict__ stats, int cap) {
+  constexpr int NS = (5 + 2 * D + 3) & ~3;
+  constexpr int NV = NS / 4;
+  __shared__ uint32_t stack_all[4][kQStack];
+  const int lane = __lane_id();
+  const int w = threadIdx.x >> 6;
+  uint32_t* stk = stack_all[w];
+  const uint64_t nq = Q.nq_dev ? *Q.nq_dev : Q.nq;
+  const uint64_t t = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (uint64_t)w;
+  if (t >= nq) return;  // the whole wave
+  const uint64_t gi = order ? (uint64_t)order[t] : t;
+  const uint32_t rq = Q.qreq ? Q.qreq[gi] : 0u;
+  const int k = Q.qreq ? Q.reqs[rq].k : Q.one.k;
+  float qq[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) qq[j] = Q.q[gi * D + j];
+  WaveTopK T;
+  T.init(k);
+  const int nviews = views->n;
+  uint64_t c_nodes = 0, c_leaves = 0, c_points = 0;
+  bool bad = false;
+
+  // 1. seed: the largest tree, along the query's side of every split
+  if (nviews > 0 && views->v[0].n_nodes > 0) {
+    const LevelView V = views->v[0];
+    const cvf4_ptr nodes = as_cvf4(V.nodes);
+    uint32_t n = 0;
+    for (int depth = 0; depth <= kMaxDepth + 1; ++depth) {
+      float f[NS];
+      load_node<NV>(nodes, (int)n, f);
+      ++c_nodes;
+      const int dim = __float_as_int(f[NF_DIM]);
+      const uint32_t a = (uint32_t)__float_as_int(f[NF_A]);
+      const uint32_t b = (uint32_t)__float_as_int(f[NF_B]);
+      if (dim < 0) {
+        if (a > V.n_slots || b > V.n_slots - a) {
+          bad = true;
+          break;
+        }
+        ++c_leaves;
+        c_points += b;
+        scan_leaf_wave<D>(qq, V.rec, a, b, T);
+        break;
+      }
+      n = select_dim_masked<D>(qq, dim) < f[NF_SPLIT] ? a : b;
+      if (n >= V.n_nodes) {
+        bad = true;
+        break;
+      }
+    }
+  }
+
+  // 2. wide search over every tree
+  int size = 0;
+  for (int v = 0; v < nviews; ++v)
+    if (views->v[v].n_nodes > 0 && size < cap) {
+      if (lane == 0) stk[size] = (uint32_t)v << kQViewShift;
+      ++size;
+    }
+  uint64_t rounds_left = 1;
+  for (int v = 0; v < nviews; ++v) rounds_left += 4ull * views->v[v].n_nodes + 16;
+  while (size > 0 && !bad) {
+    if (--rounds_left == 0) {
+      bad = true;
+      break;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (cap - size < 128) {
+      // 3. stack nearly full: walk the top pending subtree without a stack
+      --size;
+      const uint32_t e = stk[size];
+      const int v = (int)(e >> kQViewShift);
+      const uint32_t root = e & kQNodeMask;
+      const LevelView V = views->v[v];
+      const cvf4_ptr nodes = as_cvf4(V.nodes);
+      uint32_t n = root;
+      bool up = false;
+      uint64_t steps = 4ull * V.n_nodes + 16;
+      while (true) {
+        if (--steps == 0 || n >= V.n_nodes) {
+          bad = true;
+          break;
+        }
+        if (!up) {
+          float f[NS];
+          load_node<NV>(nodes, (int)n, f);
+          ++c_nodes;
+          if (box_dist2<D>(qq, f + NF_BOX) > __uint_as_float((uint32_t)(T.worst >> 32))) {
+            up = true;
+            continue;
+          }
+          const int dim = __float_as_int(f[NF_DIM]);
+          const uint32_t a = (uint32_t)__float_as_int(f[NF_A]);
+          const uint32_t b = (uint32_t)__float_as_int(f[NF_B]);
+          if (dim < 0) {
+            if (a > V.n_slots || b > V.n_slots - a) {
+              bad = true;
+              break;
+            }
+            ++c_leaves;
+            c_points += b;
+            scan_leaf_wave<D>(qq, V.rec, a, b, T);
+            up = true;
+            continue;
+          }
+          n = select_dim_masked<D>(qq, dim) < f[NF_SPLIT] ? a : b;
+        } else {
+          if (n == root) break;
+          const uint32_t p = (uint32_t)__float_as_int(nodes[(uint64_t)n * NV + 1].x);
+          if (p >= V.n_nodes) {
+            bad = true;
+            break;
+          }
+          const vf4 h = nodes[(uint64_t)p * NV];
+          const int dim = __float_as_int(h.y);
+          const uint32_t a = (uint32_t)__float_as_int(h.z);
+          const uint32_t b = (uint32_t)__float_as_int(h.w);
+          const uint32_t nearc = select_dim_masked<D>(qq, dim) < h.x ? a : b;
+          if (n == nearc) {
+            n = nearc == a ? b : a;
+            up = false;
+          } else {
+            n = p;
+          }
+        }
+      }
+      continue;
+    }
+    // pop up to 64 pending nodes, one per lane
+    const int m = size < 64 ? size : 64;
+    const bool act0 = lane < m;
+    const uint32_t e = act0 ? stk[size - 1 - lane] : 0u;
+    size -= m;
+    __builtin_amdgcn_wave_barrier();
+    const int v = (int)(e >> kQViewShift);
+    const uint32_t n = e & kQNodeMask;
+    const LevelView* Vp = &views->v[v];
+    const uint32_t nn = act0 ? Vp->n_nodes : 0u;
+    const uint32_t ns = act0 ? Vp->n_slots : 0u;
+    bool act = act0 && n < nn;
+    if (__ballot(act0 && !act)) bad = true;
+    float f[NS];
+    if (act) {
+      const float4* np = reinterpret_cast<const float4*>(Vp->nodes) + (uint64_t)n * NV;
+#pragma unroll
+      for (int u = 0; u < NV; ++u) {
+        const float4 x = np[u];
+        f[4 * u + 0] = x.x;
+        f[4 * u + 1] = x.y;
+        f[4 * u + 2] = x.z;
+        f[4 * u + 3] = x.w;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < NS; ++u) f[u] = 0.0f;
+    }
+    c_nodes += (uint64_t)__popcll(__ballot(act));
+    const float worst = __uint_as_float((uint32_t)(T.worst >> 32));
+    act = act && !(box_dist2<D>(qq, f + NF_BOX) > worst);
+    const int dim = __float_as_int(f[NF_DIM]);
+    const uint32_t a = (uint32_t)__float_as_int(f[NF_A]);
+    const uint32_t b = (uint32_t)__float_as_int(f[NF_B]);
+    const bool inner = act && dim >= 0;
+    const bool leafn = act && dim < 0;
+    if (__ballot(inner && (a >= nn || b >= nn))) bad = true;
+    if (__ballot(leafn && (a > ns || b > ns - a))) bad = true;
+    if (bad) break;
+    // push the children of inner nodes: far first, near on top
+    const uint64_t im = __ballot(inner);
+    if (inner) {
+      const uint32_t nearc = select_dim_masked<D>(qq, dim) < f[NF_SPLIT] ? a : b;
+      const uint32_t farc = nearc == a ? b : a;
+      const int pos = size + 2 * (int)__popcll(im & lanemask_lt64());
+      const uint32_t tag = (uint32_t)v << kQViewShift;
+      stk[pos] = tag | farc;
+      stk[pos + 1] = tag | nearc;
+    }
+    size += 2 * (int)__popcll(im);
+    // scan the leaves, one after another with the whole wave
+    uint64_t lm = __ballot(leafn);
+    while (lm) {
+      const int l = __builtin_ctzll(lm);
+      lm &= lm - 1;
+      const int lv = __builtin_amdgcn_readlane(v, l);
+      const uint32_t la = (uint32_t)__builtin_amdgcn_readlane((int)a, l);
+      const uint32_t lb = (uint32_t)__builtin_amdgcn_readlane((int)b, l);
+      ++c_leaves;
+      c_points += lb;
+      scan_leaf_wave<D>(qq, views->v[lv].rec, la, lb, T);
+    }
+  }
+  if (bad && lane == 0) atomicOr(err, 32u);
+  if (stats && lane == 0) {
+    atomicAdd(&stats[0], (unsigned long long)c_nodes);
+    atomicAdd(&stats[1], (unsigned long long)c_leaves);
+    atomicAdd(&stats[2], (unsigned long long)c_points);
+  }
+  const KnnReqDev R = Q.qreq ? Q.reqs[rq] : Q.one;
+  const uint64_t qi = gi - R.qoff;
+  if (lane < k) {
+    const uint64_t o = qi * (uint64_t)k + (uint64_t)lane;
+    R.out_ids[o] = (uint32_t)T.key;
+    R.out_d2[o] = __uint_as_float((uint32_t)(T.key >> 32));
+  }
+}
+
 template <int D, int KMAX>
 void launch_one(const KnnLaunch& L, const KnnQueries& Q, uint64_t grid_q, const uint32_t* order,
                 const LevelViews* views, uint32_t* err, unsigned long long* stats,
@@ -540,6 +859,13 @@ template <int D>
 void launch_d(const KnnLaunch& L, int kmax, const KnnQueries& Q, uint64_t grid_q,
               const uint32_t* order, const LevelViews* views, uint32_t* err,
               unsigned long long* st, hipStream_t s) {
+  if (L.mode == kKnnQuery) {
+    if (L.dry_run) return;
+    const unsigned g = (unsigned)((grid_q + 3) / 4);
+    const int cap = L.qstack < 130 ? 130 : (L.qstack > kQStack ? kQStack : L.qstack);
+    hipLaunchKernelGGL((k_knn_query<D>), dim3(g), dim3(256), 0, s, Q, order, views, err, st, cap);
+    return;
+  }
   if (L.mode == kKnnWave) {
     // register arrays sized to the common k exactly (no sentinel slots)
     if (kmax == 1) return launch_one<D, 1>(L, Q, grid_q, order, views, err, st, s);

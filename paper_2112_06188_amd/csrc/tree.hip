@@ -72,6 +72,8 @@ struct bdl_tree {
   int knn_block = 256;
   int use_graphs = 1;
   int persistent = 2;  // 2: on for the wavefront kernel
+  uint64_t query_max = 131072;  // auto: batches up to this size use one wave per query
+  int query_stack = 1 << 30;  // pending-node entries per wave of that kernel
   uint64_t sort_min = kSortQueriesMin;
   std::vector<bdl_knn_shape> shapes;  // launch-shape table (autotuned)
   uint32_t* d_queue = nullptr;        // work counters of persistent k-NN launches
@@ -557,6 +559,7 @@ bool ensure_batch_scratch(bdl_tree* t, uint64_t cap) {
 
 // Kernel template bucket of the register array for the largest k.
 int kmax_bucket(int mode, int kmax) {
+  if (mode == kKnnQuery) return kmax;
   if (mode == kKnnWave && (kmax == 1 || kmax == 2 || kmax == 5 || kmax == 10)) return kmax;
   if (kmax <= 4) return 4;
   if (kmax <= 8) return 8;
@@ -574,26 +577,39 @@ int kmax_bucket(int mode, int kmax) {
 KnnLaunch choose_launch(const bdl_tree* t, int kmax, uint64_t nq, bool* sort) {
   KnnLaunch L;
   L.mode = t->knn_mode;
+  // the wavefront-per-query kernel keeps node indices in 26 bits
+  uint64_t max_nodes = (uint64_t)t->b_nodes;
+  for (int i = 0; i < kMaxLevels; ++i)
+    if (t->lev[i].on && (uint64_t)t->lev[i].n_nodes > max_nodes) max_nodes = t->lev[i].n_nodes;
+  const bool query_ok = max_nodes < kKnnQueryMaxNodes;
   if (L.mode == kKnnAuto) {
-    // the wavefront kernel pays off when the queries are dense among the
-    // points (queries adjacent on the Hilbert curve then share most of their paths);
-    // sparse queries take one lane each
+    // a small batch leaves the device idle with one lane per query: one
+    // wavefront searches each query; the wavefront-per-group kernel pays
+    // off when the queries are dense among the points (queries adjacent on
+    // the Hilbert curve then share most of their paths); otherwise sparse
+    // queries take one lane each
     const int64_t live = bdl_size(t);
-    L.mode = (nq >= 65536 && (int64_t)nq * 2 >= live) ? kKnnWave : kKnnLane;
+    if (nq <= t->query_max && query_ok)
+      L.mode = kKnnQuery;
+    else
+      L.mode = (nq >= 65536 && (int64_t)nq * 2 >= live) ? kKnnWave : kKnnLane;
   }
   L.block = t->knn_block;
   L.persistent = t->persistent == 2 ? (L.mode == kKnnWave ? 1 : 0) : t->persistent;
   L.queue = t->d_queue;
+  L.qstack = t->query_stack;
   bool srt = nq >= t->sort_min;
   for (const bdl_knn_shape& r : t->shapes) {
     if (kmax < r.k_lo || kmax > r.k_hi || (int64_t)nq < r.nq_lo || (int64_t)nq > r.nq_hi)
       continue;
+    if (r.kernel == kKnnQuery && !query_ok) continue;
     L.mode = r.kernel;
     L.block = r.block;
     L.persistent = r.persistent;
     srt = r.sort != 0;
     break;
   }
+  if (L.mode == kKnnQuery && !query_ok) L.mode = kKnnLane;
   if (sort) *sort = srt;
   return L;
 }
@@ -815,7 +831,7 @@ int bdl_set_param(bdl_tree* t, int32_t param, int64_t value) {
   if (!t) return fail(BDL_EINVAL, "null tree");
   switch (param) {
     case BDL_PARAM_KNN_KERNEL:
-      if (value != kKnnLane && value != kKnnWave && value != kKnnAuto)
+      if (value != kKnnLane && value != kKnnWave && value != kKnnAuto && value != kKnnQuery)
         return fail(BDL_EINVAL, "unknown k-NN kernel");
       t->knn_mode = (int)value;
       return 0;
@@ -832,6 +848,15 @@ int bdl_set_param(bdl_tree* t, int32_t param, int64_t value) {
       if (value != 0 && value != 1) return fail(BDL_EINVAL, "use_graphs is 0 or 1");
       t->use_graphs = (int)value;
       return 0;
+    case BDL_PARAM_QUERY_STACK:
+      if (value < 130 || value > (1 << 30)) return fail(BDL_EINVAL, "query stack out of range");
+      t->query_stack = (int)value;
+      destroy_graphs(t);
+      return 0;
+    case BDL_PARAM_QUERY_MAX:
+      if (value < 0) return fail(BDL_EINVAL, "query_max must be >= 0");
+      t->query_max = (uint64_t)value;
+      return 0;
     case BDL_PARAM_PERSISTENT:
       if (value < 0 || value > 2) return fail(BDL_EINVAL, "persistent is 0, 1 or 2");
       t->persistent = (int)value;
@@ -847,7 +872,7 @@ int bdl_set_knn_shapes(bdl_tree* t, const bdl_knn_shape* rows, int32_t n) {
   for (int32_t i = 0; i < n; ++i) {
     const bdl_knn_shape& r = rows[i];
     if (r.k_lo < 1 || r.k_hi > BDL_MAX_K || r.k_lo > r.k_hi || r.nq_lo < 0 || r.nq_lo > r.nq_hi ||
-        (r.kernel != kKnnLane && r.kernel != kKnnWave) ||
+        (r.kernel != kKnnLane && r.kernel != kKnnWave && r.kernel != kKnnQuery) ||
         (r.block != 64 && r.block != 128 && r.block != 256) || (r.persistent & ~1) ||
         (r.sort & ~1))
       return fail(BDL_EINVAL, "shape row " + std::to_string(i) + " out of range");

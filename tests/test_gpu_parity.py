@@ -42,7 +42,7 @@ def _pair(bdl, d, leaf, X, idcap=1 << 22, knn_kernel=None, **kw):
     return t, oracle.OracleBDL(d, leaf, X)
 
 
-KERNELS = [0, 1]  # one lane per query; one wavefront per 64 queries
+KERNELS = [0, 1, 3]  # one lane per query; one wavefront per 64 queries; one per query
 
 
 def test_single_insert_small(torch, bdl):
@@ -222,3 +222,22 @@ def test_drain_to_empty_with_half_rule(torch, bdl):
     run_parity(t, o, ops, torch, d, what="drain")
     assert t.size() == 0 and t.level_info()["F"] == 0
     assert o.level_info()["reinserted"] > 0
+
+
+@pytest.mark.parametrize("d,k,stack", [(3, 5, 130), (3, 64, 130), (16, 64, 130), (16, 17, 2048),
+                                       (7, 10, 300)])
+def test_query_wave_kernel_stack_limits(torch, bdl, d, k, stack):
+    """One wavefront per query with a small pending-node stack: subtrees that
+    do not fit are walked through parent links instead.  Clustered points
+    with exact duplicates, several trees and a buffer."""
+    log(f"case: query kernel d={d} k={k} stack={stack}")
+    t, o = _pair(bdl, d, 8, 64, knn_kernel=3)
+    t.set_param(bdl.PARAM_QUERY_STACK, stack)
+    p = clustered_points(30_000, d, 50 + d, n_clusters=6)
+    p[1000:1400] = p[5]
+    ids = np.arange(30_000, dtype=np.uint32)
+    q = np.concatenate([clustered_points(700, d, 60 + d, n_clusters=6), p[::97],
+                        uniform_points(300, d, 61)]).astype(np.float32)
+    ops = [Op("insert", p[:20_000], ids[:20_000]), Op("insert", p[20_000:], ids[20_000:]),
+           Op("knn", q, k=k), Op("erase", p[::3], ids[::3]), Op("knn", q, k=k)]
+    run_parity(t, o, ops, torch, d, check_structure=False, what=f"query d={d} k={k}")
