@@ -134,7 +134,7 @@ int bdl_set_param(bdl_tree* t, int32_t param, int64_t value);
 /* One row of a launch-shape table for kNN_L (bdl_knn and bdl_knn_batch).  A
  * launch whose largest k lies in [k_lo, k_hi] and whose query count lies in
  * [nq_lo, nq_hi] uses this row's kernel, workgroup size, persistence and
- * (bdl_knn only) Hilbert-curve ordering; the first matching row wins and a launch
+ * Hilbert-curve ordering; the first matching row wins and a launch
  * no row matches uses the values of bdl_set_param.  Rows come from an
  * autotuner that times the candidates on the device.  Shapes change speed,
  * never results. */
@@ -145,8 +145,10 @@ typedef struct {
                            BDL_PARAM_KNN_KERNEL) */
   int32_t block;        /* 64, 128 or 256 */
   int32_t persistent;   /* 0 or 1 */
-  int32_t sort;         /* 0 or 1: order the queries of a bdl_knn call along the Hilbert curve
-                           (bdl_knn_batch always orders them) */
+  int32_t sort;         /* 0 or 1: order the queries along the Hilbert curve
+                           first (by default: for the wavefront-per-group
+                           kernel, and for the lane kernel from
+                           BDL_PARAM_SORT_MIN queries on) */
 } bdl_knn_shape;
 
 #define BDL_MAX_SHAPES 256

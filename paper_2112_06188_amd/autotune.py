@@ -58,14 +58,12 @@ def tune(tree, make_queries: Callable[[int], "object"], *,
     make_queries(n) returns n queries as a device tensor [n, dim] float32.
     A band is timed with k = its upper end and nq = min(its upper end,
     max_nq).  batched=True times bdl_knn_batch with one request per call
-    (the graph path) instead of bdl_knn, and ignores `sort`.
+    (the graph path) instead of bdl_knn.
     Returns {"rows": [...], "timings": [...]} and installs the rows.
     """
     import torch
 
     cands = list(cands) if cands is not None else candidates()
-    if batched:
-        cands = [c for c in cands if c["sort"] == 1]
     stream = tree.stream
     rows, timings = [], []
     saved = list(getattr(tree, "_shapes", []))

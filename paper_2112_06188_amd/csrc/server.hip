@@ -3,8 +3,12 @@
 // batching of k-NN requests into bdl_knn_batch launches, and copies that
 // overlap device work on two copy streams.
 //
-// One worker thread owns the tree.  Client threads only touch the pending
-// queue and the completion table, under one mutex.
+// One worker thread owns the tree and only orchestrates device work.  The
+// host copies run on the client threads: a submission copies its inputs
+// into pinned staging, and handing out a completion copies its outputs from
+// pinned staging into the client's buffers.  Client threads touch the
+// pending queue and the completion table under one mutex, and the pinned
+// cache under another.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -72,6 +76,7 @@ class SizeClassCache {
 
 struct Req {
   uint64_t ticket = 0;
+  size_t h_in_bytes = 0, h_out_bytes = 0;  // pinned staging size classes
   bdl_request r{};
   bdl_completion c{};
   size_t in_bytes = 0, out_bytes = 0;  // staging sizes (rounded classes)
@@ -102,13 +107,15 @@ struct bdl_server {
   std::condition_variable cv_done;     // completions
   bool stop = false;
   std::deque<Req*> pending;            // submitted, not admitted (arrival order)
-  std::unordered_map<uint64_t, bdl_completion> done;  // completed, not handed out
+  std::unordered_map<uint64_t, Req*> done;  // completed, not handed out
   std::deque<uint64_t> done_order;
   std::unordered_set<uint64_t> outstanding;  // submitted, completion not handed out
   uint64_t next_ticket = 1;
   uint64_t submitted = 0, completed = 0;
+  std::mutex hmu;                      // guards hcache (client threads)
+  SizeClassCache hcache{true};
   // worker-only state
-  SizeClassCache dcache{false}, hcache{true};
+  SizeClassCache dcache{false};
   std::vector<hipEvent_t> free_events;
   uint64_t next_seq = 0;
   int64_t next_launch = 0;
@@ -150,26 +157,57 @@ void put_event(bdl_server* s, hipEvent_t e) {
   if (e) s->free_events.push_back(e);
 }
 
-// Give the request its device and pinned staging and start its input copy on
-// the h2d stream.  Returns false (status set) if memory is short.
-bool stage(bdl_server* s, Req* q) {
+// Pinned staging of a request, filled with its inputs (client thread, at
+// submission).  Returns false if pinned memory is short.
+bool host_stage(bdl_server* s, Req* q) {
   const size_t n = (size_t)q->r.n;
-  q->d_in = s->dcache.take(q->in_bytes);
-  q->h_in = s->hcache.take(q->in_bytes);
-  if (q->out_bytes) {
-    q->d_out = s->dcache.take(q->out_bytes);
-    q->h_out = s->hcache.take(q->out_bytes);
+  {
+    std::lock_guard<std::mutex> lk(s->hmu);
+    q->h_in = s->hcache.take(q->h_in_bytes);
+    q->h_out = q->h_out_bytes ? s->hcache.take(q->h_out_bytes) : nullptr;
   }
-  q->ev_in = get_event(s);
-  if (!q->d_in || !q->h_in || (q->out_bytes && (!q->d_out || !q->h_out)) || !q->ev_in) {
-    q->c.status = BDL_ENOMEM;
-    return false;
-  }
+  if (!q->h_in || (q->h_out_bytes && !q->h_out)) return false;
   const size_t pb = n * s->d * 4;
   if (n) {
     std::memcpy(q->h_in, q->r.pts, pb);
     if (q->r.kind != BDL_REQ_KNN) std::memcpy((char*)q->h_in + pb, q->r.ids, n * 4);
   }
+  return true;
+}
+
+void host_unstage(bdl_server* s, Req* q) {
+  std::lock_guard<std::mutex> lk(s->hmu);
+  s->hcache.give(q->h_in, q->h_in_bytes);
+  s->hcache.give(q->h_out, q->h_out_bytes);
+  q->h_in = q->h_out = nullptr;
+}
+
+// Hand a completed request to a client: outputs into its buffers, pinned
+// staging back to the cache (client thread).
+bdl_completion hand_out(bdl_server* s, Req* q) {
+  if (q->c.status == BDL_OK && q->r.kind == BDL_REQ_KNN && q->r.n) {
+    const size_t m = (size_t)q->r.n * q->r.k;
+    std::memcpy(q->r.out_ids, q->h_out, m * 4);
+    std::memcpy(q->r.out_d2, (char*)q->h_out + m * 4, m * 4);
+  }
+  host_unstage(s, q);
+  const bdl_completion c = q->c;
+  delete q;
+  return c;
+}
+
+// Give the request its device staging and start its input copy on the h2d
+// stream.  Returns false (status set) if memory is short.
+bool stage(bdl_server* s, Req* q) {
+  const size_t n = (size_t)q->r.n;
+  q->d_in = s->dcache.take(q->in_bytes);
+  if (q->out_bytes) q->d_out = s->dcache.take(q->out_bytes);
+  q->ev_in = get_event(s);
+  if (!q->d_in || (q->out_bytes && !q->d_out) || !q->ev_in) {
+    q->c.status = BDL_ENOMEM;
+    return false;
+  }
+  const size_t pb = n * s->d * 4;
   const size_t bytes = pb + (q->r.kind != BDL_REQ_KNN ? n * 4 : 0);
   if ((bytes && hipMemcpyAsync(q->d_in, q->h_in, bytes, hipMemcpyHostToDevice, s->h2d) !=
                     hipSuccess) ||
@@ -182,35 +220,27 @@ bool stage(bdl_server* s, Req* q) {
 
 void unstage(bdl_server* s, Req* q) {
   s->dcache.give(q->d_in, q->in_bytes);
-  s->hcache.give(q->h_in, q->in_bytes);
-  if (q->out_bytes) {
-    s->dcache.give(q->d_out, q->out_bytes);
-    s->hcache.give(q->h_out, q->out_bytes);
-  }
+  if (q->out_bytes) s->dcache.give(q->d_out, q->out_bytes);
   put_event(s, q->ev_in);
-  q->d_in = q->d_out = q->h_in = q->h_out = nullptr;
+  q->d_in = q->d_out = nullptr;
   q->ev_in = nullptr;
 }
 
-// Hand the request's completion to the clients and free its slot.
+// The request's device work and output copy are done: free its device
+// staging and slot and post its completion (the outputs are copied to the
+// client's buffers when the completion is handed out).
 void finish(bdl_server* s, Req* q) {
-  if (q->c.status == BDL_OK && q->r.kind == BDL_REQ_KNN && q->r.n) {
-    const size_t m = (size_t)q->r.n * q->r.k;
-    std::memcpy(q->r.out_ids, q->h_out, m * 4);
-    std::memcpy(q->r.out_d2, (char*)q->h_out + m * 4, m * 4);
-  }
   unstage(s, q);
   q->c.t_done_ms = ms_since(s);
+  --s->inflight;
+  s->used -= q->in_bytes + q->out_bytes;
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    s->done.emplace(q->ticket, q->c);
+    s->done.emplace(q->ticket, q);
     s->done_order.push_back(q->ticket);
     ++s->completed;
   }
   s->cv_done.notify_all();
-  --s->inflight;
-  s->used -= q->in_bytes + q->out_bytes;
-  delete q;
 }
 
 // Admit pending requests in arrival order while a slot is free and their
@@ -410,6 +440,7 @@ int bdl_server_create(bdl_tree* t, const bdl_server_config* cfg, bdl_server** ou
 
 int bdl_server_submit(bdl_server* s, const bdl_request* r, uint64_t* ticket) {
   if (!s || !r) return bdl::tree_fail(BDL_EINVAL, "null argument");
+  const double t_arrive = ms_since(s);
   if (r->kind != BDL_REQ_KNN && r->kind != BDL_REQ_INSERT && r->kind != BDL_REQ_ERASE)
     return bdl::tree_fail(BDL_EINVAL, "unknown request kind");
   if (r->n < 0) return bdl::tree_fail(BDL_EINVAL, "negative size");
@@ -425,17 +456,32 @@ int bdl_server_submit(bdl_server* s, const bdl_request* r, uint64_t* ticket) {
     delete q;
     return bdl::tree_fail(BDL_EINVAL, "request larger than the memory budget");
   }
-  q->c.kind = r->kind;
-  q->c.launch = -1;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) {
       delete q;
       return bdl::tree_fail(BDL_EINVAL, "server is stopping");
     }
+  }
+  q->h_in_bytes = q->in_bytes;
+  q->h_out_bytes = q->out_bytes;
+  if (!host_stage(s, q)) {
+    host_unstage(s, q);
+    delete q;
+    return bdl::tree_fail(BDL_ENOMEM, "cannot allocate pinned staging");
+  }
+  q->c.kind = r->kind;
+  q->c.launch = -1;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) {
+      host_unstage(s, q);
+      delete q;
+      return bdl::tree_fail(BDL_EINVAL, "server is stopping");
+    }
     q->ticket = s->next_ticket++;
     q->c.ticket = q->ticket;
-    q->c.t_submit_ms = ms_since(s);
+    q->c.t_submit_ms = t_arrive;
     s->pending.push_back(q);
     s->outstanding.insert(q->ticket);
     ++s->submitted;
@@ -452,26 +498,32 @@ int bdl_server_wait(bdl_server* s, uint64_t ticket, bdl_completion* out) {
     return bdl::tree_fail(BDL_EINVAL, "unknown ticket, or its completion was handed out");
   s->cv_done.wait(lk, [&] { return s->done.count(ticket) > 0; });
   auto it = s->done.find(ticket);
-  if (out) *out = it->second;
+  Req* q = it->second;
   s->done.erase(it);
   s->outstanding.erase(ticket);
+  lk.unlock();
+  const bdl_completion c = hand_out(s, q);
+  if (out) *out = c;
   return BDL_OK;
 }
 
 int bdl_server_poll(bdl_server* s, bdl_completion* out, int32_t max, int32_t* n) {
   if (!s || (max > 0 && !out)) return bdl::tree_fail(BDL_EINVAL, "null argument");
-  std::lock_guard<std::mutex> lk(s->mu);
-  int32_t m = 0;
-  while (m < max && !s->done_order.empty()) {
-    const uint64_t tk = s->done_order.front();
-    s->done_order.pop_front();
-    auto it = s->done.find(tk);
-    if (it == s->done.end()) continue;  // handed out by bdl_server_wait
-    out[m++] = it->second;
-    s->done.erase(it);
-    s->outstanding.erase(tk);
+  std::vector<Req*> got;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    while ((int32_t)got.size() < max && !s->done_order.empty()) {
+      const uint64_t tk = s->done_order.front();
+      s->done_order.pop_front();
+      auto it = s->done.find(tk);
+      if (it == s->done.end()) continue;  // handed out by bdl_server_wait
+      got.push_back(it->second);
+      s->done.erase(it);
+      s->outstanding.erase(tk);
+    }
   }
-  if (n) *n = m;
+  for (size_t i = 0; i < got.size(); ++i) out[i] = hand_out(s, got[i]);
+  if (n) *n = (int32_t)got.size();
   return BDL_OK;
 }
 
@@ -491,6 +543,11 @@ void bdl_server_destroy(bdl_server* s) {
   }
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
+  for (auto& kv : s->done) {
+    host_unstage(s, kv.second);
+    delete kv.second;
+  }
+  s->done.clear();
   (void)hipStreamSynchronize(s->h2d);
   (void)hipStreamSynchronize(s->d2h);
   for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);

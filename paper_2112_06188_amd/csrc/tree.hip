@@ -598,7 +598,10 @@ KnnLaunch choose_launch(const bdl_tree* t, int kmax, uint64_t nq, bool* sort) {
   L.persistent = t->persistent == 2 ? (L.mode == kKnnWave ? 1 : 0) : t->persistent;
   L.queue = t->d_queue;
   L.qstack = t->query_stack;
-  bool srt = nq >= t->sort_min;
+  // the Hilbert order gives neighbouring queries to neighbouring lanes and
+  // waves: the wavefront-per-group kernel needs it, the lane kernel gains
+  // from it on large batches, one wavefront per query does not use it
+  bool srt = L.mode == kKnnWave || (L.mode == kKnnLane && nq >= t->sort_min);
   for (const bdl_knn_shape& r : t->shapes) {
     if (kmax < r.k_lo || kmax > r.k_hi || (int64_t)nq < r.nq_lo || (int64_t)nq > r.nq_hi)
       continue;
@@ -614,9 +617,11 @@ KnnLaunch choose_launch(const bdl_tree* t, int kmax, uint64_t nq, bool* sort) {
   return L;
 }
 
-int enqueue_batch(bdl_tree* t, hipStream_t s, uint64_t cap, int kt, const KnnLaunch& L) {
+int enqueue_batch(bdl_tree* t, hipStream_t s, uint64_t cap, int kt, const KnnLaunch& L,
+                  bool sort) {
   launch_gather_queries(t->breqs, t->bcount, cap, t->d, t->bq, t->bqreq, s);
-  const uint32_t* order = spatial_order(t->d, t->bq, t->bcount, 0, cap, t->bqs, s);
+  const uint32_t* order =
+      sort ? spatial_order(t->d, t->bq, t->bcount, 0, cap, t->bqs, s) : nullptr;
   KnnQueries Q;
   std::memset(&Q, 0, sizeof(Q));
   Q.q = t->bq;
@@ -662,11 +667,12 @@ int run_batch(bdl_tree* t, const bdl_knn_request* reqs, int nreq) {
     return fail(BDL_EHIP, "request table copy failed");
   t->bslot ^= 1;
   // the shape is chosen for the bucket, so that one graph serves it
-  const KnnLaunch L = choose_launch(t, kmax, cap, nullptr);
+  bool sort = true;
+  const KnnLaunch L = choose_launch(t, kmax, cap, &sort);
   const int kt = kmax_bucket(L.mode, kmax);
   t->pt.begin(BDL_PH_TRAVERSE);
   if (t->use_graphs) {
-    const auto key = std::make_tuple(cap, kt, L.mode, L.block, L.persistent);
+    const auto key = std::make_tuple(cap, kt, L.mode, L.block, L.persistent * 2 + (sort ? 1 : 0));
     auto it = t->graphs.find(key);
     if (it == t->graphs.end()) {
       hipGraph_t g = nullptr;
@@ -677,7 +683,7 @@ int run_batch(bdl_tree* t, const bdl_knn_request* reqs, int nreq) {
                        t->cap_stream);
       if (hipStreamBeginCapture(t->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(BDL_EHIP, "graph capture failed to start");
-      int rc = enqueue_batch(t, t->cap_stream, cap, kt, L);
+      int rc = enqueue_batch(t, t->cap_stream, cap, kt, L, sort);
       hipError_t e = hipStreamEndCapture(t->cap_stream, &g);
       if (rc || e != hipSuccess || !g) {
         if (g) (void)hipGraphDestroy(g);
@@ -692,7 +698,7 @@ int run_batch(bdl_tree* t, const bdl_knn_request* reqs, int nreq) {
     if (hipGraphLaunch(it->second, t->s) != hipSuccess)
       return fail(BDL_EHIP, "graph launch failed");
   } else {
-    int rc = enqueue_batch(t, t->s, cap, kt, L);
+    int rc = enqueue_batch(t, t->s, cap, kt, L, sort);
     if (rc) return fail(rc, "batched k-NN launch failed");
   }
   t->pt.end(BDL_PH_TRAVERSE);
