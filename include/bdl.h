@@ -90,7 +90,11 @@ int bdl_insert(bdl_tree* t, const float* pts, const uint32_t* ids, int64_t n);
  * it is a no-op.  A repeated id erases once.  Afterwards every static tree
  * whose live count is below half of its capacity 2^i X is rebuilt through
  * Insert_L.  Synchronises the stream once to read the per-tree live counts.
- * n_erased (host, may be NULL) receives the number of points erased. */
+ * n_erased (host, may be NULL) receives the number of points erased.
+ * Memory: BDL_ENOMEM before the erase step leaves the tree unchanged; if the
+ * rebuild cannot get memory (a static tree's first arena), the erase has
+ * still taken effect, the trees below half stay as they are (a later erase
+ * rebuilds them) and BDL_ENOMEM is returned. */
 int bdl_erase(bdl_tree* t, const float* pts, const uint32_t* ids, int64_t n,
               int64_t* n_erased);
 

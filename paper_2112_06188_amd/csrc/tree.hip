@@ -331,14 +331,20 @@ void upload_views(bdl_tree* t) {
 //    slot order) followed by the leading pool slice that fills its nominal
 //    capacity 2^j* X; each other new tree, highest first, takes the next
 //    pool slice of 2^j X points.
-int insert_impl(bdl_tree* t, const float* batch, const uint32_t* batch_ids, int64_t n) {
+// Insert_L of n points (caller rows with ids, or records when batch_ids is
+// null).  Trees in pre_clear are taken out first (Erase_L's half rule: their
+// live points are in the batch); they stay untouched unless the insert
+// succeeds, so that BDL_ENOMEM leaves the trees as they were.
+int insert_impl(bdl_tree* t, const float* batch, const uint32_t* batch_ids, int64_t n,
+                uint64_t pre_clear = 0) {
   const int64_t X = t->cfg.buffer_size;
   const int64_t pn = t->bn + n;
   const uint64_t m = (uint64_t)(pn / X);
-  const uint64_t Fn = t->F + m;
+  const uint64_t F0 = t->F & ~pre_clear;
+  const uint64_t Fn = F0 + m;
   if (Fn >> (kMaxLevels - 1)) return fail(BDL_EINVAL, "too many points for the level table");
-  const uint64_t J = Fn & ~t->F;
-  const uint64_t C = t->F & ~Fn;
+  const uint64_t J = Fn & ~F0;
+  const uint64_t C = F0 & ~Fn;
   struct Src {
     int kind;  // 0 whole level, 1 live records of a level, 2 pool range
     int level;
@@ -467,7 +473,7 @@ int insert_impl(bdl_tree* t, const float* batch, const uint32_t* batch_ids, int6
   if (rc) return fail(rc, err ? err : "build failed");
   // ---- commit ----
   for (int i = 0; i < kMaxLevels; ++i) {
-    if (!((C >> i) & 1u)) continue;
+    if (!(((C | pre_clear) >> i) & 1u)) continue;
     LevelState& L = t->lev[i];
     L.on = false;
     L.n_slots = L.live = L.n_nodes = 0;
@@ -1020,8 +1026,10 @@ int bdl_erase(bdl_tree* t, const float* pts, const uint32_t* ids, int64_t n, int
     t->pcur ^= 1;
     t->bn -= bufhits;
   }
-  // half-capacity rule (Alg. 4): gather trees with 2 * live < 2^i X into R
+  // half-capacity rule (Alg. 4): gather trees with 2 * live < 2^i X into R;
+  // the trees are taken out by the insert of R, only if it succeeds
   int64_t rn = 0;
+  uint64_t below = 0;
   for (int i = 0; i < kMaxLevels; ++i) {
     LevelState& L = t->lev[i];
     if (!L.on || 2 * L.live >= L.cap) continue;
@@ -1029,13 +1037,20 @@ int bdl_erase(bdl_tree* t, const float* pts, const uint32_t* ids, int64_t n, int
       launch_compact_live(L.rec, t->d, (uint64_t)L.n_slots, nullptr, 0, 0, t->rbuf + rn * t->S,
                           t->sc.tile_cnt, t->sc.tmp, t->s);
     rn += L.live;
-    L.on = false;
-    L.n_slots = L.live = L.n_nodes = 0;
-    t->F &= ~(1ull << i);
+    below |= 1ull << i;
   }
-  if (rn > 0 || bufhits) {
-    int rc = insert_impl(t, t->rbuf, nullptr, rn);
-    if (rc) return rc;
+  if (rn > 0 || below || bufhits) {
+    int rc = insert_impl(t, t->rbuf, nullptr, rn, below);
+    if (rc) {
+      // the erase took effect; the rebuild did not (the trees below half
+      // stay).  The buffer's tree still holds erased buffer points: rebuild
+      // it alone, which needs no new memory.
+      const std::string msg = g_err;
+      if (bufhits) (void)insert_impl(t, nullptr, nullptr, 0, 0);
+      upload_live(t);
+      upload_views(t);
+      return fail(rc, msg);
+    }
     t->reinserted += rn;
   } else {
     upload_live(t);

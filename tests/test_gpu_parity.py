@@ -241,3 +241,50 @@ def test_query_wave_kernel_stack_limits(torch, bdl, d, k, stack):
     ops = [Op("insert", p[:20_000], ids[:20_000]), Op("insert", p[20_000:], ids[20_000:]),
            Op("knn", q, k=k), Op("erase", p[::3], ids[::3]), Op("knn", q, k=k)]
     run_parity(t, o, ops, torch, d, check_structure=False, what=f"query d={d} k={k}")
+
+
+def test_memory_budget_enomem_leaves_the_tree_unchanged(torch, bdl):
+    """A tree with a device-memory budget: the insert that needs a new
+    static tree beyond the budget fails with BDL_ENOMEM before anything is
+    enqueued, the structure and the results stay those of the oracle that
+    never saw that insert, and later operations within the budget work."""
+    log("case: memory budget")
+    d, X = 3, 256
+    t = bdl.Tree(d, leaf_size=16, buffer_size=X, id_capacity=1 << 20, mem_budget=48 << 20)
+    o = oracle.OracleBDL(d, 16, X)
+    p = uniform_points(400_000, d, 70)
+    ids = np.arange(400_000, dtype=np.uint32)
+    done, failed = 0, False
+    for s0 in range(0, 400_000, 20_000):
+        try:
+            t.insert(to_dev(p[s0:s0 + 20_000], torch), to_dev(ids[s0:s0 + 20_000], torch))
+        except bdl.BdlError as e:
+            assert e.code == bdl.BDL_ENOMEM
+            failed = True
+            break
+        o.insert(p[s0:s0 + 20_000], ids[s0:s0 + 20_000])
+        done = s0 + 20_000
+    assert failed and done > 0
+    compare_structure(t, o, d, "after ENOMEM")
+    q = uniform_points(3000, d, 71)
+    gi, gd = t.knn(to_dev(q, torch), 6)
+    t.sync()
+    oi, od = o.knn(q, 6)
+    assert_knn_equal(gi.cpu().numpy(), gd.cpu().numpy(), oi, od, "knn after ENOMEM")
+    # the tree keeps working: an erase either fails before changing anything
+    # or takes effect; a small insert fits in the arenas already held
+    e = ids[:done:7]
+    try:
+        ne = t.erase(to_dev(p[e.astype(np.int64)], torch), to_dev(e, torch))
+        assert ne == o.erase(p[e.astype(np.int64)], e)
+    except bdl.BdlError as err:
+        assert err.code == bdl.BDL_ENOMEM
+    compare_structure(t, o, d, "after erase")
+    t.insert(to_dev(p[done:done + 100], torch), to_dev(ids[done:done + 100], torch))
+    o.insert(p[done:done + 100], ids[done:done + 100])
+    compare_structure(t, o, d, "after recovery")
+    gi, gd = t.knn(to_dev(q, torch), 6)
+    t.sync()
+    oi, od = o.knn(q, 6)
+    assert_knn_equal(gi.cpu().numpy(), gd.cpu().numpy(), oi, od, "knn after recovery")
+    t.close()
