@@ -38,6 +38,7 @@ if ROOT not in sys.path:
 
 METRIC = "kNN queries/s + update pts/s, 10M 3D pts k=5; p50/p99 latency under mixed load"
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
 # HBM traffic of the traversal kernel measured with rocprofv3 counters
 # (FETCH_SIZE, WRITE_SIZE) and the sources it was measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "knn_traversal_traffic.json")
@@ -170,6 +171,8 @@ def gpu_bench(args):
     # order read, results written, every live tree read once
     alg_bytes = nq * (4 * w.dim + 4 + 8 * k) + tree_bytes
     achieved = alg_bytes / (trav_ms * 1e-3) / 1e9
+    work = prof["knn_work"]
+    valu_flops = float(work["points"] * 3 * w.dim + work["nodes"] * 5 * w.dim) / max(1, args.steps)
     ins_ms = float(np.sum(lat["insert"])) / args.steps
     er_ms = float(np.sum(lat["erase"])) / args.steps
     knn_ms = float(np.sum(lat["knn"])) / args.steps
@@ -206,7 +209,15 @@ def gpu_bench(args):
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "algorithmic_bytes_per_launch": alg_bytes,
-                     "avg_launch_ms": trav_ms},
+                     "avg_launch_ms": trav_ms,
+                     # the same launch against the FP32 vector peak: flops of
+                     # the distance evaluations (sub + fma per coordinate) and
+                     # box tests (two subs, a select and an fma per
+                     # coordinate) the GPU counted
+                     "valu": {"achieved": valu_flops / (trav_ms * 1e-3) / 1e12,
+                              "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": valu_flops / (trav_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+                              "flops_per_launch": valu_flops}},
     }
     tree.close()
     return res, w, (q, out_ids, out_d2)
@@ -260,8 +271,10 @@ def batched_bench(args):
     tq = _dv(torch, uniform_points(1 << 20, w.dim, 999))
     t0 = time.perf_counter()
     tuned = autotune.tune(tree, lambda n: tq[:n], k_bands=((1, 1), (2, 5), (6, 10)),
-                          nq_bands=((1, 2048), (2049, 32768), (32769, 1 << 40)),
+                          nq_bands=((1, 2048), (2049, 32768), (32769, 262144),
+                                    (262145, 1 << 40)),
                           max_nq=1 << 20, reps=2,
+                          cands=autotune.candidates(blocks=(64, 256)),
                           log=lambda m: print(f"batched: tune {m}", file=sys.stderr, flush=True))
     tune_s = time.perf_counter() - t0
     stream = torch.cuda.current_stream()
