@@ -43,7 +43,7 @@ FP32_PEAK_TFLOPS = 157.3
 # (FETCH_SIZE, WRITE_SIZE) and the sources it was measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "knn_traversal_traffic.json")
 TRAVERSAL_SOURCES = [os.path.join(ROOT, "paper_2112_06188_amd", "csrc", f)
-                     for f in ("knn_traverse.hpp", "knn_d1_4.hip", "knn.hip", "tree.hip")]
+                     for f in ("knn_traverse.hpp", "knn_d1_4.hip", "knn.hip")]
 
 
 def traversal_source_hash() -> str:
