@@ -681,7 +681,7 @@ k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounter
 // ------------------------------------------------------------------------
 
 struct Act {
-  uint16_t begin, count, nleft;
+  uint16_t begin, count;
   int8_t dim;
   uint8_t depth;
   float split;
@@ -729,7 +729,11 @@ k_finish(const Fin* fin, uint32_t nfin, const float* soa0, const float* soa1, ui
       sidv[0][i] = 0;
     }
     if (tid < 2 * DMAX) cbox[0][tid] = tid < DMAX ? 0xFFFFFFFFu : 0u;
-    if (tid == 0) s_maxdepth = 0;
+    if (tid == 0) {
+      s_maxdepth = 0;
+      s_nact = 0;
+      s_nemit = 0;
+    }
     int cur = 0;    // pos/sid buffer holding the current order
     int ca = 0;     // act table of the current depth
     uint32_t nch = 1;
@@ -777,13 +781,13 @@ k_finish(const Fin* fin, uint32_t nfin, const float* soa0, const float* soa1, ui
     child_boxes(cur);
     __syncthreads();
 
+    // Per depth: classify the children of the previous depth (their sizes
+    // come from the previous depth's left-count prefix L), emit them, flag
+    // every point's side with a block scan, scatter.  A child's table entry
+    // is found through remap[], so positions are not renumbered in a pass of
+    // their own.
     while (true) {
       // ---- classify the children of the previous depth (or the root) ----
-      if (tid == 0) {
-        s_nact = 0;
-        s_nemit = 0;
-      }
-      __syncthreads();
       const int na = ca ^ 1;  // table that receives this depth's internal nodes
       uint32_t cbegin = 0, ccount = 0, cdepth = 0, cparent = kNone, cside = 0, le = 0;
       uint32_t ai = kNone;
@@ -802,9 +806,10 @@ k_finish(const Fin* fin, uint32_t nfin, const float* soa0, const float* soa1, ui
           cside = F.side;
         } else {
           const Act& A = act[ca][ch >> 1];
+          const uint32_t nl = (uint32_t)L[A.begin + A.count] - (uint32_t)L[A.begin];
           cside = ch & 1u;
-          cbegin = cside ? A.begin + A.nleft : A.begin;
-          ccount = cside ? A.count - A.nleft : A.nleft;
+          cbegin = cside ? A.begin + nl : A.begin;
+          ccount = cside ? A.count - nl : nl;
           cdepth = A.depth + 1u;
           cpath = (A.path << 1) | (uint64_t)cside;
           cparent = A.emit;
@@ -846,7 +851,6 @@ k_finish(const Fin* fin, uint32_t nfin, const float* soa0, const float* soa1, ui
           Act& A = act[na][ai];
           A.begin = (uint16_t)cbegin;
           A.count = (uint16_t)ccount;
-          A.nleft = 0;
           A.dim = (int8_t)cdim;
           A.depth = (uint8_t)cdepth;
           A.split = csplit;
@@ -859,20 +863,15 @@ k_finish(const Fin* fin, uint32_t nfin, const float* soa0, const float* soa1, ui
       const uint32_t nact =
           (s_base == 0xFFFFFFFFu || s_nact > (uint32_t)MAXACT) ? 0u : s_nact;
       if (nact == 0) break;
-      // ---- point each position at its node in the new table ----
-      for (uint32_t i = tid; i < n; i += NT) {
-        uint16_t s = sidv[cur][i];
-        if (s != kFrozen) sidv[cur][i] = remap[s];
-      }
       ca = na;
-      __syncthreads();
       // ---- flags and block-wide exclusive scan (blocked positions) ----
       uint32_t fl = 0, cnt = 0;
 #pragma unroll
       for (int q = 0; q < PT; ++q) {
         const uint32_t i = (uint32_t)tid * PT + q;
         if (i < n) {
-          const uint16_t s = sidv[cur][i];
+          const uint16_t s0 = sidv[cur][i];
+          const uint16_t s = s0 == kFrozen ? kFrozen : remap[s0];
           if (s != kFrozen) {
             const Act& A = act[ca][s];
             const bool f = xs[A.dim][pos[cur][i]] < A.split;
@@ -891,24 +890,25 @@ k_finish(const Fin* fin, uint32_t nfin, const float* soa0, const float* soa1, ui
       }
       if (tid == 0) L[n] = (uint16_t)tot;
       __syncthreads();
-      for (uint32_t a = tid; a < nact; a += NT) {
-        Act& A = act[ca][a];
-        A.nleft = (uint16_t)(L[A.begin + A.count] - L[A.begin]);
-      }
-      __syncthreads();
       // ---- stable scatter into the other position buffer ----
+      if (tid == 0) {
+        s_nact = 0;
+        s_nemit = 0;
+      }
       for (uint32_t i = tid; i < n; i += NT) {
-        const uint16_t s = sidv[cur][i];
+        const uint16_t s0 = sidv[cur][i];
+        const uint16_t s = s0 == kFrozen ? kFrozen : remap[s0];
         const uint16_t p = pos[cur][i];
         if (s == kFrozen) {
           pos[cur ^ 1][i] = p;
           sidv[cur ^ 1][i] = kFrozen;
         } else {
           const Act& A = act[ca][s];
+          const uint32_t nl = (uint32_t)L[A.begin + A.count] - (uint32_t)L[A.begin];
           const uint32_t lr = (uint32_t)L[i] - (uint32_t)L[A.begin];
           const bool f = L[i + 1] != L[i];
           const uint32_t np =
-              f ? A.begin + lr : A.begin + A.nleft + (i - A.begin - lr);
+              f ? A.begin + lr : A.begin + nl + (i - A.begin - lr);
           pos[cur ^ 1][np] = p;
           sidv[cur ^ 1][np] = (uint16_t)(2u * s + (f ? 0u : 1u));
         }
