@@ -252,24 +252,25 @@ __global__ void k_reset_counters(BuildCounters* c, JobTable jt, Job* jobs_dev) {
   }
 }
 
+// Tight box of every job's points.  A bounded number of workgroups per job
+// stride over its tiles and combine their bounds in registers, so that each
+// workgroup adds only one pair of device atomics per dimension.
 __global__ void __launch_bounds__(kPassThreads)
 k_root_box(const float* soa, uint64_t cap, int d, const Job* jobs, BuildCounters* c) {
   __shared__ uint32_t red[8];
   const Job J = jobs[blockIdx.y];
-  const uint64_t t0 = (uint64_t)blockIdx.x * kTile;
-  if (t0 >= J.count) return;
+  // the workgroup's first element lies beyond the job: nothing to add
+  if ((uint64_t)blockIdx.x * kPassThreads >= J.count) return;
   const int lane = __lane_id();
   const int w = threadIdx.x >> 6;
   for (int j = 0; j < d; ++j) {
     uint32_t mn = 0xFFFFFFFFu, mx = 0u;
     const float* x = soa + (uint64_t)j * cap + J.base;
-    for (int r = 0; r < kItems; ++r) {
-      uint64_t i = t0 + (uint64_t)r * kPassThreads + threadIdx.x;
-      if (i < J.count) {
-        uint32_t o = f2o(x[i]);
-        mn = o < mn ? o : mn;
-        mx = o > mx ? o : mx;
-      }
+    for (uint64_t i = (uint64_t)blockIdx.x * kPassThreads + threadIdx.x; i < J.count;
+         i += (uint64_t)gridDim.x * kPassThreads) {
+      const uint32_t o = f2o(x[i]);
+      mn = o < mn ? o : mn;
+      mx = o > mx ? o : mx;
     }
     wave_minmax(mn, mx);
     if (lane == 0) {
@@ -289,37 +290,56 @@ k_root_box(const float* soa, uint64_t cap, int d, const Job* jobs, BuildCounters
   }
 }
 
+// Root of every job: one lane per job (kMaxJobs is one wavefront); jobs above
+// the finisher threshold start the global passes, the others go straight to
+// the finisher.  List order is job order.
 __global__ void k_init_lists(const Job* jobs, int njobs, BuildCounters* c, Seg* cur, Fin* fin,
                              uint32_t T, uint64_t max_seg, uint64_t max_fin) {
-  if (threadIdx.x != 0) return;
-  for (int jb = 0; jb < njobs; ++jb) {
-    const Job J = jobs[jb];
-    if (J.count == 0) continue;
-    if (J.count > T) {
-      uint32_t k = c->nseg[0]++;
-      if (k >= max_seg) { c->err |= 1u; return; }
-      Seg& g = cur[k];
-      g.begin = J.base;
-      g.count = J.count;
-      g.job = (uint32_t)jb;
-      g.depth = 0;
-      g.path = 0;
-      g.parent_emit = kNone;
-      g.side = 0;
-      for (int j = 0; j < 2 * kMaxDim; ++j) g.box[j] = c->job_box[jb][j];
-    } else {
-      uint32_t f = c->nfin++;
-      if (f >= max_fin) { c->err |= 2u; return; }
-      Fin& F = fin[f];
-      F.begin = J.base;
-      F.count = J.count;
-      F.job = (uint32_t)jb;
-      F.depth = 0;
-      F.path = 0;
-      F.parent_emit = kNone;
-      F.side = 0;
-      F.bufsel = 0;
+  static_assert(kMaxJobs == 64, "one lane per job");
+  const int jb = threadIdx.x;
+  uint32_t cnt = 0, base = 0;
+  if (jb < njobs) {
+    cnt = jobs[jb].count;
+    base = jobs[jb].base;
+  }
+  const bool is_seg = cnt > T;
+  const bool is_fin = cnt > 0 && cnt <= T;
+  const uint64_t below = lanemask_lt();
+  const uint64_t ms = __ballot(is_seg), mf = __ballot(is_fin);
+  if (jb == 0) {
+    c->nseg[0] = (uint32_t)__popcll(ms);
+    c->nfin = (uint32_t)__popcll(mf);
+  }
+  if (is_seg) {
+    const uint32_t k = (uint32_t)__popcll(ms & below);
+    if (k >= max_seg) {
+      atomicOr(&c->err, 1u);
+      return;
     }
+    Seg& g = cur[k];
+    g.begin = base;
+    g.count = cnt;
+    g.job = (uint32_t)jb;
+    g.depth = 0;
+    g.path = 0;
+    g.parent_emit = kNone;
+    g.side = 0;
+    for (int j = 0; j < 2 * kMaxDim; ++j) g.box[j] = c->job_box[jb][j];
+  } else if (is_fin) {
+    const uint32_t f = (uint32_t)__popcll(mf & below);
+    if (f >= max_fin) {
+      atomicOr(&c->err, 2u);
+      return;
+    }
+    Fin& F = fin[f];
+    F.begin = base;
+    F.count = cnt;
+    F.job = (uint32_t)jb;
+    F.depth = 0;
+    F.path = 0;
+    F.parent_emit = kNone;
+    F.side = 0;
+    F.bufsel = 0;
   }
 }
 
@@ -980,31 +1000,45 @@ __global__ void k_layout_rank(const uint32_t* vals, uint32_t n, const uint32_t* 
   }
 }
 
-__global__ void k_layout_write(const uint32_t* emit, int es, uint32_t n, const uint32_t* final_of,
-                               const Job* jobs, int d, uint32_t* err) {
+// Write every node at its place in the vEB order.  Nodes are visited in that
+// order (order[r] is the emitted node of rank r), so the rows a wavefront
+// writes are adjacent.  An internal node's child links are written by its
+// children; the node itself leaves those two words alone.
+__global__ void k_layout_write(const uint32_t* emit, int es, uint32_t n, const uint32_t* order,
+                               const uint32_t* final_of, const Job* jobs, int d, uint32_t* err) {
   const int NS = node_stride(d);
-  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    const uint32_t e = order[q];
     const uint32_t* r = emit + (uint64_t)e * es;
     const Job& J = jobs[r[EF_JOB]];
     const uint32_t f = final_of[e];
     const uint32_t parent = r[EF_PARENT];
-    if (f >= J.node_cap || (parent != kNone && final_of[parent] >= J.node_cap)) {
+    const uint32_t fp = parent == kNone ? 0u : final_of[parent];
+    if (f >= J.node_cap || (parent != kNone && fp >= J.node_cap)) {
       atomicOr(err, 512u);
       continue;
     }
     float* nd = J.nodes + (uint64_t)f * NS;
     const int dim = (int)r[EF_DIM];
-    nd[NF_SPLIT] = __uint_as_float(r[EF_SPLIT]);
-    nd[NF_DIM] = __int_as_float(dim);
-    if (dim < 0) {
-      nd[NF_A] = __uint_as_float(r[EF_BEGIN]);
-      nd[NF_B] = __uint_as_float(r[EF_COUNT]);
+    *reinterpret_cast<float2*>(nd + NF_SPLIT) =
+        make_float2(__uint_as_float(r[EF_SPLIT]), __int_as_float(dim));
+    if (dim < 0)
+      *reinterpret_cast<float2*>(nd + NF_A) =
+          make_float2(__uint_as_float(r[EF_BEGIN]), __uint_as_float(r[EF_COUNT]));
+    // words NF_PARENT.. (parent, box, zero padding) in 16-byte stores
+    const int nbox = 2 * d;
+    for (int q4 = NF_PARENT; q4 < NS; q4 += 4) {
+      float v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = q4 + u;
+        v[u] = j == NF_PARENT ? __int_as_float(parent == kNone ? -1 : (int)fp)
+             : (j - NF_BOX < nbox ? __uint_as_float(r[EF_BOX + (j - NF_BOX)]) : 0.0f);
+      }
+      *reinterpret_cast<float4*>(nd + q4) = make_float4(v[0], v[1], v[2], v[3]);
     }
-    nd[NF_PARENT] = __int_as_float(parent == kNone ? -1 : (int)final_of[parent]);
-    for (int j = 0; j < 2 * d; ++j) nd[NF_BOX + j] = __uint_as_float(r[EF_BOX + j]);
-    for (int j = NF_BOX + 2 * d; j < NS; ++j) nd[j] = 0.0f;
     if (parent != kNone) {
-      float* pn = J.nodes + (uint64_t)final_of[parent] * NS;
+      float* pn = J.nodes + (uint64_t)fp * NS;
       pn[r[EF_SIDE] ? NF_B : NF_A] = __uint_as_float(f);
     }
   }
@@ -1173,7 +1207,7 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
   pt.begin(BDL_PH_PASSES);
   hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(kMaxJobs), 0, s, sc.ctr, jt, sc.jobs);
   {
-    dim3 g((unsigned)((maxcount + kTile - 1) / kTile), (unsigned)njobs);
+    dim3 g(grid_for(maxcount, kTile, 256), (unsigned)njobs);
     hipLaunchKernelGGL(k_root_box, g, dim3(kPassThreads), 0, s, sc.soa[0], sc.cap, d, sc.jobs,
                        sc.ctr);
   }
@@ -1259,8 +1293,8 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
   }
   hipLaunchKernelGGL(k_layout_rank, dim3(g), dim3(256), 0, s, sc.vals[which], nemit, sc.emit, es,
                      sc.ctr, sc.final_of);
-  hipLaunchKernelGGL(k_layout_write, dim3(g), dim3(256), 0, s, sc.emit, es, nemit, sc.final_of,
-                     sc.jobs, d, &sc.ctr->err);
+  hipLaunchKernelGGL(k_layout_write, dim3(g), dim3(256), 0, s, sc.emit, es, nemit,
+                     sc.vals[which], sc.final_of, sc.jobs, d, &sc.ctr->err);
   pt.end(BDL_PH_LAYOUT);
   if (hipGetLastError() != hipSuccess) return hip_fail(err, "build kernel launch failed");
   if (hipMemcpyAsync(sc.host_ctr, sc.ctr, sizeof(BuildCounters), hipMemcpyDeviceToHost, s) !=

@@ -54,41 +54,38 @@ __global__ void k_query_box_init(uint32_t* box) {
   }
 }
 
+// Tight box of a query batch.  The queries are read as one flat array of
+// nq * d floats; every thread strides over it by a multiple of d, so it only
+// ever sees one coordinate and keeps one pair of bounds.  Bounds are merged
+// per coordinate in LDS, then with one pair of device atomics per workgroup.
 __global__ void __launch_bounds__(256)
 k_query_box(const float* q, const uint64_t* nq_dev, uint64_t nq_host, int d, uint32_t* box) {
-  __shared__ uint32_t red[8];
+  __shared__ uint32_t smn[kMaxDim], smx[kMaxDim];
   const uint64_t nq = nq_dev ? *nq_dev : nq_host;
-  const int lane = __lane_id();
-  const int w = threadIdx.x >> 6;
-  for (int j = 0; j < d; ++j) {
-    uint32_t mn = 0xFFFFFFFFu, mx = 0u;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-      uint32_t o = f2o(q[i * d + j]);
+  const uint64_t total = nq * (uint64_t)d;
+  const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t stride = nthreads - nthreads % (uint64_t)d;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (threadIdx.x < kMaxDim) {
+    smn[threadIdx.x] = 0xFFFFFFFFu;
+    smx[threadIdx.x] = 0u;
+  }
+  __syncthreads();
+  uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+  if (t < stride) {
+    for (uint64_t i = t; i < total; i += stride) {
+      const uint32_t o = f2o(q[i]);
       mn = o < mn ? o : mn;
       mx = o > mx ? o : mx;
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      uint32_t a = __shfl_xor(mn, o, 64);
-      uint32_t b = __shfl_xor(mx, o, 64);
-      mn = a < mn ? a : mn;
-      mx = b > mx ? b : mx;
-    }
-    if (lane == 0) {
-      red[w] = mn;
-      red[4 + w] = mx;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int v = 1; v < 4; ++v) {
-        mn = red[v] < mn ? red[v] : mn;
-        mx = red[4 + v] > mx ? red[4 + v] : mx;
-      }
-      atomicMin(&box[j], mn);
-      atomicMax(&box[kMaxDim + j], mx);
-    }
-    __syncthreads();
+  }
+  const int j = (int)(t % (uint64_t)d);
+  atomicMin(&smn[j], mn);
+  atomicMax(&smx[j], mx);
+  __syncthreads();
+  if ((int)threadIdx.x < d) {
+    atomicMin(&box[threadIdx.x], smn[threadIdx.x]);
+    atomicMax(&box[kMaxDim + threadIdx.x], smx[threadIdx.x]);
   }
 }
 
@@ -182,8 +179,8 @@ size_t query_scratch_bytes(uint64_t cap) {
 const uint32_t* spatial_order(int d, const float* q, const uint64_t* nq_dev, uint64_t nq_host,
                              uint64_t cap, QueryScratch& qs, hipStream_t s) {
   hipLaunchKernelGGL(k_query_box_init, dim3(1), dim3(64), 0, s, qs.box);
-  unsigned g = (unsigned)((cap + 255) / 256);
-  if (g > 1024) g = 1024;
+  unsigned g = (unsigned)((cap * (uint64_t)d + 4095) / 4096);
+  if (g > 512) g = 512;
   hipLaunchKernelGGL(k_query_box, dim3(g), dim3(256), 0, s, q, nq_dev, nq_host, d, qs.box);
   unsigned g2 = (unsigned)((cap + 255) / 256);
   if (g2 > 4096) g2 = 4096;

@@ -77,6 +77,24 @@ k_scan_apply(const uint32_t* in, uint32_t* out, uint64_t n, const uint32_t* __re
   }
 }
 
+// Lanes of the wavefront whose digit equals this lane's, found with one
+// ballot per digit bit; only meaningful for valid lanes.
+__device__ inline uint64_t digit_peers(uint32_t dig, bool valid, int bits) {
+  uint64_t m = __ballot(valid);
+  for (int b = 0; b < bits; ++b) {
+    const bool bit = (dig >> b) & 1u;
+    const uint64_t bb = __ballot(valid && bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
+__device__ inline uint64_t lanes_below() {
+  const int lane = __lane_id();
+  return lane == 0 ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+// Digit counts of one tile; one LDS add per distinct digit of a wavefront.
 template <typename K>
 __global__ void __launch_bounds__(kRadixThreads)
 k_radix_hist(const K* __restrict__ keys, uint64_t n, int shift, int bits,
@@ -85,70 +103,104 @@ k_radix_hist(const K* __restrict__ keys, uint64_t n, int shift, int bits,
   h[threadIdx.x] = 0;
   __syncthreads();
   const uint32_t mask = (1u << bits) - 1u;
+  const uint64_t below = lanes_below();
   const uint64_t base = (uint64_t)blockIdx.x * kRadixTile;
 #pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
-    uint64_t i = base + (uint64_t)r * kRadixThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & mask], 1u);
+    const uint64_t i = base + (uint64_t)r * kRadixThreads + threadIdx.x;
+    const bool valid = i < n;
+    const uint32_t dig = valid ? (uint32_t)(keys[i] >> shift) & mask : 0u;
+    const uint64_t m = digit_peers(dig, valid, bits);
+    if (valid && (m & below) == 0) atomicAdd(&h[dig], (uint32_t)__popcll(m));
   }
   __syncthreads();
   hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter: element order inside the tile is preserved among equal
-// digits.  Ranks come from wave ballots (peer masks per digit) combined
-// across the four waves and across rounds through LDS counters.
+// Stable scatter of one tile.  Each wavefront ranks a contiguous quarter of
+// the tile against its own digit counters (no workgroup barrier between
+// rounds); the counters then give every element its place in the tile
+// sorted by digit, the tile is reordered in LDS, and written out so that
+// consecutive threads store consecutive positions of one digit's run.
 template <typename K>
 __global__ void __launch_bounds__(kRadixThreads)
 k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                 K* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n, int shift,
                 int bits, const uint32_t* __restrict__ hscan, uint32_t nb) {
-  __shared__ uint32_t offs[256];
-  __shared__ uint32_t running[256];
-  __shared__ uint32_t wcnt[4][256];
+  constexpr int kWaves = kRadixThreads / 64;
+  constexpr int kRounds = kRadixTile / kRadixThreads;  // rounds of 64 per wavefront
+  static_assert(kRadixThreads == 256, "one thread per digit");
+  __shared__ uint32_t wcnt[kWaves][256];
+  __shared__ uint32_t dstart[256];
+  __shared__ uint32_t gofs[256];
+  __shared__ uint32_t wsum[17];
+  __shared__ K skey[kRadixTile];
+  __shared__ uint32_t sval[kRadixTile];
   const int tid = threadIdx.x;
   const int lane = __lane_id();
   const int w = tid >> 6;
   const uint32_t mask = (1u << bits) - 1u;
-  offs[tid] = hscan[(uint64_t)tid * nb + blockIdx.x];
-  running[tid] = 0;
-  for (int i = 0; i < 4; ++i) wcnt[i][tid] = 0;
+  const uint64_t below = lanes_below();
+#pragma unroll
+  for (int v = 0; v < kWaves; ++v) wcnt[v][tid] = 0;
+  gofs[tid] = hscan[(uint64_t)tid * nb + blockIdx.x];
   __syncthreads();
-  const uint64_t base = (uint64_t)blockIdx.x * kRadixTile;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-  for (int r = 0; r < kRadixItems; ++r) {
-    uint64_t i = base + (uint64_t)r * kRadixThreads + tid;
-    bool valid = i < n;
-    K key = 0;
-    uint32_t val = 0, dig = 0;
-    if (valid) {
-      key = kin[i];
-      val = vin[i];
-      dig = (uint32_t)(key >> shift) & mask;
+  const uint64_t tbase = (uint64_t)blockIdx.x * kRadixTile;
+  const uint64_t wbase = tbase + (uint64_t)w * (kRounds * 64);
+  K key[kRounds];
+  uint32_t val[kRounds];
+  uint32_t rank[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const uint64_t i = wbase + (uint64_t)r * 64 + lane;
+    key[r] = i < n ? kin[i] : (K)0;
+    val[r] = i < n ? vin[i] : 0u;
+  }
+  // rank among the equal digits of this wavefront's earlier elements; the
+  // counters are private to the wavefront, whose LDS accesses stay in order
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const bool valid = wbase + (uint64_t)r * 64 + lane < n;
+    const uint32_t dig = (uint32_t)(key[r] >> shift) & mask;
+    const uint64_t m = digit_peers(dig, valid, bits);
+    const uint32_t lower = (uint32_t)__popcll(m & below);
+    const uint32_t seen = valid ? wcnt[w][dig] : 0u;
+    rank[r] = seen + lower;
+    if (valid && lower == 0) wcnt[w][dig] = seen + (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  // thread tid owns digit tid: wavefront prefixes, then the tile's digit starts
+  uint32_t tot = 0;
+#pragma unroll
+  for (int v = 0; v < kWaves; ++v) {
+    const uint32_t c = wcnt[v][tid];
+    wcnt[v][tid] = tot;
+    tot += c;
+  }
+  dstart[tid] = block_excl_scan(tot, wsum, nullptr);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    if (wbase + (uint64_t)r * 64 + lane < n) {
+      const uint32_t dig = (uint32_t)(key[r] >> shift) & mask;
+      const uint32_t lp = dstart[dig] + wcnt[w][dig] + rank[r];
+      skey[lp] = key[r];
+      sval[lp] = val[r];
     }
-    uint64_t m = __ballot(valid);
-    for (int b = 0; b < bits; ++b) {
-      bool bit = (dig >> b) & 1u;
-      uint64_t bb = __ballot(valid && bit);
-      m &= bit ? bb : ~bb;
+  }
+  __syncthreads();
+  const uint64_t left = n - tbase;
+  const uint32_t tcount = left < (uint64_t)kRadixTile ? (uint32_t)left : (uint32_t)kRadixTile;
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t li = (uint32_t)(r * kRadixThreads + tid);
+    if (li < tcount) {
+      const K k = skey[li];
+      const uint32_t dig = (uint32_t)(k >> shift) & mask;
+      const uint64_t dst = (uint64_t)gofs[dig] + (li - dstart[dig]);
+      kout[dst] = k;
+      vout[dst] = sval[li];
     }
-    uint32_t wrank = (uint32_t)__popcll(m & lt_mask);
-    if (valid && wrank == 0) wcnt[w][dig] = (uint32_t)__popcll(m);
-    __syncthreads();
-    if (valid) {
-      uint32_t pre = running[dig];
-      for (int v = 0; v < w; ++v) pre += wcnt[v][dig];
-      uint32_t dst = offs[dig] + pre + wrank;
-      kout[dst] = key;
-      vout[dst] = val;
-    }
-    __syncthreads();
-    running[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
-    wcnt[0][tid] = 0;
-    wcnt[1][tid] = 0;
-    wcnt[2][tid] = 0;
-    wcnt[3][tid] = 0;
-    __syncthreads();
   }
 }
 
