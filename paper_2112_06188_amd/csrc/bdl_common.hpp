@@ -146,7 +146,8 @@ struct BuildCounters {
   uint32_t nfin;
   uint32_t nemit;
   uint32_t err;
-  uint32_t pad_[2];
+  uint32_t fin_next;   // next finisher entry to take
+  uint32_t retry;      // the finisher found segments left above the threshold
   uint32_t job_nodes[kMaxJobs];
   uint32_t job_height[kMaxJobs];
   uint32_t job_node_off[kMaxJobs];

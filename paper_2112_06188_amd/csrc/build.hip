@@ -239,6 +239,7 @@ __global__ void k_reset_counters(BuildCounters* c, JobTable jt, Job* jobs_dev) {
   if (t == 0) {
     c->nseg[0] = c->nseg[1] = 0;
     c->ntiles = c->nfin = c->nemit = c->err = 0;
+    c->fin_next = c->retry = 0;
   }
   if (t < kMaxJobs) {
     c->job_nodes[t] = 0;
@@ -255,6 +256,10 @@ __global__ void k_reset_counters(BuildCounters* c, JobTable jt, Job* jobs_dev) {
 // Tight box of every job's points.  A bounded number of workgroups per job
 // stride over its tiles and combine their bounds in registers, so that each
 // workgroup adds only one pair of device atomics per dimension.
+__global__ void k_clear_retry(BuildCounters* c) {
+  if (threadIdx.x == 0) c->retry = 0u;
+}
+
 __global__ void __launch_bounds__(kPassThreads)
 k_root_box(const float* soa, uint64_t cap, int d, const Job* jobs, BuildCounters* c) {
   __shared__ uint32_t red[8];
@@ -359,6 +364,13 @@ k_setup(Seg* cur, uint32_t* segtb, uint32_t* tile_seg, BuildCounters* c, int par
   __shared__ uint32_t wsum[17];
   __shared__ uint32_t s_base, s_n;
   __shared__ uint32_t s_tb[kSetupLds];
+  // per-job node counts and heights of this depth, added to the device
+  // counters once per job instead of once per segment
+  __shared__ uint32_t s_jn[kMaxJobs], s_jh[kMaxJobs];
+  if (threadIdx.x < kMaxJobs) {
+    s_jn[threadIdx.x] = 0;
+    s_jh[threadIdx.x] = 0;
+  }
   if (threadIdx.x == 0) {
     uint32_t nn = c->nseg[par];
     if (nn > max_seg || c->err) {
@@ -399,8 +411,8 @@ k_setup(Seg* cur, uint32_t* segtb, uint32_t* tile_seg, BuildCounters* c, int par
       const Job& J = jobs[g.job];
       write_emit(emit, es, eidx, g.path, g.depth, g.job, g.parent_emit, g.side,
                  g.begin - J.base, g.count, split, dim, lo, hi, d);
-      atomicAdd(&c->job_nodes[g.job], 1u);
-      atomicMax(&c->job_height[g.job], g.depth + 1);
+      atomicAdd(&s_jn[g.job], 1u);
+      atomicMax(&s_jh[g.job], g.depth + 1);
       g.emit = eidx;
       g.dim = dim;
       g.split = split;
@@ -415,6 +427,11 @@ k_setup(Seg* cur, uint32_t* segtb, uint32_t* tile_seg, BuildCounters* c, int par
       if (s < kSetupLds) s_tb[s] = carry + ex;
     }
     carry += tot;
+  }
+  __syncthreads();
+  if (threadIdx.x < kMaxJobs && s_jn[threadIdx.x]) {
+    atomicAdd(&c->job_nodes[threadIdx.x], s_jn[threadIdx.x]);
+    atomicMax(&c->job_height[threadIdx.x], s_jh[threadIdx.x]);
   }
   const bool over = carry > max_tiles;
   if (threadIdx.x == 0) {
@@ -478,8 +495,15 @@ __global__ void __launch_bounds__(1024)
 k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_left,
            uint32_t* tile_off, Fin* fin, uint32_t T, uint64_t max_seg, uint64_t max_fin) {
   __shared__ uint32_t wsum[17];
+  // list sizes are counted in LDS (this is the only workgroup) and stored once
+  __shared__ uint32_t s_nseg, s_nfin;
   const uint32_t nt = c->ntiles;
   const uint32_t ns = c->nseg[par];
+  if (threadIdx.x == 0) {
+    s_nseg = c->nseg[par ^ 1];
+    s_nfin = c->nfin;
+  }
+  __syncthreads();
   uint32_t carry = 0;
   for (uint32_t ch = 0; ch < nt; ch += blockDim.x) {
     uint32_t t = ch + threadIdx.x;
@@ -506,7 +530,7 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
       const uint32_t cc = side ? g.count - nl : nl;
       const uint64_t cpath = (g.path << 1) | (uint64_t)side;
       if (cc > T) {
-        uint32_t k = atomicAdd(&c->nseg[par ^ 1], 1u);
+        uint32_t k = atomicAdd(&s_nseg, 1u);
         if (k >= max_seg) {
           atomicOr(&c->err, 8u);
           g.child[side] = kNone;
@@ -526,7 +550,7 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
         }
         g.child[side] = k;
       } else {
-        uint32_t f = atomicAdd(&c->nfin, 1u);
+        uint32_t f = atomicAdd(&s_nfin, 1u);
         g.child[side] = kNone;
         if (f >= max_fin) {
           atomicOr(&c->err, 16u);
@@ -543,6 +567,11 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
         F.bufsel = (uint32_t)(par ^ 1);
       }
     }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    c->nseg[par ^ 1] = s_nseg;
+    c->nfin = s_nfin;
   }
 }
 
@@ -711,7 +740,7 @@ struct Act {
 
 template <int DMAX, int TCAP, int MAXACT, int NT>
 __global__ void __launch_bounds__(NT)
-k_finish(const Fin* fin, uint32_t nfin, const float* soa0, const float* soa1, uint64_t cap,
+k_finish(const Fin* fin, int par_end, const float* soa0, const float* soa1, uint64_t cap,
          int d, uint32_t leaf, const Job* jobs, uint32_t* emit, int es, BuildCounters* c,
          uint64_t* map, uint32_t idcap, uint64_t max_emit) {
   constexpr int PT = (TCAP + NT - 1) / NT;
@@ -726,13 +755,34 @@ k_finish(const Fin* fin, uint32_t nfin, const float* soa0, const float* soa1, ui
   __shared__ uint32_t cbox[MAXCH][2 * DMAX];
   __shared__ uint16_t remap[MAXCH];
   __shared__ uint32_t wsum[17];
-  __shared__ uint32_t s_nact, s_nemit, s_base, s_maxdepth;
+  __shared__ uint32_t s_nact, s_nemit, s_base, s_maxdepth, s_fi;
 
   const int tid = threadIdx.x;
   const int lane = __lane_id();
   const int S = rec_stride(d);
 
-  for (uint32_t fi = blockIdx.x; fi < nfin; fi += gridDim.x) {
+  // The launch follows the global passes without a readback in between:
+  // if a segment is still above the threshold (or an error was flagged) the
+  // lists are incomplete, so nothing is done and the host is asked for more
+  // passes and a new launch.
+  __shared__ uint32_t s_go;
+  if (tid == 0) {
+    const uint32_t e = c->err;
+    const bool stop = e != 0u || c->nseg[par_end] != 0u;
+    if (stop && e == 0u && blockIdx.x == 0) c->retry = 1u;
+    s_go = stop ? 0u : 1u;
+  }
+  __syncthreads();
+  if (!s_go) return;
+  const uint32_t nfin = c->nfin;
+  // entries are taken from a counter, so that the grid can be one
+  // resident wave of workgroups whatever the list size
+  while (true) {
+    if (tid == 0) s_fi = atomicAdd(&c->fin_next, 1u);
+    __syncthreads();
+    const uint32_t fi = s_fi;
+    __syncthreads();
+    if (fi >= nfin) break;
     const Fin F = fin[fi];
     const uint32_t n = F.count;
     if (n > TCAP || n == 0) {
@@ -1096,12 +1146,24 @@ void launch_scatter(int d, unsigned grid, const BuildScratch& sc, int par, uint6
 }
 
 template <int DMAX, int TCAP, int MAXACT, int NT>
-void launch_finish(uint32_t nfin, const BuildScratch& sc, int d, uint32_t leaf, uint64_t* map,
+void launch_finish(int par_end, const BuildScratch& sc, int d, uint32_t leaf, uint64_t* map,
                    uint32_t idcap, hipStream_t s) {
-  unsigned g = nfin < 65535u ? nfin : 65535u;
-  hipLaunchKernelGGL((k_finish<DMAX, TCAP, MAXACT, NT>), dim3(g), dim3(NT), 0, s, sc.fin, nfin,
-                     sc.soa[0], sc.soa[1], sc.cap, d, leaf, sc.jobs, sc.emit, emit_stride(d),
-                     sc.ctr, map, idcap, sc.max_emit);
+  // one resident wave of workgroups (computed once; every device here is
+  // the same kind)
+  static const unsigned g = [] {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per, reinterpret_cast<const void*>(&k_finish<DMAX, TCAP, MAXACT, NT>), NT, 0) !=
+            hipSuccess ||
+        cus <= 0 || per <= 0)
+      return 512u;
+    return (unsigned)(cus * per);
+  }();
+  hipLaunchKernelGGL((k_finish<DMAX, TCAP, MAXACT, NT>), dim3(g), dim3(NT), 0, s, sc.fin,
+                     par_end, sc.soa[0], sc.soa[1], sc.cap, d, leaf, sc.jobs, sc.emit,
+                     emit_stride(d), sc.ctr, map, idcap, sc.max_emit);
 }
 
 }  // namespace
@@ -1213,13 +1275,13 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
   }
   hipLaunchKernelGGL(k_init_lists, dim3(1), dim3(64), 0, s, sc.jobs, njobs, sc.ctr, sc.seg[0],
                      sc.fin, T, sc.max_seg, sc.max_fin);
-  // global passes: a budget of depths, then one readback to see whether any
-  // segment still exceeds the finisher threshold
+  // global passes: a budget of depths, then the finisher, which does nothing
+  // and asks for more depths if a segment is still above the threshold
   int depth = 0;
   int budget = 1;
   while (((uint64_t)T << budget) < maxcount && budget < 40) ++budget;
   // spatial-median splits of real data are not exactly balanced: allow a
-  // few depths beyond log2(n / T) before the first readback
+  // few depths beyond log2(n / T) before the first check
   budget += 2;
   const unsigned pass_grid = grid_for(R, kTile, 2048);
   while (true) {
@@ -1236,39 +1298,32 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
       launch_scatter(d, pass_grid, sc, par, map, idcap, s);
     }
     pt.end(BDL_PH_PASSES);
+    pt.begin(BDL_PH_FINISH);
+    const int par_end = depth & 1;
+    if (d <= 3) launch_finish<3, 2304, 144, 768>(par_end, sc, d, leaf, map, idcap, s);
+    else if (d <= 8) launch_finish<8, 1024, 64, 256>(par_end, sc, d, leaf, map, idcap, s);
+    else launch_finish<16, 512, 32, 256>(par_end, sc, d, leaf, map, idcap, s);
+    pt.end(BDL_PH_FINISH);
     if (hipMemcpyAsync(sc.host_ctr, sc.ctr, sizeof(BuildCounters), hipMemcpyDeviceToHost, s) !=
         hipSuccess)
       return hip_fail(err, "counter readback failed");
     if (hipStreamSynchronize(s) != hipSuccess) return hip_fail(err, "build passes failed");
-    if (sc.host_ctr->err) {
-      *err = "build scratch overflow in the global passes";
+    const uint32_t e = sc.host_ctr->err;
+    if (e) {
+      *err = (e & (32u | 64u | 128u)) ? "build scratch overflow in the finisher"
+                                       : "build scratch overflow in the global passes";
       return BDL_EHIP;
     }
-    if (sc.host_ctr->nseg[depth & 1] == 0) break;
+    if (!sc.host_ctr->retry) break;
     if (depth > kMaxDepth + 2) {
       *err = "build did not terminate";
       return BDL_EHIP;
     }
-    budget = 8;
+    hipLaunchKernelGGL(k_clear_retry, dim3(1), dim3(64), 0, s, sc.ctr);
+    budget = 4;
     pt.begin(BDL_PH_PASSES);
   }
-  const uint32_t nfin = sc.host_ctr->nfin;
-  pt.begin(BDL_PH_FINISH);
-  if (nfin) {
-    if (d <= 3) launch_finish<3, 2304, 144, 768>(nfin, sc, d, leaf, map, idcap, s);
-    else if (d <= 8) launch_finish<8, 1024, 64, 256>(nfin, sc, d, leaf, map, idcap, s);
-    else launch_finish<16, 512, 32, 256>(nfin, sc, d, leaf, map, idcap, s);
-  }
-  pt.end(BDL_PH_FINISH);
-  if (hipMemcpyAsync(sc.host_ctr, sc.ctr, sizeof(BuildCounters), hipMemcpyDeviceToHost, s) !=
-      hipSuccess)
-    return hip_fail(err, "counter readback failed");
-  if (hipStreamSynchronize(s) != hipSuccess) return hip_fail(err, "finisher failed");
   const BuildCounters& hc = *sc.host_ctr;
-  if (hc.err) {
-    *err = "build scratch overflow in the finisher";
-    return BDL_EHIP;
-  }
   const uint32_t nemit = hc.nemit;
   int maxH = 0;
   for (int j = 0; j < njobs; ++j) {
