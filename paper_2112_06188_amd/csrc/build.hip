@@ -1282,7 +1282,7 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
   while (((uint64_t)T << budget) < maxcount && budget < 40) ++budget;
   // spatial-median splits of real data are not exactly balanced: allow a
   // few depths beyond log2(n / T) before the first check
-  budget += 2;
+  budget += 1;
   const unsigned pass_grid = grid_for(R, kTile, 2048);
   while (true) {
     for (int b = 0; b < budget; ++b, ++depth) {
