@@ -457,34 +457,37 @@ k_setup(Seg* cur, uint32_t* segtb, uint32_t* tile_seg, BuildCounters* c, int par
   }
 }
 
+// Left count of every tile: one wavefront per tile (ballots, no barriers),
+// so that all of a tile's loads are in flight at once.
 __global__ void __launch_bounds__(kPassThreads)
 k_count(const Seg* cur, const uint32_t* tile_seg, const BuildCounters* c,
         const float* src, uint64_t cap, uint32_t* tile_left) {
-  __shared__ uint32_t red[4];
+  constexpr int kWaves = kPassThreads / 64;
   const uint32_t nt = c->ntiles;
-  for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
+  const int lane = __lane_id();
+  const uint32_t nw = gridDim.x * kWaves;
+  for (uint32_t t = blockIdx.x * kWaves + (threadIdx.x >> 6); t < nt; t += nw) {
     const uint32_t s = tile_seg[t];
     const Seg& g = cur[s];
     const int dim = g.dim;
     if (dim < 0) {
-      if (threadIdx.x == 0) tile_left[t] = 0;
+      if (lane == 0) tile_left[t] = 0;
       continue;
     }
     const float split = g.split;
     const uint64_t tstart = (uint64_t)g.begin + (uint64_t)(t - g.tile_begin) * kTile;
     const uint64_t tend = min((uint64_t)g.begin + g.count, tstart + kTile);
     const float* x = src + (uint64_t)dim * cap;
+    // loads at a clamped index (always in the tile) so that none waits on
+    // a branch and all of them can be in flight together
     uint32_t cnt = 0;
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      uint64_t i = tstart + (uint64_t)r * kPassThreads + threadIdx.x;
-      if (i < tend && x[i] < split) ++cnt;
+    for (int r = 0; r < kTile / 64; ++r) {
+      const uint64_t i = tstart + (uint64_t)r * 64 + lane;
+      const float xv = x[i < tend ? i : tend - 1];
+      cnt += (uint32_t)__popcll(__ballot((i < tend) & (xv < split)));
     }
-    cnt = wave_sum(cnt);
-    if (__lane_id() == 0) red[threadIdx.x >> 6] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) tile_left[t] = red[0] + red[1] + red[2] + red[3];
-    __syncthreads();
+    if (lane == 0) tile_left[t] = cnt;
   }
 }
 
@@ -578,23 +581,24 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
 // Stable partition of every tile into the other build buffer; accumulates
 // the tight boxes of children that stay in the global passes; leaves that
 // are too large for the finisher (coincident points) are copied out whole.
-// D is the dimension: every column is moved with the same destinations and
-// the children's boxes are kept in registers for all dimensions, so a tile
-// needs three barriers whatever D is.
+// One wavefront per tile walks its rows of 64 points in order: a ballot per
+// row gives every point its rank among the tile's left (or right) points,
+// with the running count held wave-uniform, so no LDS or barrier is needed.
+// D is the dimension: all columns of a row are read once, and the children's
+// boxes are kept in registers for all dimensions.
 template <int D>
 __global__ void __launch_bounds__(kPassThreads)
 k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounters* c,
-          const float* src, float* dst, uint64_t cap, const uint32_t* tile_off,
-          const Job* jobs, uint64_t* map, uint32_t idcap) {
-  __shared__ uint32_t lt[kItems][4];
-  __shared__ uint32_t red[4][4 * D];
+          const float* __restrict__ src, float* __restrict__ dst, uint64_t cap,
+          const uint32_t* tile_off, const Job* jobs, uint64_t* map, uint32_t idcap) {
+  constexpr int kWaves = kPassThreads / 64;
   const uint32_t nt = c->ntiles;
   const int lane = __lane_id();
-  const int w = threadIdx.x >> 6;
-  const uint64_t ltm = lanemask_lt();
+  const uint64_t below = lanemask_lt();
   const uint32_t* sid = soa_ids(src, D, cap);
   uint32_t* did = soa_ids_w(dst, D, cap);
-  for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
+  const uint32_t nw = gridDim.x * kWaves;
+  for (uint32_t t = blockIdx.x * kWaves + (threadIdx.x >> 6); t < nt; t += nw) {
     const uint32_t s = tile_seg[t];
     const Seg& g = cur[s];
     const uint64_t gbegin = g.begin;
@@ -605,15 +609,13 @@ k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounter
     if (dim < 0) {
       const Job J = jobs[g.job];
       constexpr int S = (D + 1 + 3) & ~3;
-      for (int r = 0; r < kItems; ++r) {
-        uint32_t i = r * kPassThreads + threadIdx.x;
-        if (i >= tcnt) continue;
-        uint64_t p = tstart + i;
-        uint64_t slot = p - J.base;
+      for (uint32_t i = lane; i < tcnt; i += 64) {
+        const uint64_t p = tstart + i;
+        const uint64_t slot = p - J.base;
         float* rr = J.rec + slot * S;
 #pragma unroll
         for (int j = 0; j < D; ++j) rr[j] = src[(uint64_t)j * cap + p];
-        uint32_t id = sid[p];
+        const uint32_t id = sid[p];
         rr[D] = __uint_as_float(id);
 #pragma unroll
         for (int j = D + 1; j < S; ++j) rr[j] = 0.0f;
@@ -622,106 +624,83 @@ k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounter
       continue;
     }
     const float split = g.split;
-    const float* x = src + (uint64_t)dim * cap;
-    uint64_t m[kItems];
-    uint32_t fl = 0;
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      uint32_t i = r * kPassThreads + threadIdx.x;
-      bool f = i < tcnt && x[tstart + i] < split;
-      fl |= (uint32_t)f << r;
-      m[r] = __ballot(f);
-    }
-    if (lane == 0) {
-#pragma unroll
-      for (int r = 0; r < kItems; ++r) lt[r][w] = (uint32_t)__popcll(m[r]);
-    }
-    __syncthreads();
     const uint32_t tloff = tile_off[t] - tile_off[g.tile_begin];
     const uint64_t lbase = gbegin + tloff;
     const uint64_t rbase = gbegin + g.nleft + ((tstart - gbegin) - tloff);
-    uint32_t dpos[kItems];
-    uint32_t run = 0;
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      uint32_t before = 0, row = 0;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        uint32_t xv = lt[r][v];
-        before += v < w ? xv : 0u;
-        row += xv;
-      }
-      uint32_t i = r * kPassThreads + threadIdx.x;
-      uint32_t lr = run + before + (uint32_t)__popcll(m[r] & ltm);
-      dpos[r] = ((fl >> r) & 1u) ? (uint32_t)(lbase + lr) : (uint32_t)(rbase + (i - lr));
-      run += row;
-    }
     uint32_t bx[D][4];  // left min, left max, right min, right max (ordered u32)
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      const float* sj = src + (uint64_t)j * cap;
-      float* dj = dst + (uint64_t)j * cap;
-      uint32_t lmn = 0xFFFFFFFFu, lmx = 0u, rmn = 0xFFFFFFFFu, rmx = 0u;
+      bx[j][0] = 0xFFFFFFFFu;
+      bx[j][1] = 0u;
+      bx[j][2] = 0xFFFFFFFFu;
+      bx[j][3] = 0u;
+    }
+    uint32_t lrun = 0;  // left points in earlier rows
+    // groups of kRows rows: all loads of a group are issued before its
+    // stores (indices are clamped into the tile, so no load waits on a branch)
+    constexpr int kRows = 4;
+    for (uint32_t r0 = 0; r0 * 64 < tcnt; r0 += kRows) {
+      float v[kRows][D];
+      uint32_t idv[kRows];
 #pragma unroll
-      for (int r = 0; r < kItems; ++r) {
-        uint32_t i = r * kPassThreads + threadIdx.x;
-        if (i < tcnt) {
-          float v = sj[tstart + i];
-          dj[dpos[r]] = v;
-          uint32_t o = f2o(v);
-          if ((fl >> r) & 1u) {
-            lmn = o < lmn ? o : lmn;
-            lmx = o > lmx ? o : lmx;
-          } else {
-            rmn = o < rmn ? o : rmn;
-            rmx = o > rmx ? o : rmx;
+      for (int u = 0; u < kRows; ++u) {
+        const uint32_t i = (r0 + u) * 64 + lane;
+        const uint64_t p = tstart + (i < tcnt ? i : tcnt - 1);
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[u][j] = src[(uint64_t)j * cap + p];
+        idv[u] = sid[p];
+      }
+#pragma unroll
+      for (int u = 0; u < kRows; ++u) {
+        const uint32_t i = (r0 + u) * 64 + lane;
+        const bool in = i < tcnt;
+        float vd = 0.0f;
+#pragma unroll
+        for (int j = 0; j < D; ++j) vd = j == dim ? v[u][j] : vd;
+        const bool f = in && vd < split;
+        const uint64_t m = __ballot(f);
+        const uint32_t lr = lrun + (uint32_t)__popcll(m & below);
+        lrun += (uint32_t)__popcll(m);
+        if (in) {
+          const uint64_t dp = f ? lbase + lr : rbase + (i - lr);
+#pragma unroll
+          for (int j = 0; j < D; ++j) {
+            dst[(uint64_t)j * cap + dp] = v[u][j];
+            const uint32_t o = f2o(v[u][j]);
+            const int q = f ? 0 : 2;
+            bx[j][q] = o < bx[j][q] ? o : bx[j][q];
+            bx[j][q + 1] = o > bx[j][q + 1] ? o : bx[j][q + 1];
           }
+          did[dp] = idv[u];
         }
       }
-      bx[j][0] = lmn;
-      bx[j][1] = lmx;
-      bx[j][2] = rmn;
-      bx[j][3] = rmx;
-    }
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      uint32_t i = r * kPassThreads + threadIdx.x;
-      if (i < tcnt) did[dpos[r]] = sid[tstart + i];
     }
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       wave_minmax(bx[j][0], bx[j][1]);
       wave_minmax(bx[j][2], bx[j][3]);
     }
-    if (lane == 0) {
+    // lane 4j+q adds bound q of dimension j; a side with no point in this
+    // tile keeps the neutral values (0xFFFFFFFF, 0), which no finite
+    // coordinate maps to, and is skipped
+    const uint32_t c0 = g.child[0], c1 = g.child[1];
 #pragma unroll
-      for (int j = 0; j < D; ++j)
+    for (int j = 0; j < D; ++j) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) red[w][4 * j + q] = bx[j][q];
-    }
-    __syncthreads();
-    // one thread per (dimension, bound, side): combine the four waves
-    if (threadIdx.x < 4 * D) {
-      const int j = threadIdx.x >> 2, q = threadIdx.x & 3;
-      const bool is_max = q & 1;
-      uint32_t v = red[0][threadIdx.x];
-#pragma unroll
-      for (int u = 1; u < 4; ++u) {
-        const uint32_t o = red[u][threadIdx.x];
-        v = is_max ? (o > v ? o : v) : (o < v ? o : v);
-      }
-      const uint32_t ch = q < 2 ? g.child[0] : g.child[1];
-      // a side with no point in this tile keeps the neutral values
-      // (0xFFFFFFFF, 0), which no finite coordinate maps to; skip it
-      if (ch != kNone) {
-        if (is_max) {
-          if (v != 0u) atomicMax(&nxt[ch].box[kMaxDim + j], v);
-        } else {
-          if (v != 0xFFFFFFFFu) atomicMin(&nxt[ch].box[j], v);
+      for (int q = 0; q < 4; ++q) {
+        if (lane == 4 * j + q) {
+          const uint32_t ch = q < 2 ? c0 : c1;
+          const uint32_t v = bx[j][q];
+          if (ch != kNone) {
+            if (q & 1) {
+              if (v != 0u) atomicMax(&nxt[ch].box[kMaxDim + j], v);
+            } else {
+              if (v != 0xFFFFFFFFu) atomicMin(&nxt[ch].box[j], v);
+            }
+          }
         }
       }
     }
-    __syncthreads();
   }
 }
 

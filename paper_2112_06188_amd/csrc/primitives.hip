@@ -77,6 +77,50 @@ k_scan_apply(const uint32_t* in, uint32_t* out, uint64_t n, const uint32_t* __re
   }
 }
 
+// The whole scan in one workgroup of 1024 threads, for short arrays (one
+// launch instead of three): rounds of kSingleTile elements staged in LDS.
+constexpr int kSingleThreads = 1024;
+constexpr int kSingleTile = kSingleThreads * kScanItems;
+constexpr uint64_t kSingleMax = 2 * kSingleTile;
+
+__global__ void __launch_bounds__(kSingleThreads)
+k_scan_single(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* __restrict__ total) {
+  __shared__ uint32_t tile[kSingleTile + kSingleTile / 32];
+  __shared__ uint32_t wsum[17];
+  uint32_t carry = 0;
+  for (uint64_t base = 0; base < n; base += kSingleTile) {
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+      const int li = r * kSingleThreads + threadIdx.x;
+      const uint64_t i = base + li;
+      tile[pidx(li)] = i < n ? in[i] : 0u;
+    }
+    __syncthreads();
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) s += tile[pidx(threadIdx.x * kScanItems + j)];
+    uint32_t tot;
+    uint32_t run = block_excl_scan(s, wsum, &tot) + carry;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      const int li = pidx(threadIdx.x * kScanItems + j);
+      const uint32_t v = tile[li];
+      tile[li] = run;
+      run += v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+      const int li = r * kSingleThreads + threadIdx.x;
+      const uint64_t i = base + li;
+      if (i < n) out[i] = tile[pidx(li)];
+    }
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
 // Lanes of the wavefront whose digit equals this lane's, found with one
 // ballot per digit bit; only meaningful for valid lanes.
 __device__ inline uint64_t digit_peers(uint32_t dig, bool valid, int bits) {
@@ -234,6 +278,10 @@ void scan_exclusive_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t*
                         uint32_t* tmp, hipStream_t s) {
   if (n == 0) {
     if (total) hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, 0u, total);
+    return;
+  }
+  if (n <= kSingleMax) {
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kSingleThreads), 0, s, in, out, n, total);
     return;
   }
   const uint32_t nb = (uint32_t)((n + kScanTile - 1) / kScanTile);
