@@ -734,7 +734,7 @@ k_finish(const Fin* fin, int par_end, const float* soa0, const float* soa1, uint
   __shared__ uint32_t cbox[MAXCH][2 * DMAX];
   __shared__ uint16_t remap[MAXCH];
   __shared__ uint32_t wsum[17];
-  __shared__ uint32_t s_nact, s_nemit, s_base, s_maxdepth, s_fi;
+  __shared__ uint32_t s_nact, s_base, s_maxdepth, s_fi;
 
   const int tid = threadIdx.x;
   const int lane = __lane_id();
@@ -768,6 +768,12 @@ k_finish(const Fin* fin, int par_end, const float* soa0, const float* soa1, uint
       if (tid == 0) atomicOr(&c->err, 32u);
       continue;
     }
+    // Every child of a depth is emitted, so a depth emits exactly nch nodes
+    // and its emit range can be reserved one depth ahead: thread 0 keeps the
+    // reservation in flight in a register while the depth's boxes and
+    // classification are computed.
+    uint32_t ebase_next = 0;
+    if (tid == 0) ebase_next = atomicAdd(&c->nemit, 1u);
     const float* src = F.bufsel ? soa1 : soa0;
     const uint32_t* srcid = soa_ids(src, d, cap);
     const Job J = jobs[F.job];
@@ -781,7 +787,6 @@ k_finish(const Fin* fin, int par_end, const float* soa0, const float* soa1, uint
     if (tid == 0) {
       s_maxdepth = 0;
       s_nact = 0;
-      s_nemit = 0;
     }
     int cur = 0;    // pos/sid buffer holding the current order
     int ca = 0;     // act table of the current depth
@@ -869,7 +874,7 @@ k_finish(const Fin* fin, int par_end, const float* soa0, const float* soa1, uint
         for (int j = 0; j < d; ++j) degenerate = degenerate && lo[j] == hi[j];
         const bool isleaf = ccount <= leaf || degenerate || cdepth >= (uint32_t)kMaxDepth;
         if (!isleaf) choose_split(lo, hi, d, (int)cdepth, &cdim, &csplit);
-        le = atomicAdd(&s_nemit, 1u);
+        le = ch;
         if (!isleaf) {
           ai = atomicAdd(&s_nact, 1u);
           if (ai >= (uint32_t)MAXACT) {
@@ -880,14 +885,13 @@ k_finish(const Fin* fin, int par_end, const float* soa0, const float* soa1, uint
         remap[ch] = ai == kNone ? kFrozen : (uint16_t)ai;
         atomicMax(&s_maxdepth, cdepth);
       }
-      __syncthreads();
       if (tid == 0) {
-        uint32_t base = atomicAdd(&c->nemit, s_nemit);
-        if ((uint64_t)base + s_nemit > max_emit) {
+        uint32_t base = ebase_next;
+        if ((uint64_t)base + nch > max_emit) {
           atomicOr(&c->err, 128u);
           base = 0xFFFFFFFFu;
         } else {
-          atomicAdd(&c->job_nodes[F.job], s_nemit);
+          atomicAdd(&c->job_nodes[F.job], nch);
         }
         s_base = base;
       }
@@ -939,11 +943,10 @@ k_finish(const Fin* fin, int par_end, const float* soa0, const float* soa1, uint
       }
       if (tid == 0) L[n] = (uint16_t)tot;
       __syncthreads();
+      nch = 2 * nact;
+      if (tid == 0) ebase_next = atomicAdd(&c->nemit, nch);
       // ---- stable scatter into the other position buffer ----
-      if (tid == 0) {
-        s_nact = 0;
-        s_nemit = 0;
-      }
+      if (tid == 0) s_nact = 0;
       for (uint32_t i = tid; i < n; i += NT) {
         const uint16_t s0 = sidv[cur][i];
         const uint16_t s = s0 == kFrozen ? kFrozen : remap[s0];
@@ -962,7 +965,6 @@ k_finish(const Fin* fin, int par_end, const float* soa0, const float* soa1, uint
           sidv[cur ^ 1][np] = (uint16_t)(2u * s + (f ? 0u : 1u));
         }
       }
-      nch = 2 * nact;
       for (uint32_t e = tid; e < nch * 2 * DMAX; e += NT) {
         const uint32_t j = e % (2 * DMAX);
         cbox[e / (2 * DMAX)][j] = j < (uint32_t)DMAX ? 0xFFFFFFFFu : 0u;
