@@ -795,35 +795,43 @@ k_finish(const Fin* fin, int par_end, const float* soa0, const float* soa1, uint
     __syncthreads();
 
     // child boxes by a segmented min/max over positions (children are
-    // contiguous runs of equal sid)
+    // contiguous runs of equal sid, so a child occurs as one run in a
+    // wavefront and equal keys mean the same run): a segmented inclusive
+    // scan by DPP steps, whose result at the run's last lane is added to
+    // the child's box
     auto child_boxes = [&](int buf) {
+      constexpr uint32_t kNoKey = 0xFFFFFFFEu;  // no child has this key
       for (uint32_t b0 = 0; b0 < n; b0 += NT) {
         const uint32_t i = b0 + tid;
         const bool valid = i < n;
         const uint32_t key = valid ? (uint32_t)sidv[buf][i] : (uint32_t)kFrozen;
         const uint32_t p = valid ? (uint32_t)pos[buf][i] : 0u;
         bool same[6];
-#pragma unroll
-        for (int s = 0; s < 6; ++s) {
-          const int o = 1 << s;
-          uint32_t ko = (uint32_t)__shfl_up((int)key, o, 64);
-          same[s] = lane >= o && ko == key;
-        }
+        same[0] = dpp_move<kDppRowShr1, 0xF>(kNoKey, key) == key;
+        same[1] = dpp_move<kDppRowShr2, 0xF>(kNoKey, key) == key;
+        same[2] = dpp_move<kDppRowShr4, 0xF>(kNoKey, key) == key;
+        same[3] = dpp_move<kDppRowShr8, 0xF>(kNoKey, key) == key;
+        same[4] = dpp_move<kDppRowBcast15, 0xA>(kNoKey, key) == key;
+        same[5] = dpp_move<kDppRowBcast31, 0xC>(kNoKey, key) == key;
         const uint32_t kn = (uint32_t)__shfl_down((int)key, 1, 64);
         const bool last = key != kFrozen && (lane == 63 || kn != key);
         for (int j = 0; j < d; ++j) {
           uint32_t lo = valid ? f2o(xs[j][p]) : 0u;
           uint32_t hi = lo;
-#pragma unroll
-          for (int s = 0; s < 6; ++s) {
-            const int o = 1 << s;
-            uint32_t olo = (uint32_t)__shfl_up((int)lo, o, 64);
-            uint32_t ohi = (uint32_t)__shfl_up((int)hi, o, 64);
-            if (same[s]) {
+          auto step = [&](bool sm, uint32_t olo, uint32_t ohi) {
+            if (sm) {
               lo = olo < lo ? olo : lo;
               hi = ohi > hi ? ohi : hi;
             }
-          }
+          };
+          step(same[0], dpp_move<kDppRowShr1, 0xF>(lo, lo), dpp_move<kDppRowShr1, 0xF>(hi, hi));
+          step(same[1], dpp_move<kDppRowShr2, 0xF>(lo, lo), dpp_move<kDppRowShr2, 0xF>(hi, hi));
+          step(same[2], dpp_move<kDppRowShr4, 0xF>(lo, lo), dpp_move<kDppRowShr4, 0xF>(hi, hi));
+          step(same[3], dpp_move<kDppRowShr8, 0xF>(lo, lo), dpp_move<kDppRowShr8, 0xF>(hi, hi));
+          step(same[4], dpp_move<kDppRowBcast15, 0xA>(lo, lo),
+               dpp_move<kDppRowBcast15, 0xA>(hi, hi));
+          step(same[5], dpp_move<kDppRowBcast31, 0xC>(lo, lo),
+               dpp_move<kDppRowBcast31, 0xC>(hi, hi));
           if (last) {
             atomicMin(&cbox[key][j], lo);
             atomicMax(&cbox[key][DMAX + j], hi);

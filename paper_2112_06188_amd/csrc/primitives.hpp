@@ -8,14 +8,31 @@
 
 namespace bdl {
 
+// Cross-lane moves of the 64-lane wavefront by DPP (VALU operand routing, no
+// LDS traffic): row_shr:k moves within rows of 16 lanes, row_bcast:15 and
+// row_bcast:31 carry a row's last lane into the following rows.  A lane
+// whose source lies outside its row, or whose row is not in ROW_MASK,
+// receives `old`.  Six such steps form a scan over the whole wavefront.
+constexpr int kDppRowShr1 = 0x111;
+constexpr int kDppRowShr2 = 0x112;
+constexpr int kDppRowShr4 = 0x114;
+constexpr int kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142;  // rows 1 and 3 (row mask 0xA)
+constexpr int kDppRowBcast31 = 0x143;  // rows 2 and 3 (row mask 0xC)
+
+template <int CTRL, int ROW_MASK>
+__device__ inline uint32_t dpp_move(uint32_t old, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+
 // Inclusive/exclusive scans inside a 64-lane wavefront and a workgroup.
 __device__ inline uint32_t wave_incl_scan(uint32_t v) {
-  const int lane = __lane_id();
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t t = __shfl_up(v, o, 64);
-    if (lane >= o) v += t;
-  }
+  v += dpp_move<kDppRowShr1, 0xF>(0u, v);
+  v += dpp_move<kDppRowShr2, 0xF>(0u, v);
+  v += dpp_move<kDppRowShr4, 0xF>(0u, v);
+  v += dpp_move<kDppRowShr8, 0xF>(0u, v);
+  v += dpp_move<kDppRowBcast15, 0xA>(0u, v);
+  v += dpp_move<kDppRowBcast31, 0xC>(0u, v);
   return v;
 }
 
