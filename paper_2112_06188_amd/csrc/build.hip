@@ -578,6 +578,30 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
   }
 }
 
+// Add one bound of a child's box to the device copy.  A side with no point
+// keeps the neutral value (0xFFFFFFFF for a minimum, 0 for a maximum), which
+// no finite coordinate maps to; it is skipped, as is a missing child.
+__device__ inline void add_bound(Seg* nxt, uint32_t ch, int j, bool is_max, uint32_t v) {
+  if (ch == kNone) return;
+  if (is_max) {
+    if (v != 0u) atomicMax(&nxt[ch].box[kMaxDim + j], v);
+  } else {
+    if (v != 0xFFFFFFFFu) atomicMin(&nxt[ch].box[j], v);
+  }
+}
+
+// Lane 4j+q adds bound q (left min, left max, right min, right max) of
+// dimension j of a tile's children.
+template <int D>
+__device__ inline void add_child_boxes(Seg* nxt, uint32_t c0, uint32_t c1,
+                                       const uint32_t (&bx)[D][4], int lane) {
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (lane == 4 * j + q) add_bound(nxt, q < 2 ? c0 : c1, j, q & 1, bx[j][q]);
+}
+
 // Stable partition of every tile into the other build buffer; accumulates
 // the tight boxes of children that stay in the global passes; leaves that
 // are too large for the finisher (coincident points) are copied out whole.
@@ -585,20 +609,33 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
 // row gives every point its rank among the tile's left (or right) points,
 // with the running count held wave-uniform, so no LDS or barrier is needed.
 // D is the dimension: all columns of a row are read once, and the children's
-// boxes are kept in registers for all dimensions.
+// boxes are kept in registers for all dimensions.  A wavefront's last tile
+// does not add its boxes to the device right away: the workgroup's
+// wavefronts hold consecutive tiles, mostly of one segment near the root,
+// and merge their boxes first, so that the device atomics on a child's box
+// (all of which meet at one address) are fewer by the wavefront count.
+constexpr int kScatterThreads = 512;
+
 template <int D>
-__global__ void __launch_bounds__(kPassThreads)
+__global__ void __launch_bounds__(kScatterThreads)
 k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounters* c,
           const float* __restrict__ src, float* __restrict__ dst, uint64_t cap,
           const uint32_t* tile_off, const Job* jobs, uint64_t* map, uint32_t idcap) {
-  constexpr int kWaves = kPassThreads / 64;
+  constexpr int kWaves = kScatterThreads / 64;
+  __shared__ uint32_t s_ch[kWaves][2];
+  __shared__ uint32_t s_bx[kWaves][4 * D];
   const uint32_t nt = c->ntiles;
   const int lane = __lane_id();
+  const int w = threadIdx.x >> 6;
   const uint64_t below = lanemask_lt();
   const uint32_t* sid = soa_ids(src, D, cap);
   uint32_t* did = soa_ids_w(dst, D, cap);
   const uint32_t nw = gridDim.x * kWaves;
-  for (uint32_t t = blockIdx.x * kWaves + (threadIdx.x >> 6); t < nt; t += nw) {
+  // this wavefront's slot of the workgroup merge: its last tile's children
+  // and boxes (empty until then)
+  if (lane < 2) s_ch[w][lane] = kNone;
+  if (lane < 4 * D) s_bx[w][lane] = (lane & 1) ? 0u : 0xFFFFFFFFu;
+  for (uint32_t t = blockIdx.x * kWaves + w; t < nt; t += nw) {
     const uint32_t s = tile_seg[t];
     const Seg& g = cur[s];
     const uint64_t gbegin = g.begin;
@@ -680,27 +717,41 @@ k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounter
       wave_minmax(bx[j][0], bx[j][1]);
       wave_minmax(bx[j][2], bx[j][3]);
     }
-    // lane 4j+q adds bound q of dimension j; a side with no point in this
-    // tile keeps the neutral values (0xFFFFFFFF, 0), which no finite
-    // coordinate maps to, and is skipped
     const uint32_t c0 = g.child[0], c1 = g.child[1];
+    if (t + nw < nt) {
+      add_child_boxes<D>(nxt, c0, c1, bx, lane);
+    } else {
+      if (lane == 0) {
+        s_ch[w][0] = c0;
+        s_ch[w][1] = c1;
+      }
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
+      for (int j = 0; j < D; ++j)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (lane == 4 * j + q) {
-          const uint32_t ch = q < 2 ? c0 : c1;
-          const uint32_t v = bx[j][q];
-          if (ch != kNone) {
-            if (q & 1) {
-              if (v != 0u) atomicMax(&nxt[ch].box[kMaxDim + j], v);
-            } else {
-              if (v != 0xFFFFFFFFu) atomicMin(&nxt[ch].box[j], v);
-            }
-          }
-        }
+        for (int q = 0; q < 4; ++q)
+          if (lane == 4 * j + q) s_bx[w][4 * j + q] = bx[j][q];
+    }
+  }
+  // workgroup merge: runs of wavefronts with the same child combine their
+  // bounds before one device atomic per run
+  __syncthreads();
+  if (w == 0 && lane < 4 * D) {
+    const int j = lane >> 2, q = lane & 3;
+    const bool is_max = q & 1;
+    const uint32_t neutral = is_max ? 0u : 0xFFFFFFFFu;
+    uint32_t run_ch = kNone, acc = neutral;
+    for (int v = 0; v < kWaves; ++v) {
+      const uint32_t ch = s_ch[v][q >> 1];
+      const uint32_t x = s_bx[v][lane];
+      if (ch != run_ch) {
+        add_bound(nxt, run_ch, j, is_max, acc);
+        run_ch = ch;
+        acc = x;
+      } else {
+        acc = is_max ? (x > acc ? x : acc) : (x < acc ? x : acc);
       }
     }
+    add_bound(nxt, run_ch, j, is_max, acc);
   }
 }
 
@@ -1113,7 +1164,7 @@ inline unsigned grid_for(uint64_t n, unsigned threads, unsigned cap = 4096) {
 template <int D>
 void launch_scatter_d(unsigned grid, const BuildScratch& sc, int par, uint64_t* map,
                       uint32_t idcap, hipStream_t s) {
-  hipLaunchKernelGGL((k_scatter<D>), dim3(grid), dim3(kPassThreads), 0, s, sc.seg[par],
+  hipLaunchKernelGGL((k_scatter<D>), dim3(grid), dim3(kScatterThreads), 0, s, sc.seg[par],
                      sc.tile_seg, sc.seg[par ^ 1], sc.ctr, sc.soa[par], sc.soa[par ^ 1], sc.cap,
                      sc.tile_off, sc.jobs, map, idcap);
 }
@@ -1273,6 +1324,9 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
   // few depths beyond log2(n / T) before the first check
   budget += 1;
   const unsigned pass_grid = grid_for(R, kTile, 2048);
+  // two wavefronts of the scatter per tile of R points (a depth has at most
+  // R / kTile + segments tiles)
+  const unsigned scatter_grid = grid_for(R, kTile * (kScatterThreads / 128), 1024);
   while (true) {
     for (int b = 0; b < budget; ++b, ++depth) {
       const int par = depth & 1;
@@ -1284,7 +1338,7 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
       hipLaunchKernelGGL(k_tilescan, dim3(1), dim3(1024), 0, s, sc.seg[par], sc.seg[par ^ 1],
                          sc.ctr, par, sc.tile_left, sc.tile_off, sc.fin, T, sc.max_seg,
                          sc.max_fin);
-      launch_scatter(d, pass_grid, sc, par, map, idcap, s);
+      launch_scatter(d, scatter_grid, sc, par, map, idcap, s);
     }
     pt.end(BDL_PH_PASSES);
     pt.begin(BDL_PH_FINISH);
