@@ -271,11 +271,23 @@ k_root_box(const float* soa, uint64_t cap, int d, const Job* jobs, BuildCounters
   for (int j = 0; j < d; ++j) {
     uint32_t mn = 0xFFFFFFFFu, mx = 0u;
     const float* x = soa + (uint64_t)j * cap + J.base;
-    for (uint64_t i = (uint64_t)blockIdx.x * kPassThreads + threadIdx.x; i < J.count;
-         i += (uint64_t)gridDim.x * kPassThreads) {
-      const uint32_t o = f2o(x[i]);
-      mn = o < mn ? o : mn;
-      mx = o > mx ? o : mx;
+    // eight independent loads per step (indices clamped into the job; a
+    // repeated element does not change a bound)
+    const uint64_t stride = (uint64_t)gridDim.x * kPassThreads;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * kPassThreads + threadIdx.x; i0 < J.count;
+         i0 += 8 * stride) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint64_t i = i0 + (uint64_t)u * stride;
+        v[u] = x[i < J.count ? i : i0];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint32_t o = f2o(v[u]);
+        mn = o < mn ? o : mn;
+        mx = o > mx ? o : mx;
+      }
     }
     wave_minmax(mn, mx);
     if (lane == 0) {

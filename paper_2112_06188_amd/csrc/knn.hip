@@ -73,10 +73,21 @@ k_query_box(const float* q, const uint64_t* nq_dev, uint64_t nq_host, int d, uin
   __syncthreads();
   uint32_t mn = 0xFFFFFFFFu, mx = 0u;
   if (t < stride) {
-    for (uint64_t i = t; i < total; i += stride) {
-      const uint32_t o = f2o(q[i]);
-      mn = o < mn ? o : mn;
-      mx = o > mx ? o : mx;
+    // eight independent loads per step; an index past the end repeats this
+    // thread's first element, which does not change a bound
+    for (uint64_t i0 = t; i0 < total; i0 += 8 * stride) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint64_t i = i0 + (uint64_t)u * stride;
+        v[u] = q[i < total ? i : i0];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint32_t o = f2o(v[u]);
+        mn = o < mn ? o : mn;
+        mx = o > mx ? o : mx;
+      }
     }
   }
   const int j = (int)(t % (uint64_t)d);
@@ -89,44 +100,61 @@ k_query_box(const float* q, const uint64_t* nq_dev, uint64_t nq_host, int d, uin
   }
 }
 
-// Position along the Hilbert curve of the cell x[0..d) (bits per
+// Position along the Hilbert curve of the cell x[0..D) (BITS per
 // coordinate), by Skilling's transform of the axes into the curve's
 // "transposed" index (J. Skilling, Programming the Hilbert curve, AIP Conf.
 // Proc. 707, 2004) followed by bit interleaving.  Unlike Morton order the
 // curve has no jumps: consecutive keys are neighbouring cells, so a group of
-// consecutive queries covers a compact region.  x is overwritten.
-__device__ inline uint32_t hilbert_key(uint32_t* x, int d, int bits) {
-  const uint32_t top = 1u << (bits - 1);
+// consecutive queries covers a compact region.  x is overwritten.  D and
+// BITS are compile-time, so the transform is straight-line code.
+template <int D, int BITS>
+__device__ inline uint32_t hilbert_key(uint32_t (&x)[D]) {
+  constexpr uint32_t top = 1u << (BITS - 1);
+#pragma unroll
   for (uint32_t q = top; q > 1; q >>= 1) {
     const uint32_t low = q - 1;
-    for (int j = 0; j < d; ++j) {
-      if (x[j] & q) {
-        x[0] ^= low;
-      } else {
-        const uint32_t t = (x[0] ^ x[j]) & low;
-        x[0] ^= t;
-        x[j] ^= t;
-      }
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const uint32_t t = (x[0] ^ x[j]) & low;
+      const bool set = (x[j] & q) != 0u;
+      // bit q of x[j] set: invert the low bits of x[0]; else exchange them
+      // between x[0] and x[j]
+      const uint32_t x0 = set ? (x[0] ^ low) : (x[0] ^ t);
+      const uint32_t xj = set ? x[j] : (x[j] ^ t);
+      x[0] = x0;
+      if (j != 0) x[j] = xj;
     }
   }
-  for (int j = 1; j < d; ++j) x[j] ^= x[j - 1];
+#pragma unroll
+  for (int j = 1; j < D; ++j) x[j] ^= x[j - 1];
   uint32_t t = 0;
+#pragma unroll
   for (uint32_t q = top; q > 1; q >>= 1)
-    if (x[d - 1] & q) t ^= q - 1;
-  for (int j = 0; j < d; ++j) x[j] ^= t;
+    if (x[D - 1] & q) t ^= q - 1;
+#pragma unroll
+  for (int j = 0; j < D; ++j) x[j] ^= t;
   uint32_t key = 0;
-  for (int b = bits - 1; b >= 0; --b)
-    for (int j = 0; j < d; ++j) key = (key << 1) | ((x[j] >> b) & 1u);
+#pragma unroll
+  for (int b = BITS - 1; b >= 0; --b)
+#pragma unroll
+    for (int j = 0; j < D; ++j) key = (key << 1) | ((x[j] >> b) & 1u);
   return key;
 }
 
-// Hilbert key with bits = floor(30 / d) bits per dimension; positions from nq
-// up to cap get the key 0xFFFFFFFF, which sorts after every real key.
+// Hilbert key with floor(30 / D) bits per dimension; positions from nq up
+// to cap get the key 0xFFFFFFFF, which sorts after every real key.
+template <int D>
 __global__ void k_hilbert(const float* q, const uint64_t* nq_dev, uint64_t nq_host, uint64_t cap,
-                         int d, const uint32_t* box, uint32_t* keys, uint32_t* vals) {
+                          const uint32_t* box, uint32_t* keys, uint32_t* vals) {
+  constexpr int kBits = 30 / D > 0 ? 30 / D : 1;
   const uint64_t nq = nq_dev ? *nq_dev : nq_host;
-  const int bits = 30 / d > 0 ? 30 / d : 1;
-  const float cells = (float)(1u << bits);
+  const float cells = (float)(1u << kBits);
+  float lo[D], ext[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    lo[j] = o2f(box[j]);
+    ext[j] = o2f(box[kMaxDim + j]) - lo[j];
+  }
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap;
        i += (uint64_t)gridDim.x * blockDim.x) {
     vals[i] = (uint32_t)i;
@@ -134,16 +162,15 @@ __global__ void k_hilbert(const float* q, const uint64_t* nq_dev, uint64_t nq_ho
       keys[i] = 0xFFFFFFFFu;
       continue;
     }
-    uint32_t cell[kMaxDim];
-    for (int j = 0; j < d; ++j) {
-      float lo = o2f(box[j]), hi = o2f(box[kMaxDim + j]);
-      float ext = hi - lo;
-      float u = ext > 0.0f ? (q[i * d + j] - lo) / ext : 0.0f;
+    uint32_t cell[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const float u = ext[j] > 0.0f ? (q[i * D + j] - lo[j]) / ext[j] : 0.0f;
       int c = (int)(u * cells);
-      c = c < 0 ? 0 : (c >= (int)(1u << bits) ? (int)(1u << bits) - 1 : c);
+      c = c < 0 ? 0 : (c >= (1 << kBits) ? (1 << kBits) - 1 : c);
       cell[j] = (uint32_t)c;
     }
-    keys[i] = hilbert_key(cell, d, bits);
+    keys[i] = hilbert_key<D, kBits>(cell);
   }
 }
 
@@ -184,8 +211,20 @@ const uint32_t* spatial_order(int d, const float* q, const uint64_t* nq_dev, uin
   hipLaunchKernelGGL(k_query_box, dim3(g), dim3(256), 0, s, q, nq_dev, nq_host, d, qs.box);
   unsigned g2 = (unsigned)((cap + 255) / 256);
   if (g2 > 4096) g2 = 4096;
-  hipLaunchKernelGGL(k_hilbert, dim3(g2), dim3(256), 0, s, q, nq_dev, nq_host, cap, d, qs.box,
-                     qs.keys[0], qs.vals[0]);
+  switch (d) {
+#define BDL_HILBERT_CASE(DD)                                                                    \
+  case DD:                                                                                      \
+    hipLaunchKernelGGL(k_hilbert<DD>, dim3(g2), dim3(256), 0, s, q, nq_dev, nq_host, cap, qs.box, \
+                       qs.keys[0], qs.vals[0]);                                                 \
+    break;
+    BDL_HILBERT_CASE(1) BDL_HILBERT_CASE(2) BDL_HILBERT_CASE(3) BDL_HILBERT_CASE(4)
+    BDL_HILBERT_CASE(5) BDL_HILBERT_CASE(6) BDL_HILBERT_CASE(7) BDL_HILBERT_CASE(8)
+    BDL_HILBERT_CASE(9) BDL_HILBERT_CASE(10) BDL_HILBERT_CASE(11) BDL_HILBERT_CASE(12)
+    BDL_HILBERT_CASE(13) BDL_HILBERT_CASE(14) BDL_HILBERT_CASE(15) BDL_HILBERT_CASE(16)
+#undef BDL_HILBERT_CASE
+    default:
+      break;
+  }
   const int bits = (30 / d > 0 ? 30 / d : 1) * d;
   int which = radix_sort_pairs_u32(qs.keys[0], qs.vals[0], qs.keys[1], qs.vals[1], cap, 0, bits,
                                    qs.tmp, s);
