@@ -75,6 +75,32 @@ __device__ inline void write_emit(uint32_t* emit, int es, uint32_t idx, uint64_t
   }
 }
 
+// Slots from an LDS counter for the lanes that want one, with one atomic per
+// wavefront (atomics on one LDS address serialize lane by lane).  Every lane
+// of the wavefront calls it; lanes that want no slot get an unspecified value.
+__device__ inline uint32_t wave_alloc(uint32_t* counter, bool want) {
+  const uint64_t m = __ballot(want);
+  if (m == 0) return 0u;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0;
+  if (__lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+  base = (uint32_t)__shfl((int)base, leader, 64);
+  return base + (uint32_t)__popcll(m & lanemask_lt());
+}
+
+// Lanes of the wavefront with the same job as this one (jobs < kMaxJobs = 64,
+// one ballot per bit of the job index); meaningful for valid lanes only.
+__device__ inline uint64_t job_peers(uint32_t job, bool valid) {
+  uint64_t m = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 6; ++b) {
+    const bool bit = (job >> b) & 1u;
+    const uint64_t bb = __ballot(valid && bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
 __device__ inline void wave_minmax(uint32_t& mn, uint32_t& mx) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
@@ -409,6 +435,7 @@ k_setup(Seg* cur, uint32_t* segtb, uint32_t* tile_seg, BuildCounters* c, int par
   for (uint32_t ch = 0; ch < n; ch += blockDim.x) {
     uint32_t s = ch + threadIdx.x;
     uint32_t ntl = 0;
+    uint32_t sjob = 0, sdepth = 0;
     if (s < n) {
       Seg& g = cur[s];
       const uint32_t* lo = g.box;
@@ -423,12 +450,21 @@ k_setup(Seg* cur, uint32_t* segtb, uint32_t* tile_seg, BuildCounters* c, int par
       const Job& J = jobs[g.job];
       write_emit(emit, es, eidx, g.path, g.depth, g.job, g.parent_emit, g.side,
                  g.begin - J.base, g.count, split, dim, lo, hi, d);
-      atomicAdd(&s_jn[g.job], 1u);
-      atomicMax(&s_jh[g.job], g.depth + 1);
+      sjob = g.job;
+      sdepth = g.depth;
       g.emit = eidx;
       g.dim = dim;
       g.split = split;
       ntl = (g.count + kTile - 1) / kTile;
+    }
+    // node counts and heights per job: one LDS update per job and wavefront
+    {
+      const bool valid = s < n;
+      const uint64_t m = job_peers(sjob, valid);
+      if (valid && (m & lanemask_lt()) == 0) {
+        atomicAdd(&s_jn[sjob], (uint32_t)__popcll(m));
+        atomicMax(&s_jh[sjob], sdepth + 1);
+      }
     }
     uint32_t tot;
     uint32_t ex = block_excl_scan(ntl, wsum, &tot);
@@ -529,23 +565,34 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
     carry += tot;
   }
   __syncthreads();
-  for (uint32_t s = threadIdx.x; s < ns; s += blockDim.x) {
-    Seg& g = cur[s];
-    if (g.dim < 0) {
-      g.child[0] = g.child[1] = kNone;
-      continue;
+  // every thread runs the same number of rounds, so that list slots can be
+  // taken with one LDS atomic per wavefront
+  for (uint32_t s0 = 0; s0 < ns; s0 += blockDim.x) {
+    const uint32_t s = s0 + threadIdx.x;
+    const bool split = s < ns && cur[s].dim >= 0;
+    if (s < ns && !split) cur[s].child[0] = cur[s].child[1] = kNone;
+    uint32_t nl = 0, gbegin = 0, gcount = 0;
+    if (split) {
+      Seg& g = cur[s];
+      const uint32_t last = g.tile_begin + g.ntiles;
+      const uint32_t g0 = tile_off[g.tile_begin];
+      const uint32_t g1 = last < nt ? tile_off[last] : carry;
+      nl = g1 - g0;
+      g.nleft = nl;
+      gbegin = g.begin;
+      gcount = g.count;
     }
-    const uint32_t last = g.tile_begin + g.ntiles;
-    const uint32_t g0 = tile_off[g.tile_begin];
-    const uint32_t g1 = last < nt ? tile_off[last] : carry;
-    const uint32_t nl = g1 - g0;
-    g.nleft = nl;
     for (int side = 0; side < 2; ++side) {
-      const uint32_t cb = side ? g.begin + nl : g.begin;
-      const uint32_t cc = side ? g.count - nl : nl;
+      const uint32_t cb = side ? gbegin + nl : gbegin;
+      const uint32_t cc = side ? gcount - nl : nl;
+      const bool to_seg = split && cc > T;
+      const bool to_fin = split && !(cc > T);
+      const uint32_t k = wave_alloc(&s_nseg, to_seg);
+      const uint32_t f = wave_alloc(&s_nfin, to_fin);
+      if (!split) continue;
+      Seg& g = cur[s];
       const uint64_t cpath = (g.path << 1) | (uint64_t)side;
-      if (cc > T) {
-        uint32_t k = atomicAdd(&s_nseg, 1u);
+      if (to_seg) {
         if (k >= max_seg) {
           atomicOr(&c->err, 8u);
           g.child[side] = kNone;
@@ -565,7 +612,6 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
         }
         g.child[side] = k;
       } else {
-        uint32_t f = atomicAdd(&s_nfin, 1u);
         g.child[side] = kNone;
         if (f >= max_fin) {
           atomicOr(&c->err, 16u);
@@ -920,6 +966,7 @@ k_finish(const Fin* fin, int par_end, const float* soa0, const float* soa1, uint
       int cdim = -1;
       float csplit = 0.0f;
       const bool have = (uint32_t)tid < nch;
+      bool want_act = false;
       if (have) {
         const uint32_t ch = (uint32_t)tid;
         if (root) {
@@ -946,16 +993,22 @@ k_finish(const Fin* fin, int par_end, const float* soa0, const float* soa1, uint
         const bool isleaf = ccount <= leaf || degenerate || cdepth >= (uint32_t)kMaxDepth;
         if (!isleaf) choose_split(lo, hi, d, (int)cdepth, &cdim, &csplit);
         le = ch;
-        if (!isleaf) {
-          ai = atomicAdd(&s_nact, 1u);
+        want_act = !isleaf;
+      }
+      // internal children get act-table slots, one LDS atomic per wavefront
+      {
+        const uint32_t slot = wave_alloc(&s_nact, want_act);
+        if (want_act) {
+          ai = slot;
           if (ai >= (uint32_t)MAXACT) {
             atomicOr(&c->err, 64u);
             ai = kNone;
           }
         }
-        remap[ch] = ai == kNone ? kFrozen : (uint16_t)ai;
-        atomicMax(&s_maxdepth, cdepth);
       }
+      if (have) remap[tid] = ai == kNone ? kFrozen : (uint16_t)ai;
+      // all children of a depth have the same depth
+      if (tid == 0) s_maxdepth = cdepth > s_maxdepth ? cdepth : s_maxdepth;
       if (tid == 0) {
         uint32_t base = ebase_next;
         if ((uint64_t)base + nch > max_emit) {
