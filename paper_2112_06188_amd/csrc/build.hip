@@ -58,20 +58,22 @@ __device__ inline void write_emit(uint32_t* emit, int es, uint32_t idx, uint64_t
                                   uint32_t depth, uint32_t job, uint32_t parent, uint32_t side,
                                   uint32_t begin, uint32_t count, float split, int dim,
                                   const uint32_t* lo, const uint32_t* hi, int d) {
-  uint32_t* e = emit + (uint64_t)idx * es;
-  e[EF_PATH_LO] = (uint32_t)path;
-  e[EF_PATH_HI] = (uint32_t)(path >> 32);
-  e[EF_DEPTH] = depth;
-  e[EF_JOB] = job;
-  e[EF_PARENT] = parent;
-  e[EF_SIDE] = side;
-  e[EF_BEGIN] = begin;
-  e[EF_COUNT] = count;
-  e[EF_SPLIT] = __float_as_uint(split);
-  e[EF_DIM] = (uint32_t)dim;
-  for (int j = 0; j < d; ++j) {
-    e[EF_BOX + j] = o2f_bits(lo[j]);
-    e[EF_BOX + d + j] = o2f_bits(hi[j]);
+  // a record starts 8-byte aligned (es is even) and its fields pair up, so
+  // it is written with 8-byte stores
+  uint2* e = reinterpret_cast<uint2*>(emit + (uint64_t)idx * es);
+  static_assert(EF_PATH_LO == 0 && EF_DEPTH == 2 && EF_PARENT == 4 && EF_BEGIN == 6 &&
+                    EF_SPLIT == 8 && EF_BOX == 10,
+                "emit fields pair up");
+  e[0] = make_uint2((uint32_t)path, (uint32_t)(path >> 32));
+  e[1] = make_uint2(depth, job);
+  e[2] = make_uint2(parent, side);
+  e[3] = make_uint2(begin, count);
+  e[4] = make_uint2(__float_as_uint(split), (uint32_t)dim);
+  // box words lo[0..d) then hi[0..d), two at a time (2d is even)
+  for (int w = 0; w < 2 * d; w += 2) {
+    const uint32_t a = w < d ? o2f_bits(lo[w]) : o2f_bits(hi[w - d]);
+    const uint32_t b = w + 1 < d ? o2f_bits(lo[w + 1]) : o2f_bits(hi[w + 1 - d]);
+    e[5 + w / 2] = make_uint2(a, b);
   }
 }
 
@@ -544,7 +546,8 @@ k_count(const Seg* cur, const uint32_t* tile_seg, const BuildCounters* c,
 // finisher.
 __global__ void __launch_bounds__(1024)
 k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_left,
-           uint32_t* tile_off, Fin* fin, uint32_t T, uint64_t max_seg, uint64_t max_fin) {
+           uint32_t* tile_off, Fin* fin, uint32_t T, uint64_t max_seg, uint64_t max_fin, int d) {
+  const int d4 = (d + 3) & ~3;
   __shared__ uint32_t wsum[17];
   // list sizes are counted in LDS (this is the only workgroup) and stored once
   __shared__ uint32_t s_nseg, s_nfin;
@@ -606,9 +609,12 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
         h.path = cpath;
         h.parent_emit = g.emit;
         h.side = (uint32_t)side;
-        for (int j = 0; j < kMaxDim; ++j) {
-          h.box[j] = 0xFFFFFFFFu;
-          h.box[kMaxDim + j] = 0u;
+        // neutral bounds for the first d dimensions (the only ones used),
+        // four at a time
+        for (int j = 0; j < d4; j += 4) {
+          *reinterpret_cast<uint4*>(&h.box[j]) =
+              make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+          *reinterpret_cast<uint4*>(&h.box[kMaxDim + j]) = make_uint4(0u, 0u, 0u, 0u);
         }
         g.child[side] = k;
       } else {
@@ -1402,7 +1408,7 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
                          sc.tile_seg, sc.ctr, sc.soa[par], sc.cap, sc.tile_left);
       hipLaunchKernelGGL(k_tilescan, dim3(1), dim3(1024), 0, s, sc.seg[par], sc.seg[par ^ 1],
                          sc.ctr, par, sc.tile_left, sc.tile_off, sc.fin, T, sc.max_seg,
-                         sc.max_fin);
+                         sc.max_fin, d);
       launch_scatter(d, scatter_grid, sc, par, map, idcap, s);
     }
     pt.end(BDL_PH_PASSES);
