@@ -142,12 +142,14 @@ struct Fin {
 
 struct BuildCounters {
   uint32_t nseg[2];    // segment list sizes by depth parity
-  uint32_t ntiles;
+  uint32_t ntiles[2];  // tiles of the segment lists, by depth parity
+  uint32_t ebase[2];   // emit index of each list's first segment, by depth parity
   uint32_t nfin;
   uint32_t nemit;
   uint32_t err;
   uint32_t fin_next;   // next finisher entry to take
   uint32_t retry;      // the finisher found segments left above the threshold
+  uint32_t pad_;
   uint32_t job_nodes[kMaxJobs];
   uint32_t job_height[kMaxJobs];
   uint32_t job_node_off[kMaxJobs];

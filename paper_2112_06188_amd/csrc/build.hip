@@ -266,7 +266,8 @@ __global__ void k_reset_counters(BuildCounters* c, JobTable jt, Job* jobs_dev) {
   const int t = threadIdx.x;
   if (t == 0) {
     c->nseg[0] = c->nseg[1] = 0;
-    c->ntiles = c->nfin = c->nemit = c->err = 0;
+    c->ntiles[0] = c->ntiles[1] = c->ebase[0] = c->ebase[1] = 0;
+    c->nfin = c->nemit = c->err = 0;
     c->fin_next = c->retry = 0;
   }
   if (t < kMaxJobs) {
@@ -337,9 +338,12 @@ k_root_box(const float* soa, uint64_t cap, int d, const Job* jobs, BuildCounters
 
 // Root of every job: one lane per job (kMaxJobs is one wavefront); jobs above
 // the finisher threshold start the global passes, the others go straight to
-// the finisher.  List order is job order.
+// the finisher.  List order is job order.  The roots' tiles are numbered here
+// (the list kernel numbers those of every later depth), and the roots' nodes
+// take emit indices [0, roots).
 __global__ void k_init_lists(const Job* jobs, int njobs, BuildCounters* c, Seg* cur, Fin* fin,
-                             uint32_t T, uint64_t max_seg, uint64_t max_fin) {
+                             uint32_t* tile_seg, uint32_t T, uint64_t max_seg, uint64_t max_fin,
+                             uint64_t max_tiles) {
   static_assert(kMaxJobs == 64, "one lane per job");
   const int jb = threadIdx.x;
   uint32_t cnt = 0, base = 0;
@@ -351,16 +355,22 @@ __global__ void k_init_lists(const Job* jobs, int njobs, BuildCounters* c, Seg* 
   const bool is_fin = cnt > 0 && cnt <= T;
   const uint64_t below = lanemask_lt();
   const uint64_t ms = __ballot(is_seg), mf = __ballot(is_fin);
+  const uint32_t nroot = (uint32_t)__popcll(ms);
+  // tiles of the roots, numbered in list order
+  const uint32_t ntl = is_seg ? (cnt + kTile - 1) / kTile : 0u;
+  const uint32_t tinc = wave_incl_scan(ntl);
+  const uint32_t ttot = (uint32_t)__shfl((int)tinc, 63, 64);
+  const bool over = nroot > max_seg || ttot > max_tiles;
   if (jb == 0) {
-    c->nseg[0] = (uint32_t)__popcll(ms);
+    c->nseg[0] = over ? 0u : nroot;
+    c->ntiles[0] = over ? 0u : ttot;
     c->nfin = (uint32_t)__popcll(mf);
+    c->ebase[0] = 0;
+    c->nemit = over ? 0u : nroot;
+    if (over) c->err |= nroot > max_seg ? 1u : 256u;
   }
-  if (is_seg) {
+  if (is_seg && !over) {
     const uint32_t k = (uint32_t)__popcll(ms & below);
-    if (k >= max_seg) {
-      atomicOr(&c->err, 1u);
-      return;
-    }
     Seg& g = cur[k];
     g.begin = base;
     g.count = cnt;
@@ -369,22 +379,37 @@ __global__ void k_init_lists(const Job* jobs, int njobs, BuildCounters* c, Seg* 
     g.path = 0;
     g.parent_emit = kNone;
     g.side = 0;
+    g.tile_begin = tinc - ntl;
+    g.ntiles = ntl;
     for (int j = 0; j < 2 * kMaxDim; ++j) g.box[j] = c->job_box[jb][j];
+    atomicAdd(&c->job_nodes[jb], 1u);
+    atomicMax(&c->job_height[jb], 1u);
   } else if (is_fin) {
     const uint32_t f = (uint32_t)__popcll(mf & below);
     if (f >= max_fin) {
       atomicOr(&c->err, 2u);
-      return;
+    } else {
+      Fin& F = fin[f];
+      F.begin = base;
+      F.count = cnt;
+      F.job = (uint32_t)jb;
+      F.depth = 0;
+      F.path = 0;
+      F.parent_emit = kNone;
+      F.side = 0;
+      F.bufsel = 0;
     }
-    Fin& F = fin[f];
-    F.begin = base;
-    F.count = cnt;
-    F.job = (uint32_t)jb;
-    F.depth = 0;
-    F.path = 0;
-    F.parent_emit = kNone;
-    F.side = 0;
-    F.bufsel = 0;
+  }
+  if (over) return;
+  // segment of every root tile, the wavefront filling one root's run at a time
+  uint64_t rest = ms;
+  while (rest) {
+    const int l = __ffsll((unsigned long long)rest) - 1;
+    rest &= rest - 1;
+    const uint32_t k = (uint32_t)__popcll(ms & ((1ull << l) - 1ull));
+    const uint32_t tb = (uint32_t)__shfl((int)(tinc - ntl), l, 64);
+    const uint32_t tn = (uint32_t)__shfl((int)ntl, l, 64);
+    for (uint32_t i = jb; i < tn; i += 64) tile_seg[tb + i] = k;
   }
 }
 
@@ -392,139 +417,45 @@ __global__ void k_init_lists(const Job* jobs, int njobs, BuildCounters* c, Seg* 
 // global passes (one depth per pass)
 // ------------------------------------------------------------------------
 
-// Decide every segment of this depth: emit its node, pick its split (or mark
-// it a leaf copied out whole), number its tiles, and record the segment of
-// every tile (tile_seg) so that the tile kernels need no search.
-constexpr uint32_t kSetupLds = 4096;  // segments whose tile starts stay in LDS
-
-__global__ void __launch_bounds__(1024)
-k_setup(Seg* cur, uint32_t* segtb, uint32_t* tile_seg, BuildCounters* c, int par,
-        const Job* jobs, uint32_t* emit, int es, int d, uint32_t leaf, uint64_t max_emit,
-        uint64_t max_seg, uint64_t max_tiles) {
-  __shared__ uint32_t wsum[17];
-  __shared__ uint32_t s_base, s_n;
-  __shared__ uint32_t s_tb[kSetupLds];
-  // per-job node counts and heights of this depth, added to the device
-  // counters once per job instead of once per segment
-  __shared__ uint32_t s_jn[kMaxJobs], s_jh[kMaxJobs];
-  if (threadIdx.x < kMaxJobs) {
-    s_jn[threadIdx.x] = 0;
-    s_jh[threadIdx.x] = 0;
-  }
-  if (threadIdx.x == 0) {
-    uint32_t nn = c->nseg[par];
-    if (nn > max_seg || c->err) {
-      // an overflow was flagged: stop working on this build
-      c->err |= nn > max_seg ? 8u : 0u;
-      nn = 0;
-    }
-    c->nseg[par] = nn;
-    s_n = nn;
-    s_base = c->nemit;
-    c->nseg[par ^ 1] = 0;
-  }
-  __syncthreads();
-  const uint32_t n = s_n;
-  if ((uint64_t)s_base + n > max_emit) {
-    if (threadIdx.x == 0) {
-      c->err |= 4u;
-      c->ntiles = 0;
-      c->nseg[par] = 0;
-    }
-    return;
-  }
-  uint32_t carry = 0;
-  for (uint32_t ch = 0; ch < n; ch += blockDim.x) {
-    uint32_t s = ch + threadIdx.x;
-    uint32_t ntl = 0;
-    uint32_t sjob = 0, sdepth = 0;
-    if (s < n) {
-      Seg& g = cur[s];
-      const uint32_t* lo = g.box;
-      const uint32_t* hi = g.box + kMaxDim;
-      bool degenerate = true;
-      for (int j = 0; j < d; ++j) degenerate = degenerate && (lo[j] == hi[j]);
-      bool isleaf = g.count <= leaf || degenerate || g.depth >= (uint32_t)kMaxDepth;
-      int dim = -1;
-      float split = 0.0f;
-      if (!isleaf) choose_split(lo, hi, d, (int)g.depth, &dim, &split);
-      const uint32_t eidx = s_base + s;
-      const Job& J = jobs[g.job];
-      write_emit(emit, es, eidx, g.path, g.depth, g.job, g.parent_emit, g.side,
-                 g.begin - J.base, g.count, split, dim, lo, hi, d);
-      sjob = g.job;
-      sdepth = g.depth;
-      g.emit = eidx;
-      g.dim = dim;
-      g.split = split;
-      ntl = (g.count + kTile - 1) / kTile;
-    }
-    // node counts and heights per job: one LDS update per job and wavefront
-    {
-      const bool valid = s < n;
-      const uint64_t m = job_peers(sjob, valid);
-      if (valid && (m & lanemask_lt()) == 0) {
-        atomicAdd(&s_jn[sjob], (uint32_t)__popcll(m));
-        atomicMax(&s_jh[sjob], sdepth + 1);
-      }
-    }
-    uint32_t tot;
-    uint32_t ex = block_excl_scan(ntl, wsum, &tot);
-    if (s < n) {
-      cur[s].tile_begin = carry + ex;
-      cur[s].ntiles = ntl;
-      segtb[s] = carry + ex;
-      if (s < kSetupLds) s_tb[s] = carry + ex;
-    }
-    carry += tot;
-  }
-  __syncthreads();
-  if (threadIdx.x < kMaxJobs && s_jn[threadIdx.x]) {
-    atomicAdd(&c->job_nodes[threadIdx.x], s_jn[threadIdx.x]);
-    atomicMax(&c->job_height[threadIdx.x], s_jh[threadIdx.x]);
-  }
-  const bool over = carry > max_tiles;
-  if (threadIdx.x == 0) {
-    if (over) {
-      c->err |= 256u;
-      c->nseg[par] = 0;
-    }
-    c->ntiles = over ? 0u : carry;
-    c->nemit = s_base + n;
-  }
-  if (over || n == 0) return;
-  __threadfence_block();
-  __syncthreads();
-  // segment of every tile: the largest s with tile start <= t
-  const uint32_t* tb = n <= kSetupLds ? s_tb : segtb;
-  for (uint32_t t = threadIdx.x; t < carry; t += blockDim.x) {
-    uint32_t lo = 0, hi = n - 1;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (tb[mid] <= t) lo = mid; else hi = mid - 1;
-    }
-    tile_seg[t] = lo;
-  }
-}
+constexpr uint32_t kSetupLds = 4096;  // list entries whose tile starts stay in LDS
 
 // Left count of every tile: one wavefront per tile (ballots, no barriers),
-// so that all of a tile's loads are in flight at once.
+// so that all of a tile's loads are in flight at once.  Every wavefront of a
+// segment takes the segment's decision itself (leaf, or split dimension and
+// value from its box); the wavefront of its first tile emits the node and
+// records the decision for the list and scatter kernels.
 __global__ void __launch_bounds__(kPassThreads)
-k_count(const Seg* cur, const uint32_t* tile_seg, const BuildCounters* c,
-        const float* src, uint64_t cap, uint32_t* tile_left) {
+k_count(Seg* cur, const uint32_t* tile_seg, BuildCounters* c, int par, const Job* jobs,
+        uint32_t* emit, int es, int d, uint32_t leaf, const float* src, uint64_t cap,
+        uint32_t* tile_left) {
   constexpr int kWaves = kPassThreads / 64;
-  const uint32_t nt = c->ntiles;
+  const uint32_t nt = c->ntiles[par];
+  const uint32_t ebase = c->ebase[par];
   const int lane = __lane_id();
   const uint32_t nw = gridDim.x * kWaves;
   for (uint32_t t = blockIdx.x * kWaves + (threadIdx.x >> 6); t < nt; t += nw) {
     const uint32_t s = tile_seg[t];
-    const Seg& g = cur[s];
-    const int dim = g.dim;
+    Seg& g = cur[s];
+    const uint32_t* lo = g.box;
+    const uint32_t* hi = g.box + kMaxDim;
+    bool degenerate = true;
+    for (int j = 0; j < d; ++j) degenerate = degenerate && (lo[j] == hi[j]);
+    const bool isleaf = g.count <= leaf || degenerate || g.depth >= (uint32_t)kMaxDepth;
+    int dim = -1;
+    float split = 0.0f;
+    if (!isleaf) choose_split(lo, hi, d, (int)g.depth, &dim, &split);
+    if (t == g.tile_begin && lane == 0) {
+      const uint32_t eidx = ebase + s;
+      write_emit(emit, es, eidx, g.path, g.depth, g.job, g.parent_emit, g.side,
+                 g.begin - jobs[g.job].base, g.count, split, dim, lo, hi, d);
+      g.emit = eidx;
+      g.dim = dim;
+      g.split = split;
+    }
     if (dim < 0) {
       if (lane == 0) tile_left[t] = 0;
       continue;
     }
-    const float split = g.split;
     const uint64_t tstart = (uint64_t)g.begin + (uint64_t)(t - g.tile_begin) * kTile;
     const uint64_t tend = min((uint64_t)g.begin + g.count, tstart + kTile);
     const float* x = src + (uint64_t)dim * cap;
@@ -546,16 +477,24 @@ k_count(const Seg* cur, const uint32_t* tile_seg, const BuildCounters* c,
 // finisher.
 __global__ void __launch_bounds__(1024)
 k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_left,
-           uint32_t* tile_off, Fin* fin, uint32_t T, uint64_t max_seg, uint64_t max_fin, int d) {
+           uint32_t* tile_off, Fin* fin, uint32_t T, uint64_t max_seg, uint64_t max_fin, int d,
+           uint32_t* segtb, uint32_t* tile_seg_next, uint64_t max_tiles, uint64_t max_emit) {
   const int d4 = (d + 3) & ~3;
   __shared__ uint32_t wsum[17];
   // list sizes are counted in LDS (this is the only workgroup) and stored once
-  __shared__ uint32_t s_nseg, s_nfin;
-  const uint32_t nt = c->ntiles;
+  __shared__ uint32_t s_nseg, s_nfin, s_n;
+  // per-job node counts and heights of the next depth
+  __shared__ uint32_t s_jn[kMaxJobs], s_jh[kMaxJobs];
+  __shared__ uint32_t s_tb[kSetupLds];
+  const uint32_t nt = c->ntiles[par];
   const uint32_t ns = c->nseg[par];
   if (threadIdx.x == 0) {
-    s_nseg = c->nseg[par ^ 1];
+    s_nseg = 0;
     s_nfin = c->nfin;
+  }
+  if (threadIdx.x < kMaxJobs) {
+    s_jn[threadIdx.x] = 0;
+    s_jh[threadIdx.x] = 0;
   }
   __syncthreads();
   uint32_t carry = 0;
@@ -592,6 +531,15 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
       const bool to_fin = split && !(cc > T);
       const uint32_t k = wave_alloc(&s_nseg, to_seg);
       const uint32_t f = wave_alloc(&s_nfin, to_fin);
+      {
+        // the next depth's nodes per job: one LDS update per job and wavefront
+        const uint32_t cj = split ? cur[s].job : 0u;
+        const uint64_t m = job_peers(cj, to_seg);
+        if (to_seg && (m & lanemask_lt()) == 0) {
+          atomicAdd(&s_jn[cj], (uint32_t)__popcll(m));
+          atomicMax(&s_jh[cj], cur[s].depth + 2u);
+        }
+      }
       if (!split) continue;
       Seg& g = cur[s];
       const uint64_t cpath = (g.path << 1) | (uint64_t)side;
@@ -636,9 +584,61 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
     }
   }
   __syncthreads();
+  // the next depth's list: emit range, overflow checks, tile numbering
   if (threadIdx.x == 0) {
-    c->nseg[par ^ 1] = s_nseg;
     c->nfin = s_nfin;
+    uint32_t nn = s_nseg;
+    if (nn > max_seg || c->err) {
+      // an overflow was flagged: stop working on this build
+      c->err |= nn > max_seg ? 8u : 0u;
+      nn = 0;
+    }
+    const uint32_t base = c->nemit;
+    if ((uint64_t)base + nn > max_emit) {
+      c->err |= 4u;
+      nn = 0;
+    }
+    c->ebase[par ^ 1] = base;
+    c->nemit = base + nn;
+    s_n = nn;
+  }
+  __syncthreads();
+  const uint32_t n = s_n;
+  if (threadIdx.x < kMaxJobs && s_jn[threadIdx.x] && n) {
+    atomicAdd(&c->job_nodes[threadIdx.x], s_jn[threadIdx.x]);
+    atomicMax(&c->job_height[threadIdx.x], s_jh[threadIdx.x]);
+  }
+  carry = 0;
+  for (uint32_t k0 = 0; k0 < n; k0 += blockDim.x) {
+    const uint32_t k = k0 + threadIdx.x;
+    const uint32_t ntl = k < n ? (nxt[k].count + kTile - 1) / kTile : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(ntl, wsum, &tot);
+    if (k < n) {
+      nxt[k].tile_begin = carry + ex;
+      nxt[k].ntiles = ntl;
+      segtb[k] = carry + ex;
+      if (k < kSetupLds) s_tb[k] = carry + ex;
+    }
+    carry += tot;
+  }
+  const bool over = carry > max_tiles;
+  if (threadIdx.x == 0) {
+    if (over) c->err |= 256u;
+    c->nseg[par ^ 1] = over ? 0u : n;
+    c->ntiles[par ^ 1] = over ? 0u : carry;
+  }
+  if (over || n == 0) return;
+  __syncthreads();
+  // segment of every tile of the next depth: the largest k with tile start <= t
+  const uint32_t* tb = n <= kSetupLds ? s_tb : segtb;
+  for (uint32_t t = threadIdx.x; t < carry; t += blockDim.x) {
+    uint32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (tb[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    tile_seg_next[t] = lo;
   }
 }
 
@@ -682,13 +682,13 @@ constexpr int kScatterThreads = 512;
 
 template <int D>
 __global__ void __launch_bounds__(kScatterThreads)
-k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounters* c,
+k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounters* c, int par,
           const float* __restrict__ src, float* __restrict__ dst, uint64_t cap,
           const uint32_t* tile_off, const Job* jobs, uint64_t* map, uint32_t idcap) {
   constexpr int kWaves = kScatterThreads / 64;
   __shared__ uint32_t s_ch[kWaves][2];
   __shared__ uint32_t s_bx[kWaves][4 * D];
-  const uint32_t nt = c->ntiles;
+  const uint32_t nt = c->ntiles[par];
   const int lane = __lane_id();
   const int w = threadIdx.x >> 6;
   const uint64_t below = lanemask_lt();
@@ -1236,7 +1236,8 @@ template <int D>
 void launch_scatter_d(unsigned grid, const BuildScratch& sc, int par, uint64_t* map,
                       uint32_t idcap, hipStream_t s) {
   hipLaunchKernelGGL((k_scatter<D>), dim3(grid), dim3(kScatterThreads), 0, s, sc.seg[par],
-                     sc.tile_seg, sc.seg[par ^ 1], sc.ctr, sc.soa[par], sc.soa[par ^ 1], sc.cap,
+                     sc.tile_seg[par], sc.seg[par ^ 1], sc.ctr, par, sc.soa[par], sc.soa[par ^ 1],
+                     sc.cap,
                      sc.tile_off, sc.jobs, map, idcap);
 }
 
@@ -1302,7 +1303,7 @@ size_t build_scratch_bytes(uint64_t cap, int d, uint32_t T) {
   size_t b = 0;
   b += 2 * (size_t)(d + 1) * cap * 4;
   b += 2 * max_seg * (sizeof(Seg) + 4);
-  b += 3 * max_tiles * 4;
+  b += 4 * max_tiles * 4;
   b += max_fin * sizeof(Fin);
   b += max_emit * (size_t)emit_stride(d) * 4;
   b += 2 * max_emit * 12 + max_emit * 4;
@@ -1385,7 +1386,7 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
                        sc.ctr);
   }
   hipLaunchKernelGGL(k_init_lists, dim3(1), dim3(64), 0, s, sc.jobs, njobs, sc.ctr, sc.seg[0],
-                     sc.fin, T, sc.max_seg, sc.max_fin);
+                     sc.fin, sc.tile_seg[0], T, sc.max_seg, sc.max_fin, sc.max_tiles);
   // global passes: a budget of depths, then the finisher, which does nothing
   // and asks for more depths if a segment is still above the threshold
   int depth = 0;
@@ -1401,14 +1402,13 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
   while (true) {
     for (int b = 0; b < budget; ++b, ++depth) {
       const int par = depth & 1;
-      hipLaunchKernelGGL(k_setup, dim3(1), dim3(1024), 0, s, sc.seg[par], sc.segtb[par],
-                         sc.tile_seg, sc.ctr, par, sc.jobs, sc.emit, es, d, leaf, sc.max_emit,
-                         sc.max_seg, sc.max_tiles);
       hipLaunchKernelGGL(k_count, dim3(pass_grid), dim3(kPassThreads), 0, s, sc.seg[par],
-                         sc.tile_seg, sc.ctr, sc.soa[par], sc.cap, sc.tile_left);
+                         sc.tile_seg[par], sc.ctr, par, sc.jobs, sc.emit, es, d, leaf,
+                         sc.soa[par], sc.cap, sc.tile_left);
       hipLaunchKernelGGL(k_tilescan, dim3(1), dim3(1024), 0, s, sc.seg[par], sc.seg[par ^ 1],
                          sc.ctr, par, sc.tile_left, sc.tile_off, sc.fin, T, sc.max_seg,
-                         sc.max_fin, d);
+                         sc.max_fin, d, sc.segtb[par ^ 1], sc.tile_seg[par ^ 1], sc.max_tiles,
+                         sc.max_emit);
       launch_scatter(d, scatter_grid, sc, par, map, idcap, s);
     }
     pt.end(BDL_PH_PASSES);

@@ -16,7 +16,7 @@ struct BuildScratch {
   Seg* seg[2] = {nullptr, nullptr};
   uint32_t* segtb[2] = {nullptr, nullptr};
   uint32_t* tile_left = nullptr;
-  uint32_t* tile_seg = nullptr;  // segment of each tile of the current pass
+  uint32_t* tile_seg[2] = {nullptr, nullptr};  // segment of each tile, by depth parity
   uint32_t* tile_off = nullptr;
   uint64_t max_tiles = 0;
   Fin* fin = nullptr;

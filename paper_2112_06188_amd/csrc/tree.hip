@@ -186,7 +186,8 @@ void free_build_scratch(bdl_tree* t) {
     dfree(t, sc.vals[i]);
   }
   dfree(t, sc.tile_left);
-  dfree(t, sc.tile_seg);
+  dfree(t, sc.tile_seg[0]);
+  dfree(t, sc.tile_seg[1]);
   dfree(t, sc.tile_off);
   dfree(t, sc.fin);
   dfree(t, sc.emit);
@@ -233,7 +234,8 @@ bool ensure_build_scratch(bdl_tree* t, uint64_t need) {
     n.vals[i] = (uint32_t*)A(n.max_emit * 4);
   }
   n.tile_left = (uint32_t*)A(n.max_tiles * 4);
-  n.tile_seg = (uint32_t*)A(n.max_tiles * 4);
+  n.tile_seg[0] = (uint32_t*)A(n.max_tiles * 4);
+  n.tile_seg[1] = (uint32_t*)A(n.max_tiles * 4);
   n.tile_off = (uint32_t*)A(n.max_tiles * 4);
   n.fin = (Fin*)A(n.max_fin * sizeof(Fin));
   n.emit = (uint32_t*)A(n.max_emit * (size_t)emit_stride(d) * 4);
@@ -242,7 +244,8 @@ bool ensure_build_scratch(bdl_tree* t, uint64_t need) {
   n.tile_cnt = (uint32_t*)A((cap / kTile + 2) * 4 + (2ull << 20));
   if (!ok) {
     void* ps[] = {n.soa[0], n.soa[1], n.seg[0], n.seg[1], n.segtb[0], n.segtb[1], n.keys[0],
-                  n.keys[1], n.vals[0], n.vals[1], n.tile_left, n.tile_seg, n.tile_off, n.fin,
+                  n.keys[1], n.vals[0], n.vals[1], n.tile_left, n.tile_seg[0], n.tile_seg[1],
+                  n.tile_off, n.fin,
                   n.emit,
                   n.final_of, n.tmp, n.tile_cnt};
     for (void* p : ps) dfree(t, p);
