@@ -114,3 +114,36 @@ def test_clustered7d_10m_full_size():
     oi, od = oracle.bruteforce_knn(all_pts[live], qids, qop.pts[sel], qop.k)
     assert_knn_equal(gi.cpu().numpy()[sel], gd.cpu().numpy()[sel], oi, od, "7D full size sample")
     t.close()
+
+
+def test_one_build_with_a_long_node_list():
+    """One Insert_L of 2^14 * 1200 uniform 3D points builds a single tree
+    whose deepest global depth lists about 8192 nodes, more than the list
+    kernel keeps in LDS, so the next depth's tiles are found through the
+    device copy of the tile starts.  Checked: the level schedule, the size,
+    self-matches and sampled rows against brute force."""
+    import torch
+
+    import paper_2112_06188_amd as bdl
+    from bdl_inputs import uniform_points
+
+    torch.cuda.set_device(0)
+    log("case: one build with a long node list")
+    d, X = 3, 1200
+    n = (1 << 14) * X
+    pts = uniform_points(n, d, 11)
+    ids = np.arange(n, dtype=np.uint32)
+    t = bdl.Tree(d, leaf_size=16, buffer_size=X, id_capacity=n)
+    t.insert(to_dev(pts, torch), to_dev(ids, torch))
+    info = t.level_info()
+    assert bits(info["F"]) == [14] and info["buf_live"] == 0
+    assert t.size() == n
+    rng = np.random.default_rng(12)
+    sel = np.sort(rng.choice(n, size=64, replace=False))
+    q = np.concatenate([pts[sel], uniform_points(64, d, 13)]).astype(np.float32)
+    gi, gd = t.knn(to_dev(q, torch), 8)
+    t.sync()
+    assert torch.equal(gi[:64, 0], to_dev(ids[sel], torch))
+    oi, od = oracle.bruteforce_knn(pts, ids, q, 8)
+    assert_knn_equal(gi.cpu().numpy(), gd.cpu().numpy(), oi, od, "long node list")
+    t.close()
