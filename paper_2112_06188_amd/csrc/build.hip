@@ -417,7 +417,7 @@ __global__ void k_init_lists(const Job* jobs, int njobs, BuildCounters* c, Seg* 
 // global passes (one depth per pass)
 // ------------------------------------------------------------------------
 
-constexpr uint32_t kSetupLds = 4096;  // list entries whose tile starts stay in LDS
+constexpr uint32_t kListLds = 4096;  // list entries whose tile starts stay in LDS
 
 // Left count of every tile: one wavefront per tile (ballots, no barriers),
 // so that all of a tile's loads are in flight at once.  Every wavefront of a
@@ -485,7 +485,7 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
   __shared__ uint32_t s_nseg, s_nfin, s_n;
   // per-job node counts and heights of the next depth
   __shared__ uint32_t s_jn[kMaxJobs], s_jh[kMaxJobs];
-  __shared__ uint32_t s_tb[kSetupLds];
+  __shared__ uint32_t s_tb[kListLds];
   const uint32_t nt = c->ntiles[par];
   const uint32_t ns = c->nseg[par];
   if (threadIdx.x == 0) {
@@ -618,7 +618,7 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
       nxt[k].tile_begin = carry + ex;
       nxt[k].ntiles = ntl;
       segtb[k] = carry + ex;
-      if (k < kSetupLds) s_tb[k] = carry + ex;
+      if (k < kListLds) s_tb[k] = carry + ex;
     }
     carry += tot;
   }
@@ -631,7 +631,7 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
   if (over || n == 0) return;
   __syncthreads();
   // segment of every tile of the next depth: the largest k with tile start <= t
-  const uint32_t* tb = n <= kSetupLds ? s_tb : segtb;
+  const uint32_t* tb = n <= kListLds ? s_tb : segtb;
   for (uint32_t t = threadIdx.x; t < carry; t += blockDim.x) {
     uint32_t lo = 0, hi = n - 1;
     while (lo < hi) {
