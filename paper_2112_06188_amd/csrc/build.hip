@@ -367,7 +367,7 @@ __global__ void k_init_lists(const Job* jobs, int njobs, BuildCounters* c, Seg* 
     c->nfin = (uint32_t)__popcll(mf);
     c->ebase[0] = 0;
     c->nemit = over ? 0u : nroot;
-    if (over) c->err |= nroot > max_seg ? 1u : 256u;
+    if (over) atomicOr(&c->err, nroot > max_seg ? 1u : 256u);
   }
   if (is_seg && !over) {
     const uint32_t k = (uint32_t)__popcll(ms & below);
