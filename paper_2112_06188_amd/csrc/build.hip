@@ -1390,11 +1390,14 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
   // global passes: a budget of depths, then the finisher, which does nothing
   // and asks for more depths if a segment is still above the threshold
   int depth = 0;
-  int budget = 1;
-  while (((uint64_t)T << budget) < maxcount && budget < 40) ++budget;
-  // spatial-median splits of real data are not exactly balanced: allow a
-  // few depths beyond log2(n / T) before the first check
-  budget += 1;
+  int budget = 0;
+  if (maxcount > T) {
+    // log2(n / T) depths, and one more: spatial-median splits of real data
+    // are not exactly balanced.  Jobs within the threshold need none.
+    budget = 1;
+    while (((uint64_t)T << budget) < maxcount && budget < 40) ++budget;
+    budget += 1;
+  }
   const unsigned pass_grid = grid_for(R, kTile, 2048);
   // two wavefronts of the scatter per tile of R points (a depth has at most
   // R / kTile + segments tiles)
