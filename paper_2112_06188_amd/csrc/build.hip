@@ -682,6 +682,7 @@ constexpr int kScatterThreads = 512;
 
 template <int D>
 __global__ void __launch_bounds__(kScatterThreads)
+__attribute__((amdgpu_waves_per_eu(D <= 3 ? 8 : 1)))  // d <= 3 fits 64 VGPRs without spills
 k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounters* c, int par,
           const float* __restrict__ src, float* __restrict__ dst, uint64_t cap,
           const uint32_t* tile_off, const Job* jobs, uint64_t* map, uint32_t idcap) {
