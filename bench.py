@@ -570,8 +570,8 @@ def main():
                     help="run a plain device copy of this size first (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the structure would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
     if args.form == "batched":
         print(json.dumps(batched_bench(args)), flush=True)

@@ -589,7 +589,7 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
     c->nfin = s_nfin;
     uint32_t nn = s_nseg;
     if (nn > max_seg || c->err) {
-      // an overflow was flagged: stop working on this build
+      // an overflow was flagged: stop working on these trees
       c->err |= nn > max_seg ? 8u : 0u;
       nn = 0;
     }
