@@ -16,8 +16,10 @@
  *
  * Parity status per function (see the comments at each definition):
  *   orc_bruteforce_knn  pinned (scipy kd-tree on float64, exact integer lattice)
- *   orc_tree_*          pinned (Fig. 1 split example, Fig. 3 vEB example,
- *                       structural invariants checked outside the oracle)
+ *   orc_tree_*          pinned (Fig. 1 split example, hand-derived
+ *                       spatial-median split values of Section V-C, Fig. 3
+ *                       vEB example, structural invariants checked outside
+ *                       the oracle)
  *   orc_insert          pinned (Fig. 4 sequence, binary-counter closed form)
  *   orc_erase           pinned (live-set bookkeeping, half-capacity invariant)
  *   orc_knn             pinned (against the brute force definition)

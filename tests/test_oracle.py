@@ -149,6 +149,44 @@ def test_spatial_median_fig1():
         check_tree(p, i, nodes, g["leaf_size"])
 
 
+def _node_at(nodes, path):
+    """Node reached from the root by a string of L/R moves."""
+    i = 0
+    for m in path:
+        assert nodes[i]["dim"] >= 0, f"path {path!r} runs into a leaf"
+        i = int(nodes[i]["left"] if m == "L" else nodes[i]["right"])
+    return i
+
+
+def _slot_points(p, nodes, i):
+    nd = nodes[i]
+    rows = p[int(nd["begin"]):int(nd["begin"]) + int(nd["count"])]
+    return sorted(tuple(float(v) for v in r) for r in rows)
+
+
+_SPATIAL_CASES = _gold("spatial_median.json")["cases"]
+
+
+@pytest.mark.parametrize("case", _SPATIAL_CASES, ids=[c["name"] for c in _SPATIAL_CASES])
+def test_spatial_median_split_values(case):
+    """Hand-derived split values and sides (Section V-C) where the midpoint
+    of the tight extent differs from the mean and the object median, plus the
+    zero-extent dimension skip and the two fix-ups that keep both sides
+    non-empty (adjacent floats, overflowing sum)."""
+    pts = np.array(case["points"], np.float32)
+    p, i, nodes, h = oracle.tree_build(pts, np.arange(len(pts)), case["leaf_size"])
+    for want in case["nodes"]:
+        n = _node_at(nodes, want["path"])
+        nd = nodes[n]
+        assert int(nd["dim"]) == want["dim"], want["path"]
+        assert np.float32(nd["split"]).view(np.uint32) == np.float32(want["split"]).view(np.uint32), \
+            (want["path"], float(nd["split"]), want["split"])
+        as_f32 = lambda rows: sorted(tuple(float(np.float32(v)) for v in r) for r in rows)
+        assert _slot_points(p, nodes, int(nd["left"])) == as_f32(want["left"])
+        assert _slot_points(p, nodes, int(nd["right"])) == as_f32(want["right"])
+    check_tree(p, i, nodes, case["leaf_size"])
+
+
 def _tree_inputs():
     rng = np.random.default_rng(11)
     yield "uniform3", uniform_points(5000, 3, 1), 16
