@@ -22,6 +22,7 @@ _lib = None
 
 TOMB = 0xFFFFFFFF
 MAXD = 16
+SPLIT_RULES = {"spatial": 0, "object": 1}  # the two heuristics of Section V-C
 MAX_DEPTH = 63
 
 NODE_DTYPE = np.dtype([
@@ -39,7 +40,7 @@ NODE_DTYPE = np.dtype([
     ("path", np.uint64),
 ], align=True)
 
-CFLAGS = ["-O2", "-std=c99", "-Wall", "-ffp-contract=off", "-fno-fast-math",
+CFLAGS = ["-O3", "-std=c99", "-Wall", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
           "-fPIC", "-shared"]
 
 
@@ -72,6 +73,8 @@ def _load():
         lib.orc_erase.restype = ctypes.c_int64
         lib.orc_erase.argtypes = [c_v, c_f, c_u, ctypes.c_int64]
         lib.orc_knn.argtypes = [c_v, c_f, ctypes.c_int64, ctypes.c_int, c_u, c_f, c_v]
+        lib.orc_knn_parallel.restype = ctypes.c_int
+        lib.orc_knn_parallel.argtypes = [c_v, c_f, ctypes.c_int64, ctypes.c_int, c_u, c_f, c_v]
         lib.orc_size.restype = ctypes.c_int64
         lib.orc_size.argtypes = [c_v]
         lib.orc_level_info.argtypes = [c_v, ctypes.POINTER(ctypes.c_int32), c_i64, c_i64,
@@ -79,6 +82,11 @@ def _load():
                                        c_i64, c_i64]
         lib.orc_export_level.argtypes = [c_v, ctypes.c_int32, c_u, c_f, c_v, c_i64, c_i64]
         lib.orc_export_buffer_pool.argtypes = [c_v, c_u, c_f, c_i64]
+        lib.orc_set_split_rule.restype = ctypes.c_int
+        lib.orc_set_split_rule.argtypes = [c_v, ctypes.c_int]
+        lib.orc_tree_build_rule.restype = ctypes.c_int64
+        lib.orc_tree_build_rule.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, c_f, c_u,
+                                            ctypes.c_int64, c_v, ctypes.POINTER(ctypes.c_int32)]
         lib.orc_tree_build.restype = ctypes.c_int64
         lib.orc_tree_build.argtypes = [ctypes.c_int, ctypes.c_int, c_f, c_u, ctypes.c_int64,
                                        c_v, ctypes.POINTER(ctypes.c_int32)]
@@ -117,7 +125,8 @@ class Counters(ctypes.Structure):
 class OracleBDL:
     """The log structure of static kd-trees, serial."""
 
-    def __init__(self, dim: int, leaf_size: int = 16, buffer_size: int = 1024):
+    def __init__(self, dim: int, leaf_size: int = 16, buffer_size: int = 1024,
+                 split: str = "spatial"):
         self._lib = _load()
         self.dim = dim
         self.leaf_size = leaf_size
@@ -125,6 +134,8 @@ class OracleBDL:
         self._h = self._lib.orc_create(dim, leaf_size, buffer_size)
         if not self._h:
             raise ValueError("invalid oracle configuration")
+        if split not in SPLIT_RULES or self._lib.orc_set_split_rule(self._h, SPLIT_RULES[split]):
+            raise ValueError(f"unknown split rule {split!r}")
 
     def close(self) -> None:
         if self._h:
@@ -159,6 +170,19 @@ class OracleBDL:
         if counters:
             return ids, d2, {"node_visits": c.node_visits, "dist_evals": c.dist_evals}
         return ids, d2
+
+    def knn_parallel(self, q, k: int):
+        """The same rows as knn(), with the queries spread over host threads
+        (OpenMP; OMP_NUM_THREADS sets the count).  Returns (ids, d2,
+        threads used, counters)."""
+        qq = _pts(q, self.dim)
+        nq = qq.shape[0]
+        ids = np.empty((nq, k), dtype=np.uint32)
+        d2 = np.empty((nq, k), dtype=np.float32)
+        c = Counters()
+        used = self._lib.orc_knn_parallel(self._h, _fp(qq), nq, k, _up(ids), _fp(d2),
+                                          ctypes.byref(c))
+        return ids, d2, int(used), {"node_visits": c.node_visits, "dist_evals": c.dist_evals}
 
     def size(self) -> int:
         return int(self._lib.orc_size(self._h))
@@ -205,9 +229,10 @@ class OracleBDL:
         return ids, pts
 
 
-def tree_build(pts, ids, leaf_size: int = 16):
-    """BuildvEB over one point set; returns (pts, ids, nodes, height) with the
-    points in slot order and nodes in vEB order."""
+def tree_build(pts, ids, leaf_size: int = 16, split: str = "spatial"):
+    """BuildvEB over one point set with the spatial or object median; returns
+    (pts, ids, nodes, height) with the points in slot order and nodes in vEB
+    order."""
     lib = _load()
     p = np.array(pts, dtype=np.float32, copy=True, order="C")
     if p.ndim == 1:
@@ -217,8 +242,8 @@ def tree_build(pts, ids, leaf_size: int = 16):
     n = p.shape[0]
     nodes = np.empty(max(1, 2 * n - 1), NODE_DTYPE)
     h = ctypes.c_int32()
-    nn = lib.orc_tree_build(d, leaf_size, _fp(p), _up(i), n,
-                            nodes.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h))
+    nn = lib.orc_tree_build_rule(d, leaf_size, SPLIT_RULES[split], _fp(p), _up(i), n,
+                                 nodes.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h))
     return p, i, nodes[:nn].copy(), h.value
 
 

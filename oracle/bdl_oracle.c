@@ -5,7 +5,8 @@
  * (Yesantharao, Wang, Dhulipala, Shun).  Each function cites the passage it
  * follows.  It shares no code, header or table with the GPU library; the
  * test suite, the smoke check and the benchmark's CPU-baseline leg are its
- * only users.  Build with -O2 -ffp-contract=off and without fast-math.
+ * only users.  Build with -O3 -ffp-contract=off and without fast-math
+ * (-fopenmp for the all-cores k-NN baseline).
  *
  * Readings of passages that the paper leaves open are listed at the point
  * where they are used and are marked "reading".
@@ -16,6 +17,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* small helpers                                                             */
@@ -110,6 +114,8 @@ void orc_bruteforce_knn(int dim, const float* pts, const uint32_t* ids, int64_t 
 
 typedef struct {
   int dim, leaf;
+  int rule;          /* ORC_SPLIT_SPATIAL or ORC_SPLIT_OBJECT */
+  float* sortbuf;    /* n coordinates, for the object median */
   float* pts;
   uint32_t* ids;
   float* tmp_pts;
@@ -119,15 +125,30 @@ typedef struct {
   int32_t height;
 } build_ctx;
 
-/* Recursive spatial-median build.  A node is a leaf when it holds at most
- * leaf_size points, when all its points coincide, or at depth ORC_MAX_DEPTH
- * (reading: coarsened leaves of Section V-D; the depth cap bounds the tree
- * height for inputs with near-coincident points).  Otherwise the split
- * dimension is depth mod d, moved forward to the first dimension with
- * non-zero extent (reading of the dimension rotation in Alg. 1), the split
- * value is the midpoint of the tight extent (Section V-C), and the node's
- * points are partitioned stably into {x < split} then {x >= split}
- * (the partition primitive of Section III-D). */
+static int cmp_f32(const void* a, const void* b) {
+  float x = *(const float*)a, y = *(const float*)b;
+  return (x > y) - (x < y);
+}
+
+/* Recursive build.  A node is a leaf when it holds at most leaf_size
+ * points, when all its points coincide, or at depth ORC_MAX_DEPTH (reading:
+ * coarsened leaves of Section V-D; the depth cap bounds the tree height for
+ * inputs with near-coincident points).  Otherwise the split dimension is
+ * depth mod d, moved forward to the first dimension with non-zero extent
+ * (reading of the dimension rotation in Alg. 1), the split value comes from
+ * one of the two heuristics of Section V-C, and the node's points are
+ * partitioned stably into {x < split} then {x >= split} (the partition
+ * primitive of Section III-D).
+ *  - spatial median: the midpoint of the tight extent in that dimension;
+ *  - object median: the true median of the node's coordinates in that
+ *    dimension, found by sorting them (the paper sorts).  Reading: for
+ *    count points the median is the coordinate of rank floor(count/2)
+ *    (0-based, ascending), so that distinct coordinates split into
+ *    floor(count/2) points below it and the rest at or above it.
+ * Either way, a split that would leave the left side empty (the value equals
+ * the minimum: adjacent floats for the midpoint, or more than half of the
+ * points sharing the minimum for the median) or an overflowing midpoint is
+ * replaced by the maximum, and a zero split is stored as +0 (like boxes). */
 static int32_t build_rec(build_ctx* b, int64_t begin, int64_t count, int depth,
                          uint64_t path, int32_t parent) {
   const int d = b->dim;
@@ -163,9 +184,17 @@ static int32_t build_rec(build_ctx* b, int64_t begin, int64_t count, int depth,
   int c = depth % d;
   while (!(nd->hi[c] > nd->lo[c])) c = (c + 1) % d;
   float mn = nd->lo[c], mx = nd->hi[c];
-  float split = (mn + mx) * 0.5f;
-  /* reading: if rounding puts the midpoint on mn (adjacent floats) or the sum
-   * overflows, split at mx so that neither side is empty */
+  float split;
+  if (b->rule == ORC_SPLIT_OBJECT) {
+    for (int64_t i = 0; i < count; ++i) b->sortbuf[i] = b->pts[(begin + i) * d + c];
+    qsort(b->sortbuf, (size_t)count, sizeof(float), cmp_f32);
+    split = box_val(b->sortbuf[count / 2]);
+  } else {
+    split = (mn + mx) * 0.5f;
+  }
+  /* reading: if the split is not above mn (adjacent floats, or more than
+   * half of the points at the minimum) or the midpoint overflows, split at
+   * mx so that neither side is empty */
   if (!(split > mn) || split > mx) split = mx;
   nd->dim = c;
   nd->split = split;
@@ -242,11 +271,19 @@ static void veb_place(veb_ctx* v, int32_t r, int l) {
 
 int64_t orc_tree_build(int dim, int leaf_size, float* pts, uint32_t* ids, int64_t n,
                        orc_node* nodes_out, int32_t* height_out) {
+  return orc_tree_build_rule(dim, leaf_size, ORC_SPLIT_SPATIAL, pts, ids, n, nodes_out,
+                             height_out);
+}
+
+int64_t orc_tree_build_rule(int dim, int leaf_size, int rule, float* pts, uint32_t* ids,
+                            int64_t n, orc_node* nodes_out, int32_t* height_out) {
   if (height_out) *height_out = 0;
   if (n <= 0) return 0;
   build_ctx b;
   b.dim = dim;
   b.leaf = leaf_size;
+  b.rule = rule;
+  b.sortbuf = rule == ORC_SPLIT_OBJECT ? (float*)xmalloc(sizeof(float) * (size_t)n) : NULL;
   b.pts = pts;
   b.ids = ids;
   b.tmp_pts = (float*)xmalloc(sizeof(float) * (size_t)(n * dim));
@@ -282,6 +319,7 @@ int64_t orc_tree_build(int dim, int leaf_size, float* pts, uint32_t* ids, int64_
   free(b.nodes);
   free(b.tmp_pts);
   free(b.tmp_ids);
+  free(b.sortbuf);
   return nn;
 }
 
@@ -301,6 +339,7 @@ typedef struct {
 
 struct orc_bdl {
   int dim, leaf, X;
+  int rule;                /* split heuristic of every tree */
   uint64_t F;              /* bit i set iff static tree i is non-empty */
   orc_tree lev[ORC_MAXLEV];
   /* buffer region: arrival-order pool of fewer than X points and a kd-tree
@@ -330,7 +369,8 @@ static void tree_make(const orc_bdl* t, orc_tree* tr, float* pts, uint32_t* ids,
   tr->ids = ids;
   if (n > 0) {
     tr->nodes = (orc_node*)xmalloc(sizeof(orc_node) * (size_t)(2 * n - 1));
-    tr->n_nodes = orc_tree_build(t->dim, t->leaf, pts, ids, n, tr->nodes, &tr->height);
+    tr->n_nodes = orc_tree_build_rule(t->dim, t->leaf, t->rule, pts, ids, n, tr->nodes,
+                                      &tr->height);
   }
 }
 
@@ -343,7 +383,15 @@ orc_bdl* orc_create(int dim, int leaf_size, int buffer_size) {
   t->dim = dim;
   t->leaf = leaf_size;
   t->X = buffer_size;
+  t->rule = ORC_SPLIT_SPATIAL;
   return t;
+}
+
+int orc_set_split_rule(orc_bdl* t, int rule) {
+  if (rule != ORC_SPLIT_SPATIAL && rule != ORC_SPLIT_OBJECT) return -1;
+  if (t->F || t->bn) return -1;
+  t->rule = rule;
+  return 0;
 }
 
 void orc_destroy(orc_bdl* t) {
@@ -646,9 +694,36 @@ static void knn_rec(kctx* x, int32_t ni) {
   knn_rec(x, far_);
 }
 
-/* kNN_L (Alg. 5): one k-NN buffer per query, shared by every non-empty tree;
- * trees are visited one after another from the largest to the smallest
- * (Section V-B), then the buffer tree. */
+/* kNN_L (Alg. 5) for one query: one k-NN buffer shared by every non-empty
+ * tree; trees are visited one after another from the largest to the smallest
+ * (Section V-B), then the buffer tree.  Writes the row of k (id, d2). */
+static void knn_one(const orc_bdl* t, const float* qrow, int k, kbuf* kb, orc_counters* cnt,
+                    uint32_t* out_ids, float* out_d2) {
+  const uint64_t pad = mkkey(INFINITY, ORC_TOMB);
+  kb->n = 0;
+  kctx x;
+  x.dim = t->dim;
+  x.q = qrow;
+  x.kb = kb;
+  x.cnt = cnt;
+  for (int i = ORC_MAXLEV - 1; i >= 0; --i) {
+    if (!((t->F >> i) & 1u) || t->lev[i].n_nodes == 0) continue;
+    x.tr = &t->lev[i];
+    knn_rec(&x, 0);
+  }
+  if (t->btree.n_nodes > 0) {
+    x.tr = &t->btree;
+    knn_rec(&x, 0);
+  }
+  kb_compact(kb);
+  for (int j = 0; j < k; ++j) {
+    uint64_t key = j < kb->n ? kb->key[j] : pad;
+    out_ids[j] = key_id(key);
+    out_d2[j] = key_d2(key);
+  }
+}
+
+/* kNN_L (Alg. 5) over a batch of queries, one after another. */
 void orc_knn(orc_bdl* t, const float* q, int64_t nq, int k, uint32_t* out_ids,
              float* out_d2, orc_counters* cnt) {
   orc_counters local = {0, 0};
@@ -656,31 +731,41 @@ void orc_knn(orc_bdl* t, const float* q, int64_t nq, int k, uint32_t* out_ids,
   kbuf kb;
   kb.key = (uint64_t*)xmalloc(sizeof(uint64_t) * (size_t)(2 * k));
   kb.k = k;
-  uint64_t pad = mkkey(INFINITY, ORC_TOMB);
-  for (int64_t qi = 0; qi < nq; ++qi) {
-    kb.n = 0;
-    kctx x;
-    x.dim = t->dim;
-    x.q = q + qi * t->dim;
-    x.kb = &kb;
-    x.cnt = cnt;
-    for (int i = ORC_MAXLEV - 1; i >= 0; --i) {
-      if (!((t->F >> i) & 1u) || t->lev[i].n_nodes == 0) continue;
-      x.tr = &t->lev[i];
-      knn_rec(&x, 0);
-    }
-    if (t->btree.n_nodes > 0) {
-      x.tr = &t->btree;
-      knn_rec(&x, 0);
-    }
-    kb_compact(&kb);
-    for (int j = 0; j < k; ++j) {
-      uint64_t key = j < kb.n ? kb.key[j] : pad;
-      out_ids[qi * k + j] = key_id(key);
-      out_d2[qi * k + j] = key_d2(key);
-    }
-  }
+  for (int64_t qi = 0; qi < nq; ++qi)
+    knn_one(t, q + qi * t->dim, k, &kb, cnt, out_ids + qi * k, out_d2 + qi * k);
   free(kb.key);
+}
+
+/* The same batch with the queries spread over host threads (OpenMP): the
+ * data-parallel k-NN of Section IV-A.3 runs each query's search serially and
+ * parallelizes across queries.  Each thread has its own k-NN buffer and
+ * counters; rows are those of orc_knn.  Returns the number of threads used. */
+int orc_knn_parallel(orc_bdl* t, const float* q, int64_t nq, int k, uint32_t* out_ids,
+                     float* out_d2, orc_counters* cnt) {
+  int used = 1;
+  int64_t nodes = 0, evals = 0;
+#pragma omp parallel reduction(+ : nodes, evals)
+  {
+    orc_counters c = {0, 0};
+    kbuf kb;
+    kb.key = (uint64_t*)xmalloc(sizeof(uint64_t) * (size_t)(2 * k));
+    kb.k = k;
+#ifdef _OPENMP
+#pragma omp single
+    used = omp_get_num_threads();
+#endif
+#pragma omp for schedule(dynamic, 256)
+    for (int64_t qi = 0; qi < nq; ++qi)
+      knn_one(t, q + qi * t->dim, k, &kb, &c, out_ids + qi * k, out_d2 + qi * k);
+    free(kb.key);
+    nodes += c.node_visits;
+    evals += c.dist_evals;
+  }
+  if (cnt) {
+    cnt->node_visits += nodes;
+    cnt->dist_evals += evals;
+  }
+  return used;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -17,9 +17,10 @@
  * Parity status per function (see the comments at each definition):
  *   orc_bruteforce_knn  pinned (scipy kd-tree on float64, exact integer lattice)
  *   orc_tree_*          pinned (Fig. 1 split example, hand-derived
- *                       spatial-median split values of Section V-C, Fig. 3
- *                       vEB example, structural invariants checked outside
- *                       the oracle)
+ *                       spatial- and object-median split values of
+ *                       Section V-C, exact halving by the object median,
+ *                       Fig. 3 vEB example, structural invariants checked
+ *                       outside the oracle)
  *   orc_insert          pinned (Fig. 4 sequence, binary-counter closed form)
  *   orc_erase           pinned (live-set bookkeeping, half-capacity invariant)
  *   orc_knn             pinned (against the brute force definition)
@@ -37,6 +38,9 @@ extern "C" {
 #define ORC_MAX_DEPTH 63
 #define ORC_MAXLEV 48
 #define ORC_TOMB 0xFFFFFFFFu
+/* split heuristics of Section V-C */
+#define ORC_SPLIT_SPATIAL 0 /* midpoint of the node's tight extent */
+#define ORC_SPLIT_OBJECT 1  /* median of the node's coordinates */
 
 /* Node of a static kd-tree, in the tree's vEB order (index 0 = root). */
 typedef struct {
@@ -62,6 +66,10 @@ typedef struct orc_bdl orc_bdl;
 /* --- BDL-tree log structure (Section IV-B) ----------------------------- */
 orc_bdl* orc_create(int dim, int leaf_size, int buffer_size);
 void orc_destroy(orc_bdl* t);
+/* Split heuristic of every tree built from now on (ORC_SPLIT_*); only on an
+ * empty structure.  Returns 0, or -1 if the rule is unknown or the structure
+ * holds points.  The default is the spatial median. */
+int orc_set_split_rule(orc_bdl* t, int rule);
 /* Insert_L (Alg. 3).  Returns 0. */
 int orc_insert(orc_bdl* t, const float* pts, const uint32_t* ids, int64_t n);
 /* Erase_L (Alg. 4).  Returns the number of points erased. */
@@ -70,6 +78,10 @@ int64_t orc_erase(orc_bdl* t, const float* pts, const uint32_t* ids, int64_t n);
  * padded with (ORC_TOMB, +inf). */
 void orc_knn(orc_bdl* t, const float* q, int64_t nq, int k, uint32_t* out_ids,
              float* out_d2, orc_counters* cnt);
+/* The same rows with the queries spread over host threads (OpenMP, for the
+ * all-cores CPU baseline); returns the number of threads used. */
+int orc_knn_parallel(orc_bdl* t, const float* q, int64_t nq, int k, uint32_t* out_ids,
+                     float* out_d2, orc_counters* cnt);
 int64_t orc_size(const orc_bdl* t);
 /* Per-level state: live[i], cap[i] for i < *nlev, buffer live count, the
  * bitmask F and the cumulative rebuild/reinsert counters. */
@@ -90,6 +102,9 @@ int orc_export_buffer_pool(const orc_bdl* t, uint32_t* ids, float* pts, int64_t*
  * node count. */
 int64_t orc_tree_build(int dim, int leaf_size, float* pts, uint32_t* ids, int64_t n,
                        orc_node* nodes_out, int32_t* height_out);
+/* The same with either heuristic of Section V-C (ORC_SPLIT_*). */
+int64_t orc_tree_build_rule(int dim, int leaf_size, int rule, float* pts, uint32_t* ids,
+                            int64_t n, orc_node* nodes_out, int32_t* height_out);
 
 /* --- definition of the result ------------------------------------------- */
 void orc_bruteforce_knn(int dim, const float* pts, const uint32_t* ids, int64_t n,

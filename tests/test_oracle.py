@@ -187,6 +187,76 @@ def test_spatial_median_split_values(case):
     check_tree(p, i, nodes, case["leaf_size"])
 
 
+_OBJECT_CASES = _gold("object_median.json")["cases"]
+
+
+@pytest.mark.parametrize("case", _OBJECT_CASES, ids=[c["name"] for c in _OBJECT_CASES])
+def test_object_median_split_values(case):
+    """Hand-derived object-median splits (Section V-C): the coordinate of rank
+    floor(n/2), the fix-up when that is the minimum, and the dimension rule
+    shared with the spatial median."""
+    pts = np.array(case["points"], np.float32)
+    p, i, nodes, h = oracle.tree_build(pts, np.arange(len(pts)), case["leaf_size"], split="object")
+    for want in case["nodes"]:
+        nd = nodes[_node_at(nodes, want["path"])]
+        assert int(nd["dim"]) == want["dim"], want["path"]
+        assert np.float32(nd["split"]).view(np.uint32) == np.float32(want["split"]).view(np.uint32), \
+            (want["path"], float(nd["split"]), want["split"])
+        as_f32 = lambda rows: sorted(tuple(float(np.float32(v)) for v in r) for r in rows)
+        assert _slot_points(p, nodes, int(nd["left"])) == as_f32(want["left"])
+        assert _slot_points(p, nodes, int(nd["right"])) == as_f32(want["right"])
+    check_tree(p, i, nodes, case["leaf_size"])
+
+
+@pytest.mark.parametrize("d,n,leaf", [(1, 1000, 1), (3, 5000, 16), (7, 3000, 8)])
+def test_object_median_halves_distinct_coordinates(d, n, leaf):
+    """With distinct coordinates the object median puts exactly floor(n/2)
+    points on the left of every split, so the tree is balanced: its height is
+    the one of repeated halving down to the leaf size.  A spatial-median tree
+    of the same clustered points is not."""
+    rng = np.random.default_rng(50 + d)
+    pts = clustered_points(n, d, 60 + d, n_clusters=4)
+    # make every coordinate distinct (a permutation of a fine lattice)
+    for j in range(d):
+        pts[np.argsort(pts[:, j], kind="stable"), j] = np.arange(n, dtype=np.float32) / n
+    p, i, nodes, h = oracle.tree_build(pts, np.arange(n), leaf, split="object")
+    check_tree(p, i, nodes, leaf)
+    internal = nodes[nodes["dim"] >= 0]
+    left_counts = nodes["count"][internal["left"]]
+    assert np.array_equal(left_counts, internal["count"] // 2)
+    assert np.all(nodes["count"][nodes["dim"] < 0] <= leaf)
+    height, m = 1, n
+    while m > leaf:
+        m = m - m // 2
+        height += 1
+    assert h == height
+    _, _, _, hs = oracle.tree_build(pts, np.arange(n), leaf, split="spatial")
+    assert hs >= h
+
+
+def test_object_median_log_structure_matches_bruteforce():
+    """The log structure built with the object median answers k-NN like the
+    definition, through inserts, erases and a half-capacity rebuild."""
+    d, k = 3, 5
+    o = oracle.OracleBDL(d, 4, 16, split="object")
+    rng = np.random.default_rng(70)
+    pts = clustered_points(3000, d, 71, n_clusters=5)
+    ids = rng.permutation(10_000)[:3000].astype(np.uint32)
+    live = np.zeros(3000, bool)
+    for s in range(0, 3000, 500):
+        o.insert(pts[s:s + 500], ids[s:s + 500])
+        live[s:s + 500] = True
+        e = rng.choice(np.nonzero(live)[0], 200, replace=False)
+        assert o.erase(pts[e], ids[e]) == 200
+        live[e] = False
+        q = np.concatenate([pts[rng.choice(3000, 40)], uniform_points(40, d, s)])
+        oi, od = o.knn(q, k)
+        bi, bd = oracle.bruteforce_knn(pts[live], ids[live], q, k)
+        assert np.array_equal(oi, bi) and np.array_equal(od.view(np.uint32), bd.view(np.uint32))
+    with pytest.raises(ValueError):
+        oracle.OracleBDL(d, 4, 16, split="mean")
+
+
 def _tree_inputs():
     rng = np.random.default_rng(11)
     yield "uniform3", uniform_points(5000, 3, 1), 16
@@ -473,3 +543,19 @@ def test_insert_gather_order_fig4():
     o.insert(pts[14:17], ids[14:17])  # tree 2 = tree 0 ++ tree 1 ++ pool[0:4]
     assert o.export_level(2)[0].tolist() == [8, 9, 10, 11, 0, 1, 2, 3, 4, 5, 6, 7, 12, 13, 14, 15]
     assert o.buffer_pool()[0].tolist() == [16]
+
+
+def test_parallel_knn_rows_equal_serial_rows():
+    """The all-cores k-NN (queries spread over host threads) returns the
+    serial oracle's rows and the same work counts."""
+    d, k = 3, 5
+    o = oracle.OracleBDL(d, 16, 64)
+    pts = uniform_points(6000, d, 41)
+    o.insert(pts, np.arange(6000, dtype=np.uint32))
+    q = uniform_points(2000, d, 42)
+    si, sd, sc = o.knn(q, k, counters=True)
+    pi, pd, used, pc = o.knn_parallel(q, k)
+    assert used >= 1
+    assert np.array_equal(si, pi)
+    assert np.array_equal(sd.view(np.uint32), pd.view(np.uint32))
+    assert sc == pc
