@@ -171,7 +171,8 @@ def load_library(path: Optional[str] = None):
     lib.bdl_server_drain.argtypes = [vp]
     lib.bdl_server_destroy.argtypes = [vp]
     lib.bdl_server_destroy.restype = None
-    for name in ("bdl_create", "bdl_insert", "bdl_erase", "bdl_knn", "bdl_clear", "bdl_sync",
+    for name in ("bdl_create", "bdl_insert", "bdl_erase", "bdl_knn",
+                 "bdl_clear", "bdl_sync",
                  "bdl_profile", "bdl_level_sizes", "bdl_set_param", "bdl_knn_batch",
                  "bdl_set_knn_shapes", "bdl_server_create", "bdl_server_submit",
                  "bdl_server_wait", "bdl_server_poll", "bdl_server_drain",
@@ -284,19 +285,42 @@ class Tree:
                                        ctypes.byref(out)))
         return int(out.value)
 
+    def _out(self, x, nq: int, k: int, dtype, name: str):
+        """A caller-supplied output must be a contiguous [nq, k] tensor of
+        the right dtype on this tree's device; a new one is allocated when
+        x is None."""
+        torch = _torch()
+        if x is None:
+            return torch.empty((nq, k), dtype=dtype, device=self.device)
+        if not isinstance(x, torch.Tensor) or x.dtype != dtype or tuple(x.shape) != (nq, k) \
+                or x.device != self.device or not x.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape "
+                             f"[{nq}, {k}] on {self.device}")
+        return x
+
+    def _keep_on_stream(self, *tensors) -> None:
+        """The library reads and writes these on the tree's stream after the
+        call returns: keep the caching allocator from reusing them before
+        that stream passes this point."""
+        torch = _torch()
+        if self.stream != torch.cuda.current_stream(self.device):
+            for x in tensors:
+                x.record_stream(self.stream)
+
     def knn(self, q, k: int, out_ids=None, out_d2=None):
         """kNN_L (Alg. 5): (ids int32 [nq, k], squared distances float32 [nq, k])."""
+        return self._knn(self._lib.bdl_knn, q, k, out_ids, out_d2)
+
+    def _knn(self, fn, q, k: int, out_ids, out_d2):
         torch = _torch()
         qq = self._pts(q, "q")
         nq = qq.shape[0]
-        if out_ids is None:
-            out_ids = torch.empty((nq, k), dtype=torch.int32, device=self.device)
-        if out_d2 is None:
-            out_d2 = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+        out_ids = self._out(out_ids, nq, k, torch.int32, "out_ids")
+        out_d2 = self._out(out_d2, nq, k, torch.float32, "out_d2")
         with torch.cuda.device(self.device):
-            _check(self._lib.bdl_knn(self._h, ctypes.c_void_p(qq.data_ptr()), nq, int(k),
-                                     ctypes.c_void_p(out_ids.data_ptr()),
-                                     ctypes.c_void_p(out_d2.data_ptr())))
+            _check(fn(self._h, ctypes.c_void_p(qq.data_ptr()), nq, int(k),
+                      ctypes.c_void_p(out_ids.data_ptr()), ctypes.c_void_p(out_d2.data_ptr())))
+            self._keep_on_stream(qq, out_ids, out_d2)
         return out_ids, out_d2
 
     def knn_batch(self, requests, outputs=None):
@@ -309,17 +333,15 @@ class Tree:
         for i, (q, k) in enumerate(requests):
             qq = self._pts(q, "q")
             nq = qq.shape[0]
-            if outputs is not None:
-                oi, od = outputs[i]
-            else:
-                oi = torch.empty((nq, k), dtype=torch.int32, device=self.device)
-                od = torch.empty((nq, k), dtype=torch.float32, device=self.device)
-            keep.append(qq)
+            oi, od = outputs[i] if outputs is not None else (None, None)
+            oi = self._out(oi, nq, k, torch.int32, f"outputs[{i}] ids")
+            od = self._out(od, nq, k, torch.float32, f"outputs[{i}] d2")
+            keep += [qq, oi, od]
             outs.append((oi, od))
             reqs[i] = KnnRequest(qq.data_ptr(), nq, int(k), 0, oi.data_ptr(), od.data_ptr())
         with torch.cuda.device(self.device):
             _check(self._lib.bdl_knn_batch(self._h, reqs, len(requests)))
-        self._keep = keep  # queries stay alive until the stream passes them
+            self._keep_on_stream(*keep)
         return outs
 
     def sync(self) -> None:
