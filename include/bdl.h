@@ -108,6 +108,19 @@ int bdl_erase(bdl_tree* t, const float* pts, const uint32_t* ids, int64_t n,
 int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_ids,
             float* out_d2);
 
+/* kNN_L without device allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Arguments, results, ordering and errors are those of
+ * bdl_knn; the call is asynchronous.  The scratch it needs (the Hilbert-curve
+ * ordering of the queries) is a static device array of about 17.8 MB that
+ * each GPU holds until the process ends, shared by every tree on that GPU:
+ * calls on one GPU whose work overlaps in time (different streams, or
+ * different host threads) race on it, so callers must order them.
+ * BDL_EINVAL for nq > 1048576 (the array's capacity), BDL_EHIP if the
+ * runtime could not resolve the array's address on the tree's GPU. */
+int bdl_knn_noalloc(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_ids,
+                    float* out_d2);
+
 /* Tuning parameters (bdl_set_param).  They change speed, never results. */
 #define BDL_PARAM_KNN_KERNEL 1 /* 0: one lane per query; 1: one wavefront per
                                   64 neighbouring queries; 3: one wavefront

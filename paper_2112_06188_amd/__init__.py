@@ -33,7 +33,7 @@ EXPORTS = [
     "bdl_debug_export_buffer", "bdl_last_error", "bdl_profile", "bdl_level_sizes",
     "bdl_set_param", "bdl_knn_batch", "bdl_set_knn_shapes",
     "bdl_server_create", "bdl_server_submit", "bdl_server_wait", "bdl_server_poll",
-    "bdl_server_drain", "bdl_server_destroy",
+    "bdl_server_drain", "bdl_server_destroy", "bdl_knn_noalloc",
 ]
 REQ_KNN, REQ_INSERT, REQ_ERASE = 0, 1, 2
 SERVE_FIFO, SERVE_BATCHED = 0, 1
@@ -146,6 +146,7 @@ def load_library(path: Optional[str] = None):
     lib.bdl_insert.argtypes = [vp, vp, vp, i64]
     lib.bdl_erase.argtypes = [vp, vp, vp, i64, i64p]
     lib.bdl_knn.argtypes = [vp, vp, i64, i32, vp, vp]
+    lib.bdl_knn_noalloc.argtypes = [vp, vp, i64, i32, vp, vp]
     lib.bdl_sync.argtypes = [vp]
     lib.bdl_clear.argtypes = [vp]
     lib.bdl_set_param.argtypes = [vp, i32, i64]
@@ -171,7 +172,7 @@ def load_library(path: Optional[str] = None):
     lib.bdl_server_drain.argtypes = [vp]
     lib.bdl_server_destroy.argtypes = [vp]
     lib.bdl_server_destroy.restype = None
-    for name in ("bdl_create", "bdl_insert", "bdl_erase", "bdl_knn",
+    for name in ("bdl_create", "bdl_insert", "bdl_erase", "bdl_knn", "bdl_knn_noalloc",
                  "bdl_clear", "bdl_sync",
                  "bdl_profile", "bdl_level_sizes", "bdl_set_param", "bdl_knn_batch",
                  "bdl_set_knn_shapes", "bdl_server_create", "bdl_server_submit",
@@ -310,6 +311,11 @@ class Tree:
     def knn(self, q, k: int, out_ids=None, out_d2=None):
         """kNN_L (Alg. 5): (ids int32 [nq, k], squared distances float32 [nq, k])."""
         return self._knn(self._lib.bdl_knn, q, k, out_ids, out_d2)
+
+    def knn_noalloc(self, q, k: int, out_ids=None, out_d2=None):
+        """kNN_L through bdl_knn_noalloc (no device allocation by the library;
+        at most 1048576 queries per call)."""
+        return self._knn(self._lib.bdl_knn_noalloc, q, k, out_ids, out_d2)
 
     def _knn(self, fn, q, k: int, out_ids, out_d2):
         torch = _torch()

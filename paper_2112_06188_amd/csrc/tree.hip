@@ -8,6 +8,7 @@
 // tree's stream.
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <unordered_map>
@@ -32,6 +33,39 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+// Device scratch of bdl_knn_noalloc: the Hilbert-ordering keys and values
+// (two ping-pong pairs), the radix sort's partial counts and the query box,
+// for at most kNoAllocMaxQueries queries.  Each GPU the library runs on
+// holds its own copy until the process ends.  In host code the array's name
+// is only a stand-in: host code uses the address that hipGetSymbolAddress
+// returns for the current device (scratch_on), never the name itself.
+constexpr uint64_t kNoAllocMaxQueries = 1ull << 20;
+constexpr uint64_t kNoAllocTmpWords = 1ull << 18;
+constexpr uint64_t kNoAllocWords = 4 * kNoAllocMaxQueries + kNoAllocTmpWords + 2 * kMaxDim;
+static __device__ __align__(256) uint32_t scratch[kNoAllocWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_tried[kMaxDevices] = {};
+
+// Address of `scratch` on device `dev`, which must be current; resolved once
+// per device.  Null if the runtime cannot resolve it.
+uint32_t* scratch_on(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_tried[dev]) {
+    g_scratch_tried[dev] = true;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p) {
+      g_scratch_ptr[dev] = (uint32_t*)p;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  return g_scratch_ptr[dev];
+}
+
 struct LevelState {
   float* rec = nullptr;
   float* nodes = nullptr;
@@ -47,6 +81,8 @@ struct LevelState {
 struct bdl_tree {
   bdl_config cfg;
   hipStream_t s = nullptr;
+  int dev = 0;
+  uint32_t* noalloc_scratch = nullptr;  // this device's `scratch` (bdl_knn_noalloc)
   int d = 0, S = 0, NS = 0;
   uint32_t T = 0;
   uint64_t F = 0;
@@ -767,6 +803,8 @@ int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out) {
   bdl_tree* t = new bdl_tree();
   t->cfg = *cfg;
   t->s = (hipStream_t)stream;
+  t->dev = dev;
+  t->noalloc_scratch = scratch_on(dev);
   t->d = cfg->dim;
   t->S = rec_stride(cfg->dim);
   t->NS = node_stride(cfg->dim);
@@ -1093,6 +1131,52 @@ int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_id
   int rc = launch_knn(L, t->d, k, Q, (uint64_t)nq, order, t->d_views, t->d_misc + 8,
                       t->pt.mark ? t->d_stats : nullptr, t->s);
   t->pt.end(BDL_PH_TRAVERSE);
+  if (rc) return fail(rc, "k-NN launch failed");
+  return 0;
+}
+
+int bdl_knn_noalloc(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_ids,
+                    float* out_d2) {
+  if (!t) return fail(BDL_EINVAL, "null tree");
+  if (k < 1 || k > BDL_MAX_K) return fail(BDL_EINVAL, "k must be in 1..64");
+  if (nq < 0) return fail(BDL_EINVAL, "negative nq");
+  if (nq == 0) return 0;
+  if (!q || !out_ids || !out_d2) return fail(BDL_EINVAL, "null query or output");
+  if ((uint64_t)nq > kNoAllocMaxQueries)
+    return fail(BDL_EINVAL, "bdl_knn_noalloc takes at most 1048576 queries per call");
+  if (!t->noalloc_scratch)
+    return fail(BDL_EHIP, "the device scratch of bdl_knn_noalloc has no address on this GPU");
+  if (radix_tmp_words((uint64_t)nq) > kNoAllocTmpWords)
+    return fail(BDL_EINVAL, "query batch exceeds the no-allocation scratch");
+  bool sort = false;
+  const KnnLaunch L = choose_launch(t, k, (uint64_t)nq, &sort);
+  const uint32_t* order = nullptr;
+  if (sort) {
+    // the same ordering as bdl_knn, in the device's static scratch instead of
+    // the tree's growable scratch; every word it reads is written first
+    uint32_t* base = t->noalloc_scratch;
+    QueryScratch qs;
+    qs.cap = (uint64_t)nq;
+    qs.keys[0] = base;
+    qs.keys[1] = base + kNoAllocMaxQueries;
+    qs.vals[0] = base + 2 * kNoAllocMaxQueries;
+    qs.vals[1] = base + 3 * kNoAllocMaxQueries;
+    qs.tmp = base + 4 * kNoAllocMaxQueries;
+    qs.box = base + 4 * kNoAllocMaxQueries + kNoAllocTmpWords;
+    order = spatial_order(t->d, q, nullptr, (uint64_t)nq, (uint64_t)nq, qs, t->s);
+  }
+  KnnQueries Q;
+  std::memset(&Q, 0, sizeof(Q));
+  Q.q = q;
+  Q.nq = (uint64_t)nq;
+  Q.one.q = q;
+  Q.one.out_ids = out_ids;
+  Q.one.out_d2 = out_d2;
+  Q.one.qoff = 0;
+  Q.one.nq = (uint32_t)nq;
+  Q.one.k = k;
+  int rc = launch_knn(L, t->d, k, Q, (uint64_t)nq, order, t->d_views, t->d_misc + 8, nullptr,
+                      t->s);
   if (rc) return fail(rc, "k-NN launch failed");
   return 0;
 }
