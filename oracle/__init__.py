@@ -23,6 +23,8 @@ _lib = None
 TOMB = 0xFFFFFFFF
 MAXD = 16
 SPLIT_RULES = {"spatial": 0, "object": 1}  # the two heuristics of Section V-C
+# the BDL-tree and the two baselines of Section III-B (B1, B2)
+MODES = {"bdl": 0, "rebuild_all": 1, "no_rebuild": 2}
 MAX_DEPTH = 63
 
 NODE_DTYPE = np.dtype([
@@ -82,6 +84,8 @@ def _load():
                                        c_i64, c_i64]
         lib.orc_export_level.argtypes = [c_v, ctypes.c_int32, c_u, c_f, c_v, c_i64, c_i64]
         lib.orc_export_buffer_pool.argtypes = [c_v, c_u, c_f, c_i64]
+        lib.orc_set_mode.restype = ctypes.c_int
+        lib.orc_set_mode.argtypes = [c_v, ctypes.c_int]
         lib.orc_set_split_rule.restype = ctypes.c_int
         lib.orc_set_split_rule.argtypes = [c_v, ctypes.c_int]
         lib.orc_tree_build_rule.restype = ctypes.c_int64
@@ -126,7 +130,7 @@ class OracleBDL:
     """The log structure of static kd-trees, serial."""
 
     def __init__(self, dim: int, leaf_size: int = 16, buffer_size: int = 1024,
-                 split: str = "spatial"):
+                 split: str = "spatial", mode: str = "bdl"):
         self._lib = _load()
         self.dim = dim
         self.leaf_size = leaf_size
@@ -136,6 +140,8 @@ class OracleBDL:
             raise ValueError("invalid oracle configuration")
         if split not in SPLIT_RULES or self._lib.orc_set_split_rule(self._h, SPLIT_RULES[split]):
             raise ValueError(f"unknown split rule {split!r}")
+        if mode not in MODES or self._lib.orc_set_mode(self._h, MODES[mode]):
+            raise ValueError(f"unknown structure {mode!r}")
 
     def close(self) -> None:
         if self._h:

@@ -340,6 +340,7 @@ typedef struct {
 struct orc_bdl {
   int dim, leaf, X;
   int rule;                /* split heuristic of every tree */
+  int mode;                /* ORC_MODE_*: the BDL-tree or a baseline */
   uint64_t F;              /* bit i set iff static tree i is non-empty */
   orc_tree lev[ORC_MAXLEV];
   /* buffer region: arrival-order pool of fewer than X points and a kd-tree
@@ -384,7 +385,16 @@ orc_bdl* orc_create(int dim, int leaf_size, int buffer_size) {
   t->leaf = leaf_size;
   t->X = buffer_size;
   t->rule = ORC_SPLIT_SPATIAL;
+  t->mode = ORC_MODE_BDL;
   return t;
+}
+
+int orc_set_mode(orc_bdl* t, int mode) {
+  if (mode != ORC_MODE_BDL && mode != ORC_MODE_REBUILD_ALL && mode != ORC_MODE_NO_REBUILD)
+    return -1;
+  if (t->F || t->bn) return -1;
+  t->mode = mode;
+  return 0;
 }
 
 int orc_set_split_rule(orc_bdl* t, int rule) {
@@ -412,6 +422,152 @@ static void rebuild_buffer_tree(orc_bdl* t) {
   tree_make(t, &t->btree, p, ids, t->bn);
 }
 
+/* ------------------------------------------------------------------------ */
+/* The two baselines of Section III-B (B1 and B2 of Section VI): one kd-tree  */
+/* over all live points, kept as static tree 0 (F = 1 while it holds slots);  */
+/* no buffer.                                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Copies of the live points of tree 0 in slot order followed by pts/ids. */
+static int64_t gather_live_plus(const orc_bdl* t, const float* pts, const uint32_t* ids,
+                                int64_t n, float** out_p, uint32_t** out_i) {
+  const int d = t->dim;
+  const orc_tree* tr = &t->lev[0];
+  int64_t tot = n + ((t->F & 1u) ? tr->live : 0);
+  float* p = (float*)xmalloc(sizeof(float) * (size_t)(tot * d));
+  uint32_t* id = (uint32_t*)xmalloc(sizeof(uint32_t) * (size_t)tot);
+  int64_t w = 0;
+  if (t->F & 1u) {
+    for (int64_t s = 0; s < tr->n; ++s) {
+      if (tr->ids[s] == ORC_TOMB) continue;
+      memcpy(p + w * d, tr->pts + s * d, sizeof(float) * d);
+      id[w++] = tr->ids[s];
+    }
+  }
+  if (n > 0) {
+    memcpy(p + w * d, pts, sizeof(float) * (size_t)(n * d));
+    memcpy(id + w, ids, sizeof(uint32_t) * (size_t)n);
+  }
+  *out_p = p;
+  *out_i = id;
+  return tot;
+}
+
+/* B1: the tree is rebuilt after every batch update (Section III-B).  Reading:
+ * the rebuild takes the old tree's live points in slot order followed by the
+ * batch in input order. */
+static void b1_rebuild(orc_bdl* t, const float* pts, const uint32_t* ids, int64_t n) {
+  float* p;
+  uint32_t* id;
+  int64_t tot = gather_live_plus(t, pts, ids, n, &p, &id);
+  if (tot == 0) {
+    free(p);
+    free(id);
+    tree_free(&t->lev[0]);
+    t->F = 0;
+    return;
+  }
+  tree_make(t, &t->lev[0], p, id, tot);
+  t->F = 1;
+  t->rebuilt += tot;
+}
+
+/* B2: the tree keeps the spatial partition of its first build; a batch is
+ * inserted into the existing structure (Section III-B).  Each new point
+ * follows the splits (x[dim] < split goes left) to a leaf, which takes it
+ * after its own points (input order among the new ones); the boxes on its
+ * path grow to contain it, so every box still bounds its subtree.  The slots
+ * are then laid out again, leaves in their order.  Erased points stay as
+ * tombstones (nothing is ever rebuilt). */
+typedef struct {
+  int64_t* cnt;    /* new points per node (leaves only) */
+  int64_t* start;  /* first index into the bucket array per leaf */
+  int64_t* bucket; /* new point indices grouped by leaf, input order */
+  float* np;
+  uint32_t* ni;
+  int64_t w;
+} b2_ctx;
+
+static void b2_layout(const orc_bdl* t, orc_tree* tr, b2_ctx* c, const float* pts,
+                      const uint32_t* ids, int32_t v) {
+  const int d = t->dim;
+  orc_node* nd = &tr->nodes[v];
+  if (nd->dim < 0) {
+    const int64_t b = c->w;
+    for (int64_t s = nd->begin; s < (int64_t)nd->begin + nd->count; ++s) {
+      memcpy(c->np + c->w * d, tr->pts + s * d, sizeof(float) * d);
+      c->ni[c->w++] = tr->ids[s];
+    }
+    for (int64_t k = 0; k < c->cnt[v]; ++k) {
+      const int64_t i = c->bucket[c->start[v] + k];
+      memcpy(c->np + c->w * d, pts + i * d, sizeof(float) * d);
+      c->ni[c->w++] = ids[i];
+    }
+    nd->begin = (int32_t)b;
+    nd->count = (int32_t)(c->w - b);
+    return;
+  }
+  b2_layout(t, tr, c, pts, ids, nd->left);
+  b2_layout(t, tr, c, pts, ids, nd->right);
+  nd->begin = tr->nodes[nd->left].begin;
+  nd->count = tr->nodes[nd->left].count + tr->nodes[nd->right].count;
+}
+
+static void b2_insert(orc_bdl* t, const float* pts, const uint32_t* ids, int64_t n) {
+  const int d = t->dim;
+  if (n <= 0) return;
+  if (!(t->F & 1u)) {
+    b1_rebuild(t, pts, ids, n);  /* the first batch builds the tree */
+    return;
+  }
+  orc_tree* tr = &t->lev[0];
+  int64_t* leaf = (int64_t*)xmalloc(sizeof(int64_t) * (size_t)n);
+  b2_ctx c;
+  c.cnt = (int64_t*)xmalloc(sizeof(int64_t) * (size_t)tr->n_nodes);
+  c.start = (int64_t*)xmalloc(sizeof(int64_t) * (size_t)tr->n_nodes);
+  memset(c.cnt, 0, sizeof(int64_t) * (size_t)tr->n_nodes);
+  for (int64_t i = 0; i < n; ++i) {
+    const float* p = pts + i * d;
+    int32_t v = 0;
+    while (1) {
+      orc_node* nd = &tr->nodes[v];
+      for (int j = 0; j < d; ++j) {
+        float x = box_val(p[j]);
+        if (x < nd->lo[j]) nd->lo[j] = x;
+        if (x > nd->hi[j]) nd->hi[j] = x;
+      }
+      if (nd->dim < 0) break;
+      v = p[nd->dim] < nd->split ? nd->left : nd->right;
+    }
+    leaf[i] = v;
+    c.cnt[v]++;
+  }
+  int64_t run = 0;
+  for (int64_t v = 0; v < tr->n_nodes; ++v) {
+    c.start[v] = run;
+    run += c.cnt[v];
+  }
+  c.bucket = (int64_t*)xmalloc(sizeof(int64_t) * (size_t)n);
+  int64_t* fill = (int64_t*)xmalloc(sizeof(int64_t) * (size_t)tr->n_nodes);
+  memset(fill, 0, sizeof(int64_t) * (size_t)tr->n_nodes);
+  for (int64_t i = 0; i < n; ++i) c.bucket[c.start[leaf[i]] + fill[leaf[i]]++] = i;
+  c.np = (float*)xmalloc(sizeof(float) * (size_t)((tr->n + n) * d));
+  c.ni = (uint32_t*)xmalloc(sizeof(uint32_t) * (size_t)(tr->n + n));
+  c.w = 0;
+  b2_layout(t, tr, &c, pts, ids, 0);
+  free(tr->pts);
+  free(tr->ids);
+  tr->pts = c.np;
+  tr->ids = c.ni;
+  tr->n += n;
+  tr->live += n;
+  free(leaf);
+  free(fill);
+  free(c.cnt);
+  free(c.start);
+  free(c.bucket);
+}
+
 /* Insert_L (Alg. 3 and the text that follows it).
  * Readings of what the paper leaves open:
  *  - the pool is the buffer's points in arrival order followed by P in input
@@ -423,6 +579,14 @@ static void rebuild_buffer_tree(orc_bdl* t) {
  *    fills its nominal capacity 2^j X; the other new trees, highest first, take
  *    the following pool slices of 2^j X points each. */
 int orc_insert(orc_bdl* t, const float* pts, const uint32_t* ids, int64_t n) {
+  if (t->mode == ORC_MODE_REBUILD_ALL) {
+    if (n > 0) b1_rebuild(t, pts, ids, n);
+    return 0;
+  }
+  if (t->mode == ORC_MODE_NO_REBUILD) {
+    b2_insert(t, pts, ids, n);
+    return 0;
+  }
   const int d = t->dim;
   const int64_t X = t->X;
   int64_t pn = t->bn + n;
@@ -534,6 +698,15 @@ static int erase_in_tree(const orc_bdl* t, orc_tree* tr, const float* p, uint32_
 int64_t orc_erase(orc_bdl* t, const float* pts, const uint32_t* ids, int64_t n) {
   const int d = t->dim;
   int64_t erased = 0;
+  if (t->mode != ORC_MODE_BDL) {
+    /* baselines: tombstone in the one tree; B1 then rebuilds from the
+     * survivors (if anything was erased), B2 never does */
+    for (int64_t e = 0; e < n; ++e)
+      if (ids[e] != ORC_TOMB && (t->F & 1u))
+        erased += erase_in_tree(t, &t->lev[0], pts + e * d, ids[e]);
+    if (t->mode == ORC_MODE_REBUILD_ALL && erased > 0) b1_rebuild(t, NULL, NULL, 0);
+    return erased;
+  }
   int buffer_hit = 0;
   for (int64_t e = 0; e < n; ++e) {
     const float* p = pts + e * d;

@@ -21,7 +21,9 @@
  *                       Section V-C, exact halving by the object median,
  *                       Fig. 3 vEB example, structural invariants checked
  *                       outside the oracle)
- *   orc_insert          pinned (Fig. 4 sequence, binary-counter closed form)
+ *   orc_insert          pinned (Fig. 4 sequence, binary-counter closed form;
+ *                       baselines: B1 equals one fresh build, B2 keeps its
+ *                       splits and places points by them)
  *   orc_erase           pinned (live-set bookkeeping, half-capacity invariant)
  *   orc_knn             pinned (against the brute force definition)
  */
@@ -38,6 +40,10 @@ extern "C" {
 #define ORC_MAX_DEPTH 63
 #define ORC_MAXLEV 48
 #define ORC_TOMB 0xFFFFFFFFu
+/* the structure: the BDL-tree, or one of the baselines of Section III-B */
+#define ORC_MODE_BDL 0          /* log structure of static trees + buffer */
+#define ORC_MODE_REBUILD_ALL 1  /* B1: one tree, rebuilt after every update */
+#define ORC_MODE_NO_REBUILD 2   /* B2: one tree, updated in place, never rebuilt */
 /* split heuristics of Section V-C */
 #define ORC_SPLIT_SPATIAL 0 /* midpoint of the node's tight extent */
 #define ORC_SPLIT_OBJECT 1  /* median of the node's coordinates */
@@ -70,6 +76,10 @@ void orc_destroy(orc_bdl* t);
  * empty structure.  Returns 0, or -1 if the rule is unknown or the structure
  * holds points.  The default is the spatial median. */
 int orc_set_split_rule(orc_bdl* t, int rule);
+/* Structure (ORC_MODE_*); only on an empty structure.  Returns 0 or -1.  The
+ * baselines keep one tree as static tree 0 (F = 1 while it holds slots) and
+ * no buffer. */
+int orc_set_mode(orc_bdl* t, int mode);
 /* Insert_L (Alg. 3).  Returns 0. */
 int orc_insert(orc_bdl* t, const float* pts, const uint32_t* ids, int64_t n);
 /* Erase_L (Alg. 4).  Returns the number of points erased. */

@@ -559,3 +559,130 @@ def test_parallel_knn_rows_equal_serial_rows():
     assert np.array_equal(si, pi)
     assert np.array_equal(sd.view(np.uint32), pd.view(np.uint32))
     assert sc == pc
+
+
+# --------------------------------------------------------------------------
+# baselines B1 (rebuild everything) and B2 (keep the partition), Section III-B
+# --------------------------------------------------------------------------
+
+def _single_tree(o):
+    info = o.level_info()
+    assert info["F"] in (0, 1) and info["buf_live"] == 0
+    return o.export_level(0) if info["F"] else None
+
+
+def _side(ids, pts, nodes, child, live_only=False):
+    nd = nodes[child]
+    b, c = int(nd["begin"]), int(nd["count"])
+    return sorted(tuple(float(v) for v in pts[s]) for s in range(b, b + c)
+                  if not (live_only and ids[s] == oracle.TOMB))
+
+
+@pytest.mark.parametrize("mode", ["rebuild_all", "no_rebuild"])
+def test_baselines_fig1(mode):
+    """Fig. 1: the upper tree (B1) is rebuilt around x = 4 after (5,5) and
+    (7,7) arrive; the lower tree (B2) keeps its split at x = 2, puts both new
+    points into the right leaf and grows that leaf's box."""
+    g = _gold("fig1_baselines.json")
+    o = oracle.OracleBDL(2, g["leaf_size"], 4, mode=mode)
+    o.insert(np.array(g["initial"], np.float32), np.array(g["initial_ids"], np.uint32))
+    o.insert(np.array(g["inserted"], np.float32), np.array(g["inserted_ids"], np.uint32))
+    for stage in ("after_insert", "after_erase"):
+        if stage == "after_erase":
+            assert o.erase(np.array(g["erased"], np.float32), np.array(g["erased_ids"], np.uint32)) == 1
+        want = g[mode][stage]
+        ids, pts, nodes = _single_tree(o)
+        root = nodes[0]
+        assert int(root["dim"]) == want["root_dim"]
+        assert np.float32(root["split"]) == np.float32(want["root_split"])
+        assert _side(ids, pts, nodes, int(root["left"])) == sorted(map(tuple, map(lambda r: map(float, r), want["left"])))
+        assert _side(ids, pts, nodes, int(root["right"])) == sorted(map(tuple, map(lambda r: map(float, r), want["right"])))
+        r = nodes[int(root["right"])]
+        if "right_box" in want:
+            assert r["lo"][:2].tolist() == want["right_box"][0] and r["hi"][:2].tolist() == want["right_box"][1]
+        if "root_box" in want:
+            assert root["lo"][:2].tolist() == want["root_box"][0] and root["hi"][:2].tolist() == want["root_box"][1]
+        if want.get("right_is_leaf"):
+            assert int(r["dim"]) == -1
+        if "right_live" in want:
+            assert _side(ids, pts, nodes, int(root["right"]), live_only=True) == \
+                sorted(map(tuple, map(lambda rr: map(float, rr), want["right_live"])))
+
+
+def _check_bounding_partition(ids, pts, nodes):
+    """What B2 keeps: every box bounds the points of its subtree (erased ones
+    included), every point lies on its side of every split above it, and
+    the leaves tile the slots."""
+    covered = np.zeros(len(ids), np.int32)
+    stack = [0]
+    while stack:
+        v = stack.pop()
+        nd = nodes[v]
+        b, c = int(nd["begin"]), int(nd["count"])
+        sub = pts[b:b + c]
+        d = pts.shape[1]
+        assert np.all(sub >= nd["lo"][:d]) and np.all(sub <= nd["hi"][:d])
+        if nd["dim"] < 0:
+            covered[b:b + c] += 1
+            continue
+        l, r = nodes[int(nd["left"])], nodes[int(nd["right"])]
+        assert int(l["begin"]) == b and int(l["count"]) + int(r["count"]) == c
+        assert np.all(pts[b:b + int(l["count"]), int(nd["dim"])] < nd["split"])
+        assert np.all(pts[b + int(l["count"]):b + c, int(nd["dim"])] >= nd["split"])
+        stack += [int(nd["left"]), int(nd["right"])]
+    assert np.all(covered == 1)
+
+
+@pytest.mark.parametrize("mode,seed,d,clustered", [
+    ("rebuild_all", 0, 2, False), ("rebuild_all", 1, 5, True),
+    ("no_rebuild", 2, 2, True), ("no_rebuild", 3, 3, False), ("no_rebuild", 4, 7, True),
+])
+def test_baselines_random_ops(mode, seed, d, clustered):
+    """Both baselines answer k-NN like the definition through random inserts
+    and erases.  B1 is always one fresh build (tight boxes, leaves within the
+    leaf size, nothing erased left in it); B2 never changes a split after its
+    first build, keeps erased points as tombstones, and stays a bounding
+    partition."""
+    rng = np.random.default_rng(seed)
+    leaf = 4
+    o = oracle.OracleBDL(d, leaf, 16, mode=mode)
+    live = {}
+    splits0 = None
+    ops = list(random_op_sequence(seed, d, n_ops=30, max_batch=300, id_capacity=1 << 20,
+                                  clustered=clustered))
+    for op in ops:
+        if op.kind == "insert":
+            o.insert(op.pts, op.ids)
+            for p, i in zip(op.pts, op.ids):
+                live[int(i)] = p
+        elif op.kind == "erase":
+            n0 = o.erase(op.pts, op.ids)
+            hit = 0
+            for p, i in zip(op.pts, op.ids):
+                if int(i) in live and np.array_equal(live[int(i)].view(np.uint32), p.view(np.uint32)):
+                    del live[int(i)]
+                    hit += 1
+            assert n0 == hit
+        else:
+            if op.n == 0:
+                continue
+            li = np.array(sorted(live), np.uint32)
+            lp = np.array([live[int(i)] for i in li], np.float32).reshape(-1, d)
+            oi, od = o.knn(op.pts, op.k)
+            bi, bd = oracle.bruteforce_knn(lp, li, op.pts, op.k)
+            assert np.array_equal(oi, bi) and np.array_equal(od.view(np.uint32), bd.view(np.uint32))
+        assert o.size() == len(live)
+        tr = _single_tree(o)
+        if tr is None:
+            continue
+        ids, pts, nodes = tr
+        if mode == "rebuild_all":
+            assert np.all(ids != oracle.TOMB)
+            check_tree(pts, ids, nodes, leaf)
+        else:
+            _check_bounding_partition(ids, pts, nodes)
+            inner = nodes[nodes["dim"] >= 0][["dim", "split", "left", "right"]]
+            if splits0 is None:
+                splits0 = inner.copy()
+            assert np.array_equal(inner, splits0)
+    assert mode != "no_rebuild" or splits0 is not None
