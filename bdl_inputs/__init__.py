@@ -288,12 +288,46 @@ def _served3d_50m(scale: float = 1.0, seed: int = 0) -> Workload:
                     n_setup=50)
 
 
+def _mixed(scale: float = 1.0, seed: int = 0, d: int = 2, clustered: bool = True) -> Workload:
+    """The mixed-operations experiment of Section VI-D.3: 20 Insert_L batches
+    of 5% of the points each, kNN_L (k = 5) for every live point after every
+    fifth insert, then 15 Erase_L batches of 5% each (random live points, no
+    repeats) with kNN_L for every live point after every fifth erase: seven
+    sections INS0..INS3, DEL0..DEL2.  Points are 10M x scale, clustered
+    (the VisualVar stand-in) or uniform; queries are the live points in
+    ascending id order."""
+    n = int(round(10_000_000 * scale))
+    n -= n % 20
+    pts = clustered_points(n, d, seed) if clustered else uniform_points(n, d, seed)
+    ids = np.arange(n, dtype=np.uint32)
+    b = n // 20
+    ops: List[Op] = []
+    for i in range(20):
+        ops.append(Op("insert", pts[i * b:(i + 1) * b], ids[i * b:(i + 1) * b]))
+        if i % 5 == 4:
+            ops.append(Op("knn", pts[:(i + 1) * b], k=5))
+    order = np.random.default_rng(seed + 1).permutation(n)
+    alive = np.ones(n, bool)
+    for i in range(15):
+        e = np.sort(order[i * b:(i + 1) * b])
+        alive[e] = False
+        ops.append(Op("erase", pts[e], ids[e]))
+        if i % 5 == 4:
+            ops.append(Op("knn", pts[alive], k=5))
+    kind = "clustered" if clustered else "uniform"
+    return Workload(f"mixed{d}d_10m", d, 16, 1024, n, ops,
+                    f"{d}D {kind} {n} points: 20 inserts of {b}, 15 erases of {b}, "
+                    f"kNN_L k=5 of every live point after every 5 updates")
+
+
 WORKLOADS = {
     "uniform2d_small": _uniform_small,
     "served3d_50m": _served3d_50m,
     "batched5d_20m": _batched5d_20m,
     "uniform3d_10m": _uniform3d_10m,
     "clustered7d_10m": _clustered7d,
+    "mixed2d_10m": lambda scale=1.0, seed=0: _mixed(scale, seed, d=2, clustered=True),
+    "mixed7d_10m": lambda scale=1.0, seed=0: _mixed(scale, seed, d=7, clustered=False),
 }
 
 

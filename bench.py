@@ -13,13 +13,17 @@ call (bdl_knn per batch) and once in the batched form (bdl_knn_batch over
 the kNN batches between two inserts, replayed hipGraphs), both with the
 autotuned launch shapes; results must be identical.
 
+--form mixed: the mixed-operations experiment of Section VI-D.3 (20 inserts
+and 15 erases of 5% each, kNN_L over every live point after every fifth)
+on the BDL-tree and the baselines B1 (rebuild all) and B2 (no rebuild).
+
 --form served: a 50M-point 3D clustered resident set and 2000 requests
 (70% kNN_L k=5, 20% Insert_L, 10% Erase_L) arriving as a Poisson stream at
 0.5, 0.8 and 0.95 of the FIFO loop's saturation rate, served by the native
 request loop in FIFO mode and with continuous batching; p50/p99 latency and
 throughput of both, and the k-NN results of the two compared.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--form plain|batched|served]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--form plain|batched|served|mixed]
 """
 from __future__ import annotations
 
@@ -38,7 +42,10 @@ if ROOT not in sys.path:
 
 METRIC = "kNN queries/s + update pts/s, 10M 3D pts k=5; p50/p99 latency under mixed load"
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3
+# FP32 vector FMA rate without packed-FP32 instructions (256 CUs x 2.4 GHz x
+# 128 flops per CU per clock); the library is built with packed FP32 off, so
+# this is the rate its kernels can reach (157.3 TFLOP/s needs packed FP32)
+FP32_PEAK_TFLOPS = 78.6
 # HBM traffic of the traversal kernel measured with rocprofv3 counters
 # (FETCH_SIZE, WRITE_SIZE) and the sources it was measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "knn_traversal_traffic.json")
@@ -70,6 +77,37 @@ def measured_traffic():
 
 def _pct(xs, p):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), p)) if xs else None
+
+
+def erase_route_leg(torch, bdl, tree, inserts, erases, stream):
+    """The step's erases located through the id map and, as Erase_S with
+    per-tree Bloom filters (Section V-A), by routing each point down the
+    trees; the routed time includes building the filters (lazily, at the
+    first erase after the trees changed).  Untimed inserts before each."""
+    out = {}
+    counts = {}
+    n_er = sum(p.shape[0] for p, _ in erases)
+    for name, route in (("map", 0), ("routed", 1)):
+        tree.set_param(bdl.PARAM_ERASE_ROUTE, route)
+        ms = []
+        for rep in range(2):
+            tree.clear()
+            for p, i in inserts:
+                tree.insert(p, i)
+            tree.sync()
+            got = []
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for p, i in erases:
+                got.append(tree.erase(p, i))
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        counts[name] = got
+        out[name] = {"ms": ms[-1], "pts_per_s": n_er / (ms[-1] * 1e-3)}
+    tree.set_param(bdl.PARAM_ERASE_ROUTE, 0)
+    out["same_counts"] = counts["map"] == counts["routed"]
+    return out
 
 
 def gpu_bench(args):
@@ -152,12 +190,18 @@ def gpu_bench(args):
     prof = tree.profile()
     elapsed = t1 - t0
     ms_step = elapsed * 1e3 / args.steps
+    route_leg = erase_route_leg(torch, bdl, tree, inserts, erases, stream) if args.extra else None
 
-    # full-size property check: every query is a live point, so its own id is
-    # its nearest neighbour at squared distance 0 (no duplicate coordinates)
+    # full-size property check: every query is a live point (queries in
+    # ascending id order), so each row starts at squared distance 0 with its
+    # own id, or with a smaller id at the same coordinates
     qids = dv(np.nonzero(np.isin(np.arange(w.id_capacity), np.asarray(
         [op.ids for op in w.ops if op.kind == "erase"][0]), invert=True))[0].astype(np.uint32))
-    self_ok = bool(torch.equal(out_ids[:, 0], qids)) and bool((out_d2[:, 0] == 0).all())
+    first = out_ids[:, 0].to(torch.int64) & 0xFFFFFFFF
+    own = qids.to(torch.int64) & 0xFFFFFFFF
+    self_ok = bool((out_d2[:, 0] == 0).all()) and bool((first <= own).all())
+    self_exact = float((first == own).to(torch.float32).mean())
+    counters = tree.counters()
 
     info = tree.level_info()
     sizes = tree.level_sizes()
@@ -174,6 +218,14 @@ def gpu_bench(args):
     work = prof["knn_work"]
     valu_flops = float(work["points"] * 3 * w.dim + work["nodes"] * 5 * w.dim) / max(1, args.steps)
     ins_ms = float(np.sum(lat["insert"])) / args.steps
+    # compulsory HBM bytes of the step's Insert_L calls: every batch read once,
+    # every rebuilt point gathered (read) and written to its tree once, and the
+    # rebuilt trees' nodes written once (node count estimated from the final
+    # trees' nodes per slot)
+    rebuilt = counters["rebuilt"]
+    nodes_per_slot = (int(sizes["nodes"].sum()) / max(1, int(sizes["slots"].sum())))
+    ins_bytes = n_ins * 4 * (w.dim + 1) + rebuilt * 2 * 4 * (w.dim + 1) + \
+        int(rebuilt * nodes_per_slot) * NS * 4
     er_ms = float(np.sum(lat["erase"])) / args.steps
     knn_ms = float(np.sum(lat["knn"])) / args.steps
     res = {
@@ -196,7 +248,8 @@ def gpu_bench(args):
         "knn_queries_per_s": nq / (knn_ms * 1e-3),
         "insert_pts_per_s": n_ins / (ins_ms * 1e-3),
         "erase_pts_per_s": n_er / (er_ms * 1e-3),
-        "latency_ms": {kind: {"p50": _pct(v, 50), "p99": _pct(v, 99), "n": len(v)}
+        "erase_route": route_leg,
+        "sequential_call_latency_ms": {kind: {"p50": _pct(v, 50), "p99": _pct(v, 99), "n": len(v)}
                        for kind, v in lat.items()},
         "phase_ms_per_step": {kname: v["ms"] / args.steps for kname, v in prof.items()
                               if kname != "knn_work"},
@@ -204,6 +257,13 @@ def gpu_bench(args):
         "final_levels": [i for i in range(64) if (info["F"] >> i) & 1],
         "buffer_points": info["buf_live"],
         "self_match_all_queries": self_ok,
+        "self_match_own_id_fraction": self_exact,
+        "insert_roofline": {"bound": "hbm", "compulsory_bytes_per_step": ins_bytes,
+                            "rebuilt_points_per_step": rebuilt,
+                            "insert_ms_per_step": ins_ms,
+                            "achieved": ins_bytes / (ins_ms * 1e-3) / 1e9,
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": ins_bytes / (ins_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "roofline": {"kernel": ("k_knn" if args.knn_kernel == 0 else "k_knn_wave")
                      + " (kNN_L traversal)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -392,7 +452,7 @@ def batched_bench(args):
     }
 
 
-def served_bench(args):
+def served_bench(args, scale=None, lambdas=(0.5, 0.8, 0.95)):
     """FIFO loop vs continuous batching on one Poisson request stream."""
     import torch
 
@@ -401,7 +461,7 @@ def served_bench(args):
 
     torch.cuda.set_device(0)
     t_gen = time.perf_counter()
-    w = workload("served3d_50m", scale=args.scale)
+    w = workload("served3d_50m", scale=args.scale if scale is None else scale)
     t_gen = time.perf_counter() - t_gen
     setup = [(_dv(torch, op.pts), _dv(torch, op.ids)) for op in w.ops[:w.n_setup]]
     reqs = w.ops[w.n_setup:]
@@ -473,14 +533,14 @@ def served_bench(args):
     del comps_fifo, comps_bat
     out["saturation"] = {"fifo": sat_fifo, "batched": sat_bat}
     rate = sat_fifo["requests_per_s"]
-    for lam in (0.5, 0.8, 0.95):
+    for lam in lambdas:
         row = {}
         for name, mode in (("fifo", bdl.SERVE_FIFO), ("batched", bdl.SERVE_BATCHED)):
             print(f"served: lambda {lam} {name}", file=sys.stderr, flush=True)
             row[name], _ = run(mode, lam * rate)
         out[f"lambda_{lam}"] = row
     tree.close()
-    hi = out["lambda_0.95"]
+    hi = out[f"lambda_{lambdas[-1]}"]
     return {
         "metric": "served form: request throughput and p50/p99 latency under a Poisson "
                   "stream (3D clustered, 50M resident, 70/20/10 kNN/insert/erase)",
@@ -495,7 +555,7 @@ def served_bench(args):
                    "staging_budget_bytes": budget},
         "saturation_speedup_batched_over_fifo":
             sat_bat["requests_per_s"] / sat_fifo["requests_per_s"],
-        "p99_ratio_fifo_over_batched_at_0.95": hi["fifo"]["latency_ms"]["p99"] /
+        f"p99_ratio_fifo_over_batched_at_{lambdas[-1]}": hi["fifo"]["latency_ms"]["p99"] /
             hi["batched"]["latency_ms"]["p99"],
         "results_identical_fifo_vs_batched": bool(same and erased_same),
         "runs": out,
@@ -503,10 +563,184 @@ def served_bench(args):
     }
 
 
-def cpu_baseline(w, gpu_out, n_sample: int):
-    """The oracle on the host: the full update sequence, then kNN_L on a
-    sample of the queries; throughput in the benchmark's unit (the kNN time
-    is scaled from the sample to all queries)."""
+def mixed_bench(args, name=None, scale=None):
+    """The mixed-operations experiment of Section VI-D.3 on the BDL-tree and
+    on the two baselines of Section III-B (B1 rebuilds its one tree after
+    every update, B2 never does): per section (five updates, then kNN_L for
+    every live point) the update and k-NN device times; the three structures
+    must return identical k-NN rows."""
+    import torch
+
+    import paper_2112_06188_amd as bdl
+    from bdl_inputs import workload
+
+    torch.cuda.set_device(0)
+    w = workload(name or args.mixed_workload, scale=args.scale if scale is None else scale)
+    stream = torch.cuda.current_stream()
+    ops = []
+    for op in w.ops:
+        if op.kind == "knn":
+            ops.append(("knn", _dv(torch, op.pts), op.k))
+        else:
+            ops.append((op.kind, _dv(torch, op.pts), _dv(torch, op.ids)))
+    labels = ["INS0", "INS1", "INS2", "INS3", "DEL0", "DEL1", "DEL2"]
+    ref = None
+    out = {}
+    for structure in ("bdl", "rebuild_all", "no_rebuild"):
+        tree = bdl.Tree(w.dim, leaf_size=w.leaf_size, buffer_size=w.buffer_size,
+                        id_capacity=w.id_capacity, structure=structure)
+        evs, results, sec = [], [], 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for kind, x, y in ops:
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            if kind == "insert":
+                tree.insert(x, y)
+            elif kind == "erase":
+                tree.erase(x, y)
+            else:
+                results.append(tree.knn(x, y))
+            b.record(stream)
+            evs.append((kind, sec, a, b))
+            if kind == "knn":
+                sec += 1
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        tree.sync()
+        secs = [{"section": labels[i], "update_ms": 0.0, "knn_ms": 0.0} for i in range(sec)]
+        for kind, i, a, b in evs:
+            secs[i]["knn_ms" if kind == "knn" else "update_ms"] += a.elapsed_time(b)
+        for r in secs:
+            r["total_ms"] = r["update_ms"] + r["knn_ms"]
+        same = None
+        if ref is None:
+            ref = results
+        else:
+            same = all(torch.equal(p[0], q[0]) and torch.equal(p[1].view(torch.int32),
+                                                             q[1].view(torch.int32))
+                       for p, q in zip(ref, results))
+        if ref is not results:
+            del results
+        tree.close()
+        out[structure] = {"sections": secs, "wall_seconds": wall,
+                          "update_ms": sum(r["update_ms"] for r in secs),
+                          "knn_ms": sum(r["knn_ms"] for r in secs),
+                          "total_ms": sum(r["total_ms"] for r in secs),
+                          "knn_rows_equal_to_bdl": same}
+        print(f"mixed: {structure} total {out[structure]['total_ms']:.1f} ms "
+              f"(updates {out[structure]['update_ms']:.1f}, knn {out[structure]['knn_ms']:.1f})",
+              file=sys.stderr, flush=True)
+    best = min(out, key=lambda kk: out[kk]["total_ms"])
+    # sampled rows of the last k-NN pass against brute force over the live set
+    check = None
+    if args.cpu_sample > 0:
+        import oracle
+        q = ops[-1][1].cpu().numpy()
+        sel = np.sort(np.random.default_rng(3).choice(q.shape[0], 16, replace=False))
+        dead = np.concatenate([op.ids for op in w.ops if op.kind == "erase"])
+        live = np.ones(w.id_capacity, bool)
+        live[dead.astype(np.int64)] = False
+        allp = np.concatenate([op.pts for op in w.ops if op.kind == "insert"])
+        oi, od = oracle.bruteforce_knn(allp[live], np.nonzero(live)[0].astype(np.uint32), q[sel], 5)
+        gi = ref[-1][0].cpu().numpy().view(np.uint32)[sel]
+        gd = ref[-1][1].cpu().numpy()[sel]
+        check = {"rows": len(sel), "equal": bool(np.array_equal(gi, oi) and
+                                                 np.array_equal(gd.view(np.uint32), od.view(np.uint32)))}
+    return {
+        "metric": "mixed operations (Section VI-D.3): device time of 20 inserts, 15 erases and "
+                  "7 k-NN passes over every live point, BDL-tree vs baselines B1 and B2",
+        "value": out["bdl"]["total_ms"], "unit": "ms (whole experiment, BDL-tree)",
+        "higher_is_better": False, "n_gpus": 1, "dtype": "f32",
+        "data": f"synthetic ({w.description})",
+        "config": {"workload": w.name, "dim": w.dim, "points": w.id_capacity,
+                   "leaf_size": w.leaf_size, "buffer_size": w.buffer_size},
+        "structures": out, "best_total": best,
+        "speedup_bdl_over_rebuild_all": out["rebuild_all"]["total_ms"] / out["bdl"]["total_ms"],
+        "speedup_bdl_over_no_rebuild": out["no_rebuild"]["total_ms"] / out["bdl"]["total_ms"],
+        "bruteforce_rows": check,
+    }
+
+
+def served_leg(args):
+    """The metric's mixed-load half: the served form on the clustered 3D
+    request stream with a 10M-point resident set (the served workload at
+    scale 0.2: 2000 requests, 70% kNN_L k=5 of 1-65536 queries, 20% Insert_L
+    and 10% Erase_L of 200-200K points), Poisson arrivals at 0.5 and 0.8 of
+    the FIFO loop's saturation rate; p50/p99 latency of the FIFO loop and of
+    continuous batching, whose results must be identical."""
+    r = served_bench(args, scale=args.served_scale, lambdas=(0.5, 0.8))
+    runs = r["runs"]
+    out = {"workload": r["config"]["workload"], "resident_points": r["config"]["resident_points"],
+           "requests": r["config"]["requests"],
+           "results_identical_fifo_vs_batched": r["results_identical_fifo_vs_batched"],
+           "saturation_requests_per_s": {m: runs["saturation"][m]["requests_per_s"]
+                                         for m in ("fifo", "batched")},
+           "saturation_speedup_batched_over_fifo": r["saturation_speedup_batched_over_fifo"]}
+    for lam in (0.5, 0.8):
+        row = runs[f"lambda_{lam}"]
+        out[f"lambda_{lam}"] = {m: {"latency_ms": row[m]["latency_ms"],
+                                    "knn_latency_ms": row[m]["knn_latency_ms"],
+                                    "requests_per_s": row[m]["requests_per_s"]}
+                                for m in ("fifo", "batched")}
+    return out
+
+
+def clustered_leg(args):
+    """The 7D clustered workload (10M points in 100 Gaussian blobs, 100
+    Insert_L of 100K, one Erase_L of 1M, kNN_L k = 10 for every live point):
+    throughput, the traversal's roofline, the self-match property and rows
+    sampled against brute force over the live set."""
+    import oracle
+
+    a = argparse.Namespace(**vars(args))
+    a.workload = "clustered7d_10m"
+    a.scale = 1.0
+    a.steps = args.clustered_steps
+    a.warmup = 1
+    r, w, (q, gi, gd) = gpu_bench(a)
+    ins = [op for op in w.ops if op.kind == "insert"]
+    er = set(int(x) for op in w.ops if op.kind == "erase" for x in op.ids)
+    allp = np.concatenate([op.pts for op in ins])
+    alli = np.concatenate([op.ids for op in ins])
+    live = np.array([int(i) not in er for i in alli])
+    qop = [op for op in w.ops if op.kind == "knn"][0]
+    sel = np.sort(np.random.default_rng(7).choice(qop.n, size=24, replace=False))
+    oi, od = oracle.bruteforce_knn(allp[live], alli[live], qop.pts[sel], qop.k)
+    g_i = gi.cpu().numpy().view(np.uint32)[sel]
+    g_d = gd.cpu().numpy()[sel]
+    keep = ("value", "unit", "ms_per_step", "steps", "config", "knn_queries_per_s",
+            "insert_pts_per_s", "erase_pts_per_s", "phase_ms_per_step", "knn_work_per_query",
+            "final_levels", "buffer_points", "self_match_all_queries",
+            "self_match_own_id_fraction", "insert_roofline")
+    out = {kk: r[kk] for kk in keep}
+    rf = r["roofline"]
+    out["roofline"] = {kk: rf[kk] for kk in ("kernel", "bound", "achieved", "peak", "unit", "frac",
+                                             "algorithmic_bytes_per_launch", "avg_launch_ms")}
+    out["bruteforce_rows"] = {"rows": len(sel), "equal": bool(
+        np.array_equal(g_i, oi) and np.array_equal(g_d.view(np.uint32), od.view(np.uint32)))}
+    return out
+
+
+def host_cpu_model() -> str:
+    """The host CPU's model name (what lscpu reports), from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(w, gpu_out, n_sample: int, n_sample_par: int):
+    """The oracle on the host cores.  The updates (every Insert_L and the
+    Erase_L of the step, at full size) run serially: the oracle's update code
+    is serial.  kNN_L runs (i) serially on a sample of the queries and (ii)
+    with the queries spread over all host threads (OpenMP) on a larger
+    sample; the kNN time is scaled from the sample to all queries.  `value`
+    uses the all-cores kNN time."""
     import oracle
 
     o = oracle.OracleBDL(w.dim, w.leaf_size, w.buffer_size)
@@ -525,30 +759,45 @@ def cpu_baseline(w, gpu_out, n_sample: int):
             n_er += op.n
     qop = [op for op in w.ops if op.kind == "knn"][0]
     nq = qop.n
-    sel = np.random.default_rng(123).choice(nq, size=min(n_sample, nq), replace=False)
-    sel.sort()
+    rng = np.random.default_rng(123)
+    sel = np.sort(rng.choice(nq, size=min(n_sample, nq), replace=False))
     t0 = time.perf_counter()
-    oi, od = o.knn(qop.pts[sel], qop.k)
+    oi, od, cnt = o.knn(qop.pts[sel], qop.k, counters=True)
     t_knn = time.perf_counter() - t0
-    # parity on the sample at full size
+    sel_p = np.sort(rng.choice(nq, size=min(n_sample_par, nq), replace=False))
+    t0 = time.perf_counter()
+    pi, pd, threads, _ = o.knn_parallel(qop.pts[sel_p], qop.k)
+    t_knn_p = time.perf_counter() - t0
+    # parity on both samples at full size
     q, gi, gd = gpu_out
-    g_ids = gi.cpu().numpy().view(np.uint32)[sel]
-    g_d2 = gd.cpu().numpy()[sel]
-    ids_equal = bool(np.array_equal(g_ids, oi))
-    d2_equal = bool(np.array_equal(g_d2.view(np.uint32), od.view(np.uint32)))
-    t_total = t_ins + t_er + t_knn * nq / len(sel)
+    g_ids = gi.cpu().numpy().view(np.uint32)
+    g_d2 = gd.cpu().numpy().view(np.uint32)
+    ids_equal = bool(np.array_equal(g_ids[sel], oi) and np.array_equal(g_ids[sel_p], pi))
+    d2_equal = bool(np.array_equal(g_d2[sel], od.view(np.uint32)) and
+                    np.array_equal(g_d2[sel_p], pd.view(np.uint32)))
+    o.close()
+    t_par = t_ins + t_er + t_knn_p * nq / len(sel_p)
+    t_ser = t_ins + t_er + t_knn * nq / len(sel)
+    unit = "ops/s (inserted + erased points + kNN queries per second)"
     return {
-        "value": (n_ins + n_er + nq) / t_total,
-        "unit": "ops/s (inserted + erased points + kNN queries per second)",
-        "cores": 1,
+        "value": (n_ins + n_er + nq) / t_par,
+        "unit": unit,
+        "cores": threads,
         "kind": "oracle",
-        "sample": (f"serial oracle: all {len(w.ops) - 2} inserts and the erase at full size, "
-                   f"kNN_L on {len(sel)} of {nq} queries (time scaled to all queries)"),
+        "sample": (f"oracle at full size: all {n_ins} inserted points and {n_er} erases run "
+                   f"serially (its update code is serial); kNN_L on {len(sel_p)} of {nq} "
+                   f"queries over {threads} host threads (OpenMP over queries), time scaled "
+                   f"to all queries"),
         "insert_pts_per_s": n_ins / t_ins,
         "erase_pts_per_s": n_er / t_er,
-        "knn_queries_per_s": len(sel) / t_knn,
-        "seconds": t_ins + t_er + t_knn,
-        "host": {"nproc": os.cpu_count(), "cpu": platform.processor() or platform.machine()},
+        "knn_queries_per_s": len(sel_p) / t_knn_p,
+        "serial": {"value": (n_ins + n_er + nq) / t_ser, "unit": unit, "cores": 1,
+                   "knn_queries_per_s": len(sel) / t_knn, "knn_sample": len(sel)},
+        "seconds": t_ins + t_er + t_knn + t_knn_p,
+        "host": {"nproc": os.cpu_count(), "threads_used": threads, "cpu": host_cpu_model(),
+                 "omp_num_threads": os.environ.get("OMP_NUM_THREADS")},
+        "oracle_work_per_query": {"node_visits": cnt["node_visits"] / len(sel),
+                                  "dist_evals": cnt["dist_evals"] / len(sel)},
         "gpu_matches_oracle_on_sample": {"ids": ids_equal, "d2_bitwise": d2_equal},
     }
 
@@ -564,8 +813,19 @@ def main():
                     help="0: one lane per query, 1: one wavefront per 64 queries, "
                          "2: chosen per launch from the query density")
     ap.add_argument("--cpu-sample", type=int, default=200_000,
-                    help="queries the CPU oracle answers for the baseline (0: skip)")
-    ap.add_argument("--form", default="plain", choices=["plain", "batched", "served"])
+                    help="queries the serial CPU oracle answers for the baseline (0: skip)")
+    ap.add_argument("--cpu-sample-par", type=int, default=1_000_000,
+                    help="queries the all-cores CPU oracle answers for the baseline")
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "served", "mixed"])
+    ap.add_argument("--mixed-workload", default="mixed2d_10m",
+                    choices=["mixed2d_10m", "mixed7d_10m"])
+    ap.add_argument("--mixed-scale", type=float, default=0.1,
+                    help="scale of the mixed-operations leg of the plain form (0: skip)")
+    ap.add_argument("--extra", type=int, default=1,
+                    help="1: the plain form also runs the served leg (mixed-load p50/p99) "
+                         "and the 7D clustered workload; 0: the 3D step only")
+    ap.add_argument("--served-scale", type=float, default=0.2)
+    ap.add_argument("--clustered-steps", type=int, default=2)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter scaling)")
     args = ap.parse_args()
@@ -579,11 +839,29 @@ def main():
     if args.form == "served":
         print(json.dumps(served_bench(args)), flush=True)
         return
+    if args.form == "mixed":
+        print(json.dumps(mixed_bench(args)), flush=True)
+        return
     res, w, gpu_out = gpu_bench(args)
     if args.cpu_sample > 0:
-        res["cpu_baseline"] = cpu_baseline(w, gpu_out, args.cpu_sample)
+        res["cpu_baseline"] = cpu_baseline(w, gpu_out, args.cpu_sample, args.cpu_sample_par)
     else:
         res["cpu_baseline"] = None
+    if args.extra:
+        print("bench: 7D clustered workload", file=sys.stderr, flush=True)
+        res["clustered7d_10m"] = clustered_leg(args)
+        print("bench: served leg", file=sys.stderr, flush=True)
+        res["served_mixed_load"] = served_leg(args)
+        if args.mixed_scale > 0:
+            print("bench: mixed-operations leg", file=sys.stderr, flush=True)
+            m = mixed_bench(args, "mixed2d_10m", args.mixed_scale)
+            res["mixed_operations"] = {kk: m[kk] for kk in (
+                "config", "best_total", "speedup_bdl_over_rebuild_all",
+                "speedup_bdl_over_no_rebuild", "bruteforce_rows")}
+            res["mixed_operations"]["total_ms"] = {kk: v["total_ms"]
+                                                   for kk, v in m["structures"].items()}
+            res["mixed_operations"]["knn_rows_equal"] = all(
+                v["knn_rows_equal_to_bdl"] is not False for v in m["structures"].values())
     print(json.dumps(res), flush=True)
 
 

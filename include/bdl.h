@@ -8,8 +8,8 @@
  * (Insert_L, Alg. 3), batch deletion erases from every tree and rebuilds
  * trees that fall below half capacity (Erase_L, Alg. 4), and batched k-NN
  * visits every non-empty tree with one k-NN state per query (kNN_L, Alg. 5).
- * Each tree is built with the spatial median (Section V-C) in van Emde Boas
- * order (BuildvEB, Alg. 1).
+ * Each tree is built with the spatial median (Section V-C; the object median
+ * with BDL_FLAG_OBJECT_MEDIAN) in van Emde Boas order (BuildvEB, Alg. 1).
  *
  * All work runs in HIP kernels on one gfx950 GPU.  Points are float32 of a
  * fixed dimension d (1..16) with caller-chosen uint32 ids.
@@ -50,6 +50,27 @@ extern "C" {
                                     before each insert (costs one sync) */
 #define BDL_FLAG_PROFILE 2u      /* time each phase with HIP events on the
                                     tree's stream (see bdl_profile) */
+#define BDL_FLAG_OBJECT_MEDIAN 4u /* build every tree with the object median
+                                     of Section V-C instead of the spatial
+                                     median: a node splits at its coordinate
+                                     of rank floor(count/2) in the split
+                                     dimension (0-based, ascending; the
+                                     maximum if that equals the minimum), so
+                                     distinct coordinates halve exactly.
+                                     Results of kNN_L are unchanged. */
+/* The two baselines of Section III-B instead of the BDL-tree; both keep one
+ * kd-tree (reported as static tree 0, F = 1 while it holds points) and no
+ * buffer, and exclude each other. */
+#define BDL_FLAG_REBUILD_ALL 8u   /* B1: every insert and every erase that
+                                     removes a point rebuilds the tree over
+                                     the live points (old slot order, then
+                                     the batch) */
+#define BDL_FLAG_NO_REBUILD 16u   /* B2: the first insert builds the tree;
+                                     later inserts follow its splits into
+                                     its leaves (boxes grow to contain the
+                                     new points, leaves keep their points
+                                     first) and erases leave tombstones; no
+                                     split ever changes */
 
 /* Phases timed under BDL_FLAG_PROFILE. */
 #define BDL_PH_GATHER 0    /* Insert_L: gather of the points of new trees */
@@ -80,9 +101,16 @@ int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out);
  * [n] uint32.  Preconditions: coordinates finite, ids < id_capacity and not
  * live (not currently in the tree, not repeated in the batch).  With
  * BDL_FLAG_CHECK_INPUTS a violation of the first two and of "not live" is
- * reported as BDL_EINVAL with the tree unchanged; otherwise violating
- * inputs give undefined results (never out-of-bounds accesses).  Input
- * buffers may be reused once the call returns. */
+ * reported as BDL_EINVAL with the tree unchanged (the check waits for the
+ * stream once); otherwise violating inputs give undefined results (never
+ * out-of-bounds accesses).  Asynchronous: the whole insert, including the
+ * build of every new tree for as many depths as its data needs, is enqueued
+ * on the tree's stream without waiting for it (on a device without
+ * cooperative launch the host waits once per budget of build depths), so
+ * the inputs must stay unchanged until the stream has passed the call.
+ * The build's device-side consistency checks (scratch overflow, a build
+ * that does not end; never expected) are reported by the next bdl_sync or
+ * bdl_erase as BDL_EHIP. */
 int bdl_insert(bdl_tree* t, const float* pts, const uint32_t* ids, int64_t n);
 
 /* Erase_L (Alg. 4).  A pair (pts[i], ids[i]) erases the live point with
@@ -125,10 +153,11 @@ int bdl_knn_noalloc(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t
 #define BDL_PARAM_KNN_KERNEL 1 /* 0: one lane per query; 1: one wavefront per
                                   64 neighbouring queries; 3: one wavefront
                                   per query; 2 (default): 3 for launches of
-                                  at most BDL_PARAM_QUERY_MAX queries, 1 when
-                                  a launch has at least 65536 queries and half
-                                  as many as live points, else 0.  3 needs
-                                  every tree below 2^26 nodes, else 0 runs */
+                                  at most BDL_PARAM_QUERY_MAX queries and for
+                                  every launch when dim >= 5, 1 when a launch
+                                  has at least 65536 queries and half as many
+                                  as live points, else 0.  3 needs every tree
+                                  below 2^26 nodes, else 0 runs */
 #define BDL_PARAM_SORT_MIN 2   /* query batches of at least this many queries
                                   are visited in Hilbert-curve order (default 4096) */
 #define BDL_PARAM_KNN_BLOCK 3  /* k-NN workgroup size: 64, 128 or 256 (default) */
@@ -146,6 +175,17 @@ int bdl_knn_noalloc(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t
                                    3, at least 130 (default and maximum 2048);
                                    a smaller stack walks more subtrees through
                                    parent links instead */
+#define BDL_PARAM_ERASE_ROUTE 8 /* how bdl_erase finds a point.  0 (default):
+                                   through the id map, one lookup per pair.
+                                   1: as Erase_S (Alg. 2) with the Bloom
+                                   filters of Section V-A: every tree whose
+                                   filter may hold the pair is descended
+                                   along its splits to one leaf, which is
+                                   searched; each tree's filter (16 bits per
+                                   point, 4 bits in one 64-bit word) is built
+                                   at the first such erase after the tree
+                                   changed, the buffer's at every such
+                                   erase.  Same results either way. */
 int bdl_set_param(bdl_tree* t, int32_t param, int64_t value);
 
 /* One row of a launch-shape table for kNN_L (bdl_knn and bdl_knn_batch).  A
@@ -215,8 +255,15 @@ int bdl_knn_batch(bdl_tree* t, const bdl_knn_request* reqs, int32_t nreq);
 
 /* Block until all work enqueued on the tree's stream has finished.  Returns
  * BDL_EHIP if a k-NN traversal since the last call met an out-of-range tree
- * index (a corrupt tree; never expected). */
+ * index, or a build reported a device-side error (a corrupt tree or an
+ * undersized scratch; never expected). */
 int bdl_sync(bdl_tree* t);
+
+/* Number of times the library has blocked the calling thread on the tree's
+ * stream since bdl_create (stream and event waits: bdl_erase's readback,
+ * bdl_sync, inspection calls, input checks, scratch growth).  A sequence of
+ * inserts into a tree whose scratch is already large enough adds none. */
+int bdl_host_waits(const bdl_tree* t, int64_t* waits);
 
 void bdl_destroy(bdl_tree* t);
 

@@ -33,11 +33,15 @@ EXPORTS = [
     "bdl_debug_export_buffer", "bdl_last_error", "bdl_profile", "bdl_level_sizes",
     "bdl_set_param", "bdl_knn_batch", "bdl_set_knn_shapes",
     "bdl_server_create", "bdl_server_submit", "bdl_server_wait", "bdl_server_poll",
-    "bdl_server_drain", "bdl_server_destroy", "bdl_knn_noalloc",
+    "bdl_server_drain", "bdl_server_destroy", "bdl_knn_noalloc", "bdl_host_waits",
 ]
 REQ_KNN, REQ_INSERT, REQ_ERASE = 0, 1, 2
 SERVE_FIFO, SERVE_BATCHED = 0, 1
 FLAG_PROFILE = 2
+FLAG_OBJECT_MEDIAN = 4  # split heuristic: object median instead of spatial (Section V-C)
+FLAG_REBUILD_ALL = 8    # baseline B1 of Section III-B instead of the BDL-tree
+FLAG_NO_REBUILD = 16    # baseline B2 of Section III-B instead of the BDL-tree
+STRUCTURES = {"bdl": 0, "rebuild_all": FLAG_REBUILD_ALL, "no_rebuild": FLAG_NO_REBUILD}
 PARAM_KNN_KERNEL = 1
 PARAM_SORT_MIN = 2
 PARAM_KNN_BLOCK = 3
@@ -45,6 +49,7 @@ PARAM_USE_GRAPHS = 4
 PARAM_PERSISTENT = 5
 PARAM_QUERY_MAX = 6
 PARAM_QUERY_STACK = 7
+PARAM_ERASE_ROUTE = 8
 MAX_SHAPES = 256
 KNN_LANE = 0
 KNN_WAVE = 1
@@ -160,6 +165,8 @@ def load_library(path: Optional[str] = None):
     lib.bdl_level_info.argtypes = [vp, ctypes.POINTER(i32), i64p, i64p, i64p,
                                    ctypes.POINTER(ctypes.c_uint64)]
     lib.bdl_counters.argtypes = [vp, i64p, i64p]
+    lib.bdl_host_waits.argtypes = [vp, i64p]
+    lib.bdl_host_waits.restype = ctypes.c_int
     lib.bdl_level_sizes.argtypes = [vp, ctypes.POINTER(i32), i64p, i64p, i64p]
     lib.bdl_debug_export_level.argtypes = [vp, i32, u32p, f32p, vp, i64p, i64p]
     lib.bdl_debug_export_buffer.argtypes = [vp, u32p, f32p, i64p]
@@ -198,6 +205,10 @@ def _torch():
 class Tree:
     """A BDL-tree resident in HBM of one GPU.
 
+    split selects the build heuristic of Section V-C: "spatial" (midpoint of
+    a node's extent, the default) or "object" (median of its coordinates).
+    structure selects the BDL-tree ("bdl", the default) or one of the
+    baselines of Section III-B: "rebuild_all" (B1) or "no_rebuild" (B2).
     Points and queries are CUDA (HIP) float32 tensors of shape [n, dim];
     ids are int32 or uint32 tensors holding the uint32 ids bit for bit.
     All work is ordered on the stream that is current at construction.
@@ -205,7 +216,8 @@ class Tree:
 
     def __init__(self, dim: int, leaf_size: int = 16, buffer_size: int = 1024,
                  id_capacity: int = 1 << 24, mem_budget: int = 0, check_inputs: bool = False,
-                 profile: bool = False, device: Optional[int] = None, stream=None):
+                 profile: bool = False, device: Optional[int] = None, stream=None,
+                 split: str = "spatial", structure: str = "bdl"):
         torch = _torch()
         lib = load_library()
         if not torch.cuda.is_available():
@@ -217,7 +229,12 @@ class Tree:
         self.id_capacity = int(id_capacity)
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-            flags = (FLAG_CHECK_INPUTS if check_inputs else 0) | (FLAG_PROFILE if profile else 0)
+            if split not in ("spatial", "object"):
+                raise ValueError(f"split must be 'spatial' or 'object', not {split!r}")
+            if structure not in STRUCTURES:
+                raise ValueError(f"structure must be one of {sorted(STRUCTURES)}, not {structure!r}")
+            flags = (FLAG_CHECK_INPUTS if check_inputs else 0) | (FLAG_PROFILE if profile else 0) \
+                | (FLAG_OBJECT_MEDIAN if split == "object" else 0) | STRUCTURES[structure]
             cfg = Config(self.dim, self.leaf_size, self.buffer_size, self.id_capacity,
                          int(mem_budget), flags)
             h = ctypes.c_void_p()
@@ -274,6 +291,7 @@ class Tree:
         with _torch().cuda.device(self.device):
             _check(self._lib.bdl_insert(self._h, ctypes.c_void_p(p.data_ptr()),
                                         ctypes.c_void_p(i.data_ptr()), p.shape[0]))
+            self._keep_on_stream(p, i)
 
     def erase(self, pts, ids) -> int:
         """Erase_L (Alg. 4); returns the number of points erased."""
@@ -410,6 +428,12 @@ class Tree:
                                          ctypes.byref(bnodes)))
         n = nlev.value
         return {"slots": slots[:n].copy(), "nodes": nodes[:n].copy(), "buf_nodes": bnodes.value}
+
+    def host_waits(self) -> int:
+        """Times the library has blocked the host on the tree's stream."""
+        w = ctypes.c_int64()
+        _check(self._lib.bdl_host_waits(self._h, ctypes.byref(w)))
+        return int(w.value)
 
     def counters(self) -> Dict:
         rb = ctypes.c_int64()

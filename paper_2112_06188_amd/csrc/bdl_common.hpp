@@ -130,8 +130,14 @@ struct Seg {
   float split;
   uint32_t tile_begin, ntiles, nleft;
   uint32_t child[2];   // index in the next depth's list, or kNone
+  uint32_t sel_key;    // object median: ordered-u32 digits selected so far
+  uint32_t sel_rank;   // object median: rank still sought among matching keys
   uint32_t box[2 * kMaxDim];  // ordered-u32 lo[j] at j, hi[j] at kMaxDim + j
 };
+
+// Split heuristics of Section V-C.
+constexpr int kSplitSpatial = 0;  // midpoint of the node's tight extent
+constexpr int kSplitObject = 1;   // median of the node's coordinates
 
 // A subtree small enough to be finished in LDS by one workgroup.
 struct Fin {
@@ -149,7 +155,11 @@ struct BuildCounters {
   uint32_t err;
   uint32_t fin_next;   // next finisher entry to take
   uint32_t retry;      // the finisher found segments left above the threshold
-  uint32_t pad_;
+  uint32_t par_final;  // parity of the depth list the finisher starts from
+  uint32_t max_height;  // layout: the tallest job's height (vEB key bits)
+  uint32_t job_bits;    // layout: bits of a job index
+  uint32_t sort_sel;    // layout: buffer pair holding the sorted nodes
+  uint32_t deepest;     // global-pass depths this build needed
   uint32_t job_nodes[kMaxJobs];
   uint32_t job_height[kMaxJobs];
   uint32_t job_node_off[kMaxJobs];
@@ -166,12 +176,16 @@ struct PoolSrc {
   uint64_t n;
 };
 
-// One static tree (or the buffer's tree) as seen by the k-NN kernel.
+// One static tree (or the buffer's tree) as seen by the k-NN kernel.  Its
+// node count is filled in on the device from the builds' counts (slot
+// kMaxLevels of that array is the buffer's tree).
 struct LevelView {
   const float* rec;
   const float* nodes;
   uint32_t n_slots;
   uint32_t n_nodes;
+  uint32_t level;  // static tree index, or kMaxLevels for the buffer's tree
+  uint32_t pad_;
 };
 
 constexpr int kMaxViews = kMaxLevels + 1;

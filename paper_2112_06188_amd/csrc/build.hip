@@ -17,6 +17,10 @@
 // a node's point set, and every partition is stable.
 #include "bdl.h"
 #include "build.hpp"
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
+
 #include "primitives.hpp"
 
 namespace bdl {
@@ -42,16 +46,50 @@ __device__ inline uint64_t lanemask_lt() {
 // with non-zero extent, value = midpoint of the tight extent; if rounding
 // puts the midpoint on the lower bound (or the sum overflows), the upper
 // bound is used so that both sides are non-empty.
-__device__ inline void choose_split(const uint32_t* lo, const uint32_t* hi, int d, int depth,
-                                    int* dim_out, float* split_out) {
+__device__ inline int choose_dim(const uint32_t* lo, const uint32_t* hi, int d, int depth) {
   int c = depth % d;
   for (int it = 0; it < d && !(hi[c] > lo[c]); ++it) c = (c + 1 == d) ? 0 : c + 1;
+  return c;
+}
+
+__device__ inline void choose_split(const uint32_t* lo, const uint32_t* hi, int d, int depth,
+                                    int* dim_out, float* split_out) {
+  const int c = choose_dim(lo, hi, d, depth);
   float mn = o2f(lo[c]);
   float mx = o2f(hi[c]);
   float split = (mn + mx) * 0.5f;
   if (!(split > mn) || split > mx) split = mx;
   *dim_out = c;
   *split_out = split;
+}
+
+// Object-median split (Section V-C) from the ordered-u32 key of the
+// coordinate of rank floor(count/2) in dimension c: that coordinate (+0 for
+// a zero), or the upper bound if it equals the lower bound (more than half of
+// the points at the minimum), so that both sides are non-empty.
+__device__ inline float object_split(const uint32_t* lo, const uint32_t* hi, int c,
+                                     uint32_t key) {
+  return key > lo[c] ? o2f(key) : o2f(hi[c]);
+}
+
+// A build counter written by other workgroups earlier in the same launch (the
+// cooperative depth loop): read at the device's coherence point, so that
+// every workgroup sees the same value after a grid barrier.
+__device__ inline uint32_t ld_ctr(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Lanes of the wavefront whose 8-bit digit equals this lane's (one ballot per
+// digit bit); meaningful for valid lanes only.
+__device__ inline uint64_t digit_peers8(uint32_t dig, bool valid) {
+  uint64_t m = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (dig >> b) & 1u;
+    const uint64_t bb = __ballot(valid && bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
 }
 
 __device__ inline void write_emit(uint32_t* emit, int es, uint32_t idx, uint64_t path,
@@ -269,6 +307,8 @@ __global__ void k_reset_counters(BuildCounters* c, JobTable jt, Job* jobs_dev) {
     c->ntiles[0] = c->ntiles[1] = c->ebase[0] = c->ebase[1] = 0;
     c->nfin = c->nemit = c->err = 0;
     c->fin_next = c->retry = 0;
+    c->par_final = 0;
+    c->deepest = 0;
   }
   if (t < kMaxJobs) {
     c->job_nodes[t] = 0;
@@ -424,16 +464,16 @@ constexpr uint32_t kListLds = 4096;  // list entries whose tile starts stay in L
 // segment takes the segment's decision itself (leaf, or split dimension and
 // value from its box); the wavefront of its first tile emits the node and
 // records the decision for the list and scatter kernels.
-__global__ void __launch_bounds__(kPassThreads)
-k_count(Seg* cur, const uint32_t* tile_seg, BuildCounters* c, int par, const Job* jobs,
-        uint32_t* emit, int es, int d, uint32_t leaf, const float* src, uint64_t cap,
-        uint32_t* tile_left) {
-  constexpr int kWaves = kPassThreads / 64;
-  const uint32_t nt = c->ntiles[par];
-  const uint32_t ebase = c->ebase[par];
+// Wavefront wv of nwv takes tiles wv, wv + nwv, ...
+__device__ __forceinline__ void count_tiles(Seg* cur, const uint32_t* tile_seg, BuildCounters* c,
+                                            int par, const Job* jobs, uint32_t* emit, int es,
+                                            int d, uint32_t leaf, const float* src, uint64_t cap,
+                                            uint32_t* tile_left, int rule, uint32_t wv,
+                                            uint32_t nwv) {
+  const uint32_t nt = ld_ctr(&c->ntiles[par]);
+  const uint32_t ebase = ld_ctr(&c->ebase[par]);
   const int lane = __lane_id();
-  const uint32_t nw = gridDim.x * kWaves;
-  for (uint32_t t = blockIdx.x * kWaves + (threadIdx.x >> 6); t < nt; t += nw) {
+  for (uint32_t t = wv; t < nt; t += nwv) {
     const uint32_t s = tile_seg[t];
     Seg& g = cur[s];
     const uint32_t* lo = g.box;
@@ -444,6 +484,7 @@ k_count(Seg* cur, const uint32_t* tile_seg, BuildCounters* c, int par, const Job
     int dim = -1;
     float split = 0.0f;
     if (!isleaf) choose_split(lo, hi, d, (int)g.depth, &dim, &split);
+    if (!isleaf && rule == kSplitObject) split = object_split(lo, hi, dim, g.sel_key);
     if (t == g.tile_begin && lane == 0) {
       const uint32_t eidx = ebase + s;
       write_emit(emit, es, eidx, g.path, g.depth, g.job, g.parent_emit, g.side,
@@ -472,13 +513,144 @@ k_count(Seg* cur, const uint32_t* tile_seg, BuildCounters* c, int par, const Job
   }
 }
 
+__global__ void __launch_bounds__(kPassThreads)
+k_count(Seg* cur, const uint32_t* tile_seg, BuildCounters* c, int par, const Job* jobs,
+        uint32_t* emit, int es, int d, uint32_t leaf, const float* src, uint64_t cap,
+        uint32_t* tile_left, int rule) {
+  constexpr int kWaves = kPassThreads / 64;
+  count_tiles(cur, tile_seg, c, par, jobs, emit, es, d, leaf, src, cap, tile_left, rule,
+              blockIdx.x * kWaves + (threadIdx.x >> 6), gridDim.x * kWaves);
+}
+
+// Object median of the global passes: a radix select per segment over the
+// ordered-u32 keys of its coordinates in the split dimension, four rounds of
+// 8-bit digits from the most significant.  In round r a tile counts, per
+// digit, its keys whose higher digits equal the segment's digits selected so
+// far (all keys in round 0); the pick kernel then finds the digit holding
+// the sought rank (floor(count/2) in round 0) and narrows the rank to it.
+// After four rounds sel_key is the key of that rank.  One wavefront per tile,
+// as in the count; the workgroup's wavefronts merge their counts per segment
+// before the device atomics.
+template <int kWaves>
+__device__ __forceinline__ void sel_hist_tiles(const Seg* cur, const uint32_t* tile_seg,
+                                               const BuildCounters* c, int par, int d,
+                                               uint32_t leaf, const float* src, uint64_t cap,
+                                               uint32_t* hist, int round, uint32_t blk,
+                                               uint32_t nblk) {
+  static_assert(kWaves * 64 >= 256, "one thread per digit in the merge");
+  __shared__ uint32_t h[kWaves][256];
+  __shared__ uint32_t hs[kWaves];
+  const uint32_t nt = ld_ctr(&c->ntiles[par]);
+  const int lane = __lane_id();
+  const int w = threadIdx.x >> 6;
+  const uint64_t below = lanemask_lt();
+  const int shift = 24 - 8 * round;
+  const uint32_t nw = nblk * kWaves;
+  // every wavefront of the workgroup runs the same rounds (barriers inside)
+  for (uint32_t t0 = blk * kWaves; t0 < nt; t0 += nw) {
+    const uint32_t t = t0 + w;
+    for (int i = lane; i < 256; i += 64) h[w][i] = 0u;
+    uint32_t s = kNone;
+    if (t < nt) {
+      s = tile_seg[t];
+      const Seg& g = cur[s];
+      const uint32_t* lo = g.box;
+      const uint32_t* hi = g.box + kMaxDim;
+      bool degenerate = true;
+      for (int j = 0; j < d; ++j) degenerate = degenerate && (lo[j] == hi[j]);
+      if (g.count <= leaf || degenerate || g.depth >= (uint32_t)kMaxDepth) {
+        s = kNone;
+      } else {
+        const int dim = choose_dim(lo, hi, d, (int)g.depth);
+        const uint32_t pref = round == 0 ? 0u : g.sel_key;
+        const uint64_t tstart = (uint64_t)g.begin + (uint64_t)(t - g.tile_begin) * kTile;
+        const uint64_t tend = min((uint64_t)g.begin + g.count, tstart + kTile);
+        const float* x = src + (uint64_t)dim * cap;
+        for (uint64_t i0 = tstart; i0 < tend; i0 += 64) {
+          const uint64_t i = i0 + lane;
+          const bool in = i < tend;
+          const uint32_t key = in ? f2o(x[i]) : 0u;
+          // higher digits equal those selected so far (64-bit shifts: in
+          // round 0 there are none and both sides are 0)
+          const bool match =
+              in && ((uint64_t)key >> (shift + 8)) == ((uint64_t)pref >> (shift + 8));
+          const uint32_t dig = (key >> shift) & 255u;
+          const uint64_t m = digit_peers8(dig, match);
+          if (match && (m & below) == 0) atomicAdd(&h[w][dig], (uint32_t)__popcll(m));
+        }
+      }
+    }
+    if (lane == 0) hs[w] = s;
+    __syncthreads();
+    // thread b owns digit b: each segment among the wavefronts adds its sum once
+    const int b = threadIdx.x;
+    for (int v = 0; v < kWaves && b < 256; ++v) {
+      const uint32_t sv = hs[v];
+      bool first = sv != kNone;
+      for (int u = 0; u < v; ++u) first = first && hs[u] != sv;
+      if (!first) continue;
+      uint32_t sum = 0;
+      for (int u = v; u < kWaves; ++u) sum += hs[u] == sv ? h[u][b] : 0u;
+      if (sum) atomicAdd(&hist[(uint64_t)sv * 256 + b], sum);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kPassThreads)
+k_sel_hist(const Seg* cur, const uint32_t* tile_seg, const BuildCounters* c, int par, int d,
+           uint32_t leaf, const float* src, uint64_t cap, uint32_t* hist, int round) {
+  sel_hist_tiles<kPassThreads / 64>(cur, tile_seg, c, par, d, leaf, src, cap, hist, round,
+                                    blockIdx.x, gridDim.x);
+}
+
+// One wavefront per segment: the digit of round r that holds the sought rank;
+// clears the segment's counts for the next round.
+__device__ __forceinline__ void sel_pick_segs(Seg* cur, const BuildCounters* c, int par,
+                                              uint32_t* hist, int round, uint32_t wv,
+                                              uint32_t nwv) {
+  const uint32_t ns = ld_ctr(&c->nseg[par]);
+  const int lane = __lane_id();
+  const int shift = 24 - 8 * round;
+  for (uint32_t s = wv; s < ns; s += nwv) {
+    Seg& g = cur[s];
+    uint32_t* hr = hist + (uint64_t)s * 256;
+    const uint4 hv = reinterpret_cast<const uint4*>(hr)[lane];
+    reinterpret_cast<uint4*>(hr)[lane] = make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t hb[4] = {hv.x, hv.y, hv.z, hv.w};
+    const uint32_t own = hb[0] + hb[1] + hb[2] + hb[3];
+    const uint32_t incl = wave_incl_scan(own);
+    // a leaf segment counted nothing: no lane holds the rank
+    const uint32_t rank = round == 0 ? g.count / 2u : g.sel_rank;
+    const uint32_t pref = round == 0 ? 0u : g.sel_key;
+    const uint32_t excl = incl - own;
+    if (excl <= rank && rank < incl) {
+      uint32_t cum = excl;
+      int q = 0;
+      while (q < 3 && rank >= cum + hb[q]) cum += hb[q++];
+      g.sel_key = pref | ((uint32_t)(lane * 4 + q) << shift);
+      g.sel_rank = rank - cum;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kPassThreads)
+k_sel_pick(Seg* cur, const BuildCounters* c, int par, uint32_t* hist, int round) {
+  constexpr int kWaves = kPassThreads / 64;
+  sel_pick_segs(cur, c, par, hist, round, blockIdx.x * kWaves + (threadIdx.x >> 6),
+                gridDim.x * kWaves);
+}
+
 // Prefix sum of the tiles' left counts; create the children of every split
 // segment: large ones go to the next depth's list, small ones to the
 // finisher.
-__global__ void __launch_bounds__(1024)
-k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_left,
-           uint32_t* tile_off, Fin* fin, uint32_t T, uint64_t max_seg, uint64_t max_fin, int d,
-           uint32_t* segtb, uint32_t* tile_seg_next, uint64_t max_tiles, uint64_t max_emit) {
+// One workgroup of any multiple of 64 threads up to 1024.
+__device__ __forceinline__ void tilescan_block(Seg* cur, Seg* nxt, BuildCounters* c, int par,
+                                               const uint32_t* tile_left, uint32_t* tile_off,
+                                               Fin* fin, uint32_t T, uint64_t max_seg,
+                                               uint64_t max_fin, int d, uint32_t* segtb,
+                                               uint32_t* tile_seg_next, uint64_t max_tiles,
+                                               uint64_t max_emit) {
   const int d4 = (d + 3) & ~3;
   __shared__ uint32_t wsum[17];
   // list sizes are counted in LDS (this is the only workgroup) and stored once
@@ -486,11 +658,11 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
   // per-job node counts and heights of the next depth
   __shared__ uint32_t s_jn[kMaxJobs], s_jh[kMaxJobs];
   __shared__ uint32_t s_tb[kListLds];
-  const uint32_t nt = c->ntiles[par];
-  const uint32_t ns = c->nseg[par];
+  const uint32_t nt = ld_ctr(&c->ntiles[par]);
+  const uint32_t ns = ld_ctr(&c->nseg[par]);
   if (threadIdx.x == 0) {
     s_nseg = 0;
-    s_nfin = c->nfin;
+    s_nfin = ld_ctr(&c->nfin);
   }
   if (threadIdx.x < kMaxJobs) {
     s_jn[threadIdx.x] = 0;
@@ -588,14 +760,14 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
   if (threadIdx.x == 0) {
     c->nfin = s_nfin;
     uint32_t nn = s_nseg;
-    if (nn > max_seg || c->err) {
+    if (nn > max_seg || ld_ctr(&c->err)) {
       // an overflow was flagged: stop working on these trees
-      c->err |= nn > max_seg ? 8u : 0u;
+      if (nn > max_seg) atomicOr(&c->err, 8u);
       nn = 0;
     }
-    const uint32_t base = c->nemit;
+    const uint32_t base = ld_ctr(&c->nemit);
     if ((uint64_t)base + nn > max_emit) {
-      c->err |= 4u;
+      atomicOr(&c->err, 4u);
       nn = 0;
     }
     c->ebase[par ^ 1] = base;
@@ -624,9 +796,11 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
   }
   const bool over = carry > max_tiles;
   if (threadIdx.x == 0) {
-    if (over) c->err |= 256u;
+    if (over) atomicOr(&c->err, 256u);
     c->nseg[par ^ 1] = over ? 0u : n;
     c->ntiles[par ^ 1] = over ? 0u : carry;
+    // the next depth's list is non-empty: the passes run at least to it
+    if (n) c->deepest = nxt[0].depth + 1u > c->deepest ? nxt[0].depth + 1u : c->deepest;
   }
   if (over || n == 0) return;
   __syncthreads();
@@ -640,6 +814,14 @@ k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_l
     }
     tile_seg_next[t] = lo;
   }
+}
+
+__global__ void __launch_bounds__(1024)
+k_tilescan(Seg* cur, Seg* nxt, BuildCounters* c, int par, const uint32_t* tile_left,
+           uint32_t* tile_off, Fin* fin, uint32_t T, uint64_t max_seg, uint64_t max_fin, int d,
+           uint32_t* segtb, uint32_t* tile_seg_next, uint64_t max_tiles, uint64_t max_emit) {
+  tilescan_block(cur, nxt, c, par, tile_left, tile_off, fin, T, max_seg, max_fin, d, segtb,
+                 tile_seg_next, max_tiles, max_emit);
 }
 
 // Add one bound of a child's box to the device copy.  A side with no point
@@ -680,27 +862,28 @@ __device__ inline void add_child_boxes(Seg* nxt, uint32_t c0, uint32_t c1,
 // (all of which meet at one address) are fewer by the wavefront count.
 constexpr int kScatterThreads = 512;
 
-template <int D>
-__global__ void __launch_bounds__(kScatterThreads)
-__attribute__((amdgpu_waves_per_eu(D <= 3 ? 8 : 1)))  // d <= 3 fits 64 VGPRs without spills
-k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounters* c, int par,
-          const float* __restrict__ src, float* __restrict__ dst, uint64_t cap,
-          const uint32_t* tile_off, const Job* jobs, uint64_t* map, uint32_t idcap) {
-  constexpr int kWaves = kScatterThreads / 64;
+template <int D, int kWaves>
+__device__ __forceinline__ void scatter_tiles(const Seg* cur, const uint32_t* tile_seg, Seg* nxt,
+                                              const BuildCounters* c, int par,
+                                              const float* __restrict__ src,
+                                              float* __restrict__ dst, uint64_t cap,
+                                              const uint32_t* tile_off, const Job* jobs,
+                                              uint64_t* map, uint32_t idcap, uint32_t blk,
+                                              uint32_t nblk) {
   __shared__ uint32_t s_ch[kWaves][2];
   __shared__ uint32_t s_bx[kWaves][4 * D];
-  const uint32_t nt = c->ntiles[par];
+  const uint32_t nt = ld_ctr(&c->ntiles[par]);
   const int lane = __lane_id();
   const int w = threadIdx.x >> 6;
   const uint64_t below = lanemask_lt();
   const uint32_t* sid = soa_ids(src, D, cap);
   uint32_t* did = soa_ids_w(dst, D, cap);
-  const uint32_t nw = gridDim.x * kWaves;
+  const uint32_t nw = nblk * kWaves;
   // this wavefront's slot of the workgroup merge: its last tile's children
   // and boxes (empty until then)
   if (lane < 2) s_ch[w][lane] = kNone;
   if (lane < 4 * D) s_bx[w][lane] = (lane & 1) ? 0u : 0xFFFFFFFFu;
-  for (uint32_t t = blockIdx.x * kWaves + w; t < nt; t += nw) {
+  for (uint32_t t = blk * kWaves + w; t < nt; t += nw) {
     const uint32_t s = tile_seg[t];
     const Seg& g = cur[s];
     const uint64_t gbegin = g.begin;
@@ -820,6 +1003,83 @@ k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounter
   }
 }
 
+template <int D>
+__global__ void __launch_bounds__(kScatterThreads)
+__attribute__((amdgpu_waves_per_eu(D <= 3 ? 8 : 1)))  // d <= 3 fits 64 VGPRs without spills
+k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounters* c, int par,
+          const float* __restrict__ src, float* __restrict__ dst, uint64_t cap,
+          const uint32_t* tile_off, const Job* jobs, uint64_t* map, uint32_t idcap) {
+  scatter_tiles<D, kScatterThreads / 64>(cur, tile_seg, nxt, c, par, src, dst, cap, tile_off,
+                                         jobs, map, idcap, blockIdx.x, gridDim.x);
+}
+
+// Arguments of the depth loop (every buffer of the global passes).
+struct PassArgs {
+  Seg* seg[2];
+  uint32_t* tile_seg[2];
+  uint32_t* segtb[2];
+  float* soa[2];
+  BuildCounters* c;
+  const Job* jobs;
+  uint32_t* emit;
+  uint32_t* tile_left;
+  uint32_t* tile_off;
+  Fin* fin;
+  uint64_t* map;
+  uint32_t* sel_hist;
+  uint64_t cap, max_seg, max_fin, max_tiles, max_emit;
+  uint32_t T, leaf, idcap;
+  int es, d, rule, par0, depth0;
+};
+
+// All remaining depths of the global passes in one cooperative launch: the
+// workgroups run count, list and scatter (and the object median's select
+// rounds) of a depth with a grid-wide barrier between the steps, and stop
+// when the depth's list is empty (every segment went to the finisher or was
+// a leaf), when an error is flagged, or past the depth cap.  The stop test
+// reads the counters at the coherence point after a barrier, so every
+// workgroup takes the same decision.  The parity of the last list is left in
+// par_final for the finisher.
+template <int D>
+__global__ void __launch_bounds__(kScatterThreads) k_passes(PassArgs A) {
+  constexpr int KW = kScatterThreads / 64;
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  const uint32_t wv = blockIdx.x * KW + (threadIdx.x >> 6);
+  const uint32_t nwv = gridDim.x * KW;
+  int par = A.par0;
+  for (int depth = A.depth0; depth <= kMaxDepth + 1; ++depth) {
+    if (ld_ctr(&A.c->nseg[par]) == 0u || ld_ctr(&A.c->err) != 0u) break;
+    if (A.rule == kSplitObject) {
+      for (int r = 0; r < 4; ++r) {
+        sel_hist_tiles<KW>(A.seg[par], A.tile_seg[par], A.c, par, A.d, A.leaf, A.soa[par],
+                           A.cap, A.sel_hist, r, blockIdx.x, gridDim.x);
+        grid.sync();
+        sel_pick_segs(A.seg[par], A.c, par, A.sel_hist, r, wv, nwv);
+        grid.sync();
+      }
+    }
+    count_tiles(A.seg[par], A.tile_seg[par], A.c, par, A.jobs, A.emit, A.es, A.d, A.leaf,
+                A.soa[par], A.cap, A.tile_left, A.rule, wv, nwv);
+    grid.sync();
+    if (blockIdx.x == 0)
+      tilescan_block(A.seg[par], A.seg[par ^ 1], A.c, par, A.tile_left, A.tile_off, A.fin, A.T,
+                     A.max_seg, A.max_fin, A.d, A.segtb[par ^ 1], A.tile_seg[par ^ 1],
+                     A.max_tiles, A.max_emit);
+    grid.sync();
+    scatter_tiles<D, KW>(A.seg[par], A.tile_seg[par], A.seg[par ^ 1], A.c, par, A.soa[par],
+                         A.soa[par ^ 1], A.cap, A.tile_off, A.jobs, A.map, A.idcap, blockIdx.x,
+                         gridDim.x);
+    grid.sync();
+    par ^= 1;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) A.c->par_final = (uint32_t)par;
+}
+
+__global__ void k_set_par_final(BuildCounters* c, int par) {
+  if (threadIdx.x == 0) c->par_final = (uint32_t)par;
+}
+
 // ------------------------------------------------------------------------
 // LDS finisher: one workgroup builds a whole subtree of at most TCAP points
 // ------------------------------------------------------------------------
@@ -833,10 +1093,15 @@ struct Act {
   uint64_t path;
 };
 
-template <int DMAX, int TCAP, int MAXACT, int NT>
+// OBJ selects the object median (Section V-C): after a depth's internal
+// nodes are classified, a radix select over 4-bit digits (eight rounds, LDS
+// counts per node) finds each node's coordinate of rank floor(count/2) in its
+// split dimension, which replaces the spatial split in the node and its
+// emitted record.
+template <int DMAX, int TCAP, int MAXACT, int NT, bool OBJ>
 __global__ void __launch_bounds__(NT)
-k_finish(const Fin* fin, int par_end, const float* soa0, const float* soa1, uint64_t cap,
-         int d, uint32_t leaf, const Job* jobs, uint32_t* emit, int es, BuildCounters* c,
+k_finish(const Fin* fin, const float* soa0, const float* soa1, uint64_t cap, int d,
+         uint32_t leaf, const Job* jobs, uint32_t* emit, int es, BuildCounters* c,
          uint64_t* map, uint32_t idcap, uint64_t max_emit) {
   constexpr int PT = (TCAP + NT - 1) / NT;
   constexpr int MAXCH = 2 * MAXACT;
@@ -851,6 +1116,11 @@ k_finish(const Fin* fin, int par_end, const float* soa0, const float* soa1, uint
   __shared__ uint16_t remap[MAXCH];
   __shared__ uint32_t wsum[17];
   __shared__ uint32_t s_nact, s_base, s_maxdepth, s_fi;
+  // object median, per internal node of the depth: digits selected so far,
+  // rank still sought, box bounds in the split dimension, digit counts
+  constexpr int OA = OBJ ? MAXACT : 1;
+  __shared__ uint32_t o_key[OA], o_rank[OA], o_lo[OA], o_hi[OA];
+  __shared__ uint32_t o_hist[OA][16];
 
   const int tid = threadIdx.x;
   const int lane = __lane_id();
@@ -862,6 +1132,7 @@ k_finish(const Fin* fin, int par_end, const float* soa0, const float* soa1, uint
   // passes and a new launch.
   __shared__ uint32_t s_go;
   if (tid == 0) {
+    const uint32_t par_end = c->par_final & 1u;
     const uint32_t e = c->err;
     const bool stop = e != 0u || c->nseg[par_end] != 0u;
     if (stop && e == 0u && blockIdx.x == 0) c->retry = 1u;
@@ -1040,6 +1311,10 @@ k_finish(const Fin* fin, int par_end, const float* soa0, const float* soa1, uint
           A.split = csplit;
           A.emit = eidx;
           A.path = cpath;
+          if constexpr (OBJ) {
+            o_lo[ai] = cbox[tid][cdim];
+            o_hi[ai] = cbox[tid][DMAX + cdim];
+          }
         }
       }
       root = false;
@@ -1048,6 +1323,44 @@ k_finish(const Fin* fin, int par_end, const float* soa0, const float* soa1, uint
           (s_base == 0xFFFFFFFFu || s_nact > (uint32_t)MAXACT) ? 0u : s_nact;
       if (nact == 0) break;
       ca = na;
+      if constexpr (OBJ) {
+        // ---- object median: radix select of rank floor(count/2) per node ----
+        for (uint32_t a = tid; a < nact; a += NT) {
+          o_key[a] = 0u;
+          o_rank[a] = (uint32_t)act[ca][a].count / 2u;
+        }
+        for (int r = 0; r < 8; ++r) {
+          const int shift = 28 - 4 * r;
+          for (uint32_t e = tid; e < nact * 16u; e += NT) o_hist[e >> 4][e & 15u] = 0u;
+          __syncthreads();
+          for (uint32_t i = tid; i < n; i += NT) {
+            const uint16_t s0 = sidv[cur][i];
+            const uint16_t sx = s0 == kFrozen ? kFrozen : remap[s0];
+            if (sx == kFrozen) continue;
+            const uint32_t key = f2o(xs[act[ca][sx].dim][pos[cur][i]]);
+            // higher digits equal those selected so far (none in round 0)
+            if (((uint64_t)key >> (shift + 4)) == ((uint64_t)o_key[sx] >> (shift + 4)))
+              atomicAdd(&o_hist[sx][(key >> shift) & 15u], 1u);
+          }
+          __syncthreads();
+          for (uint32_t a = tid; a < nact; a += NT) {
+            const uint32_t rank = o_rank[a];
+            uint32_t cum = 0;
+            int g = 0;
+            while (g < 15 && rank >= cum + o_hist[a][g]) cum += o_hist[a][g++];
+            o_key[a] |= (uint32_t)g << shift;
+            o_rank[a] = rank - cum;
+          }
+          __syncthreads();
+        }
+        for (uint32_t a = tid; a < nact; a += NT) {
+          Act& A = act[ca][a];
+          const float sp = o_key[a] > o_lo[a] ? o2f(o_key[a]) : o2f(o_hi[a]);
+          A.split = sp;
+          emit[(uint64_t)A.emit * es + EF_SPLIT] = __float_as_uint(sp);
+        }
+        __syncthreads();
+      }
       // ---- flags and block-wide exclusive scan (blocked positions) ----
       uint32_t fl = 0, cnt = 0;
 #pragma unroll
@@ -1125,17 +1438,23 @@ k_finish(const Fin* fin, int par_end, const float* soa0, const float* soa1, uint
 // layout
 // ------------------------------------------------------------------------
 
-__global__ void k_job_offsets(BuildCounters* c, int njobs) {
+__global__ void k_job_offsets(BuildCounters* c, int njobs, int jobbits) {
   if (threadIdx.x != 0) return;
-  uint32_t run = 0;
+  uint32_t run = 0, h = 0;
   for (int j = 0; j < njobs; ++j) {
     c->job_node_off[j] = run;
     run += c->job_nodes[j];
+    h = c->job_height[j] > h ? c->job_height[j] : h;
   }
+  c->max_height = h;
+  c->job_bits = (uint32_t)jobbits;
 }
 
-__global__ void k_layout_keys(const uint32_t* emit, int es, uint32_t n, const BuildCounters* c,
+// vEB key of every emitted node (its job's height decides the layout); the
+// count comes from the device, so no readback precedes the layout.
+__global__ void k_layout_keys(const uint32_t* emit, int es, const BuildCounters* c,
                               int job_shift, uint64_t* keys, uint32_t* vals) {
+  const uint32_t n = c->nemit;
   for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
     const uint32_t* r = emit + (uint64_t)e * es;
     const uint64_t path = (uint64_t)r[EF_PATH_LO] | ((uint64_t)r[EF_PATH_HI] << 32);
@@ -1147,14 +1466,24 @@ __global__ void k_layout_keys(const uint32_t* emit, int es, uint32_t n, const Bu
   }
 }
 
-__global__ void k_layout_jobkeys(const uint32_t* emit, int es, uint32_t n, const uint32_t* vals,
-                                 uint64_t* keys) {
-  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
-    keys[r] = emit[(uint64_t)vals[r] * es + EF_JOB];
+// After the sort by vEB key: the job of every node, in that order, into the
+// first buffer pair (for a stable sort by job that keeps the vEB order
+// within each job).
+__global__ void k_layout_jobkeys(const uint32_t* emit, int es, const BuildCounters* c,
+                                 uint32_t* vals0, const uint32_t* vals1, uint64_t* keys0) {
+  const uint32_t n = c->nemit;
+  const uint32_t* vin = c->sort_sel ? vals1 : vals0;
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const uint32_t e = vin[r];
+    keys0[r] = emit[(uint64_t)e * es + EF_JOB];
+    vals0[r] = e;
+  }
 }
 
-__global__ void k_layout_rank(const uint32_t* vals, uint32_t n, const uint32_t* emit, int es,
-                              const BuildCounters* c, uint32_t* final_of) {
+__global__ void k_layout_rank(const uint32_t* vals0, const uint32_t* vals1, const uint32_t* emit,
+                              int es, const BuildCounters* c, uint32_t* final_of) {
+  const uint32_t n = c->nemit;
+  const uint32_t* vals = c->sort_sel ? vals1 : vals0;
   for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
     const uint32_t e = vals[r];
     const uint32_t job = emit[(uint64_t)e * es + EF_JOB];
@@ -1166,9 +1495,12 @@ __global__ void k_layout_rank(const uint32_t* vals, uint32_t n, const uint32_t* 
 // order (order[r] is the emitted node of rank r), so the rows a wavefront
 // writes are adjacent.  An internal node's child links are written by its
 // children; the node itself leaves those two words alone.
-__global__ void k_layout_write(const uint32_t* emit, int es, uint32_t n, const uint32_t* order,
+__global__ void k_layout_write(const uint32_t* emit, int es, const BuildCounters* c,
+                               const uint32_t* order0, const uint32_t* order1,
                                const uint32_t* final_of, const Job* jobs, int d, uint32_t* err) {
   const int NS = node_stride(d);
+  const uint32_t n = c->nemit;
+  const uint32_t* order = c->sort_sel ? order1 : order0;
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     const uint32_t e = order[q];
     const uint32_t* r = emit + (uint64_t)e * es;
@@ -1204,6 +1536,29 @@ __global__ void k_layout_write(const uint32_t* emit, int es, uint32_t n, const u
       pn[r[EF_SIDE] ? NF_B : NF_A] = __uint_as_float(f);
     }
   }
+}
+
+// End of a build: publish every job's node count for its tree (slot
+// kMaxLevels is the buffer's tree) and keep any error for the next check on
+// the host (a segment left above the finisher's size counts as one).
+__global__ void k_build_done(BuildCounters* c, const Job* jobs, int njobs, uint32_t* level_nodes,
+                             uint32_t* sticky_err) {
+  const int j = threadIdx.x;
+  if (j < njobs) {
+    const uint32_t lv = jobs[j].level;
+    level_nodes[lv == kBufferLevel ? (uint32_t)kMaxLevels : lv] = c->job_nodes[j];
+  }
+  if (j == 0) {
+    const uint32_t e = c->err | (c->retry ? 1024u : 0u);
+    if (e) atomicOr(sticky_err, e);
+    level_nodes[kMaxLevels + 1] = c->deepest;
+  }
+}
+
+// Node counts of the trees k-NN visits, from the builds' published counts.
+__global__ void k_patch_views(LevelViews* v, const uint32_t* level_nodes) {
+  const int i = threadIdx.x;
+  if (i < v->n) v->v[i].n_nodes = level_nodes[v->v[i].level];
 }
 
 struct U32x64 {
@@ -1258,9 +1613,48 @@ void launch_scatter(int d, unsigned grid, const BuildScratch& sc, int par, uint6
   }
 }
 
-template <int DMAX, int TCAP, int MAXACT, int NT>
-void launch_finish(int par_end, const BuildScratch& sc, int d, uint32_t leaf, uint64_t* map,
-                   uint32_t idcap, hipStream_t s) {
+// Cooperative launch of the depth loop on one resident wave of workgroups.
+template <int D>
+hipError_t launch_passes_d(const PassArgs& A, hipStream_t s) {
+  static const unsigned g = [] {
+    int dev = 0, cus = 0, per = 0, coop = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per, reinterpret_cast<const void*>(&k_passes<D>), kScatterThreads, 0) !=
+            hipSuccess ||
+        !coop || cus <= 0 || per <= 0)
+      return 0u;
+    // one workgroup per compute unit: a grid barrier costs more with more
+    // workgroups, and this launch only finishes the depths left over
+    return (unsigned)cus;
+  }();
+  if (g == 0) return hipErrorNotSupported;
+  PassArgs a = A;
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_passes<D>), dim3(g),
+                                    dim3(kScatterThreads), args, 0, s);
+}
+
+hipError_t launch_passes(int d, const PassArgs& A, hipStream_t s) {
+  switch (d) {
+#define BDL_PASSES_CASE(DD) \
+  case DD:                  \
+    return launch_passes_d<DD>(A, s);
+    BDL_PASSES_CASE(1) BDL_PASSES_CASE(2) BDL_PASSES_CASE(3) BDL_PASSES_CASE(4)
+    BDL_PASSES_CASE(5) BDL_PASSES_CASE(6) BDL_PASSES_CASE(7) BDL_PASSES_CASE(8)
+    BDL_PASSES_CASE(9) BDL_PASSES_CASE(10) BDL_PASSES_CASE(11) BDL_PASSES_CASE(12)
+    BDL_PASSES_CASE(13) BDL_PASSES_CASE(14) BDL_PASSES_CASE(15) BDL_PASSES_CASE(16)
+#undef BDL_PASSES_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <int DMAX, int TCAP, int MAXACT, int NT, bool OBJ>
+void launch_finish(const BuildScratch& sc, int d, uint32_t leaf, uint64_t* map, uint32_t idcap,
+                   hipStream_t s) {
   // one resident wave of workgroups (computed once; every device here is
   // the same kind)
   static const unsigned g = [] {
@@ -1268,15 +1662,28 @@ void launch_finish(int par_end, const BuildScratch& sc, int d, uint32_t leaf, ui
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per, reinterpret_cast<const void*>(&k_finish<DMAX, TCAP, MAXACT, NT>), NT, 0) !=
+            &per, reinterpret_cast<const void*>(&k_finish<DMAX, TCAP, MAXACT, NT, OBJ>), NT, 0) !=
             hipSuccess ||
         cus <= 0 || per <= 0)
       return 512u;
     return (unsigned)(cus * per);
   }();
-  hipLaunchKernelGGL((k_finish<DMAX, TCAP, MAXACT, NT>), dim3(g), dim3(NT), 0, s, sc.fin,
-                     par_end, sc.soa[0], sc.soa[1], sc.cap, d, leaf, sc.jobs, sc.emit,
-                     emit_stride(d), sc.ctr, map, idcap, sc.max_emit);
+  hipLaunchKernelGGL((k_finish<DMAX, TCAP, MAXACT, NT, OBJ>), dim3(g), dim3(NT), 0, s, sc.fin,
+                     sc.soa[0], sc.soa[1], sc.cap, d, leaf, sc.jobs, sc.emit, emit_stride(d),
+                     sc.ctr, map, idcap, sc.max_emit);
+}
+
+void launch_finisher(bool obj, const BuildScratch& sc, int d, uint32_t leaf, uint64_t* map,
+                     uint32_t idcap, hipStream_t s) {
+  if (obj) {
+    if (d <= 3) launch_finish<3, 2304, 144, 768, true>(sc, d, leaf, map, idcap, s);
+    else if (d <= 8) launch_finish<8, 1024, 64, 256, true>(sc, d, leaf, map, idcap, s);
+    else launch_finish<16, 512, 32, 256, true>(sc, d, leaf, map, idcap, s);
+  } else {
+    if (d <= 3) launch_finish<3, 2304, 144, 768, false>(sc, d, leaf, map, idcap, s);
+    else if (d <= 8) launch_finish<8, 1024, 64, 256, false>(sc, d, leaf, map, idcap, s);
+    else launch_finish<16, 512, 32, 256, false>(sc, d, leaf, map, idcap, s);
+  }
 }
 
 }  // namespace
@@ -1351,6 +1758,11 @@ void launch_store_u32(uint32_t* dst, const uint32_t* vals, int n, hipStream_t s)
   hipLaunchKernelGGL(k_store_vals, dim3(1), dim3(64), 0, s, dst, v, n);
 }
 
+void launch_patch_views(LevelViews* views, const uint32_t* level_nodes, hipStream_t s) {
+  static_assert(kMaxViews <= 64, "one lane per view");
+  hipLaunchKernelGGL(k_patch_views, dim3(1), dim3(64), 0, s, views, level_nodes);
+}
+
 void launch_store_views(LevelViews* dst, const LevelViews& v, hipStream_t s) {
   hipLaunchKernelGGL(k_store_views, dim3(1), dim3(256), 0, s, dst, v);
 }
@@ -1366,18 +1778,18 @@ static int hip_fail(const char** err, const char* what) {
 }
 
 int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32_t T,
-              uint64_t* map, uint32_t idcap, hipStream_t s, uint32_t* job_nodes,
-              const char** err, const PhaseTimer& pt) {
+              int rule, float depth_ratio, uint64_t* map, uint32_t idcap, hipStream_t s,
+              uint32_t* level_nodes, uint32_t* sticky_err, int* base_depths,
+              int64_t* host_waits, const char** err, const PhaseTimer& pt) {
+  if (base_depths) *base_depths = 0;
+  const bool obj = rule == kSplitObject;
   const int njobs = jt.n;
   uint64_t R = 0, maxcount = 0;
   for (int j = 0; j < njobs; ++j) {
     R += jt.jobs[j].count;
     if (jt.jobs[j].count > maxcount) maxcount = jt.jobs[j].count;
   }
-  if (R == 0) {
-    for (int j = 0; j < njobs; ++j) job_nodes[j] = 0;
-    return 0;
-  }
+  if (R == 0) return 0;
   const int es = emit_stride(d);
   pt.begin(BDL_PH_PASSES);
   hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(kMaxJobs), 0, s, sc.ctr, jt, sc.jobs);
@@ -1388,96 +1800,146 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
   }
   hipLaunchKernelGGL(k_init_lists, dim3(1), dim3(64), 0, s, sc.jobs, njobs, sc.ctr, sc.seg[0],
                      sc.fin, sc.tile_seg[0], T, sc.max_seg, sc.max_fin, sc.max_tiles);
-  // global passes: a budget of depths, then the finisher, which does nothing
-  // and asks for more depths if a segment is still above the threshold
-  int depth = 0;
-  int budget = 0;
-  if (maxcount > T) {
-    // log2(n / T) depths, and one more: spatial-median splits of real data
-    // are not exactly balanced.  Jobs within the threshold need none.
-    budget = 1;
-    while (((uint64_t)T << budget) < maxcount && budget < 40) ++budget;
-    budget += 1;
-  }
+  // Global passes.  The host launches a budget of depths: the base
+  // log2(n / T) + 1, scaled by the ratio of needed to base depths that the
+  // tree's recent builds showed (clustered points need two to three times
+  // the base); each depth's kernels do nothing once its list is empty.  A cooperative
+  // kernel then runs whatever depths are left, on the device, so the host
+  // never waits for the build.  Without cooperative launch the host asks the
+  // finisher whether more depths are needed (one wait per budget).
   const unsigned pass_grid = grid_for(R, kTile, 2048);
+  // one wavefront per segment of a depth (at most max_seg)
+  const unsigned sel_grid = grid_for(sc.max_seg, kPassThreads / 64, 1024);
   // two wavefronts of the scatter per tile of R points (a depth has at most
   // R / kTile + segments tiles)
   const unsigned scatter_grid = grid_for(R, kTile * (kScatterThreads / 128), 1024);
-  while (true) {
-    for (int b = 0; b < budget; ++b, ++depth) {
+  auto launch_depths = [&](int from, int count) {
+    for (int depth = from; depth < from + count; ++depth) {
       const int par = depth & 1;
+      if (obj) {
+        for (int r = 0; r < 4; ++r) {
+          hipLaunchKernelGGL(k_sel_hist, dim3(pass_grid), dim3(kPassThreads), 0, s, sc.seg[par],
+                             sc.tile_seg[par], sc.ctr, par, d, leaf, sc.soa[par], sc.cap,
+                             sc.sel_hist, r);
+          hipLaunchKernelGGL(k_sel_pick, dim3(sel_grid), dim3(kPassThreads), 0, s, sc.seg[par],
+                             sc.ctr, par, sc.sel_hist, r);
+        }
+      }
       hipLaunchKernelGGL(k_count, dim3(pass_grid), dim3(kPassThreads), 0, s, sc.seg[par],
                          sc.tile_seg[par], sc.ctr, par, sc.jobs, sc.emit, es, d, leaf,
-                         sc.soa[par], sc.cap, sc.tile_left);
+                         sc.soa[par], sc.cap, sc.tile_left, rule);
       hipLaunchKernelGGL(k_tilescan, dim3(1), dim3(1024), 0, s, sc.seg[par], sc.seg[par ^ 1],
                          sc.ctr, par, sc.tile_left, sc.tile_off, sc.fin, T, sc.max_seg,
                          sc.max_fin, d, sc.segtb[par ^ 1], sc.tile_seg[par ^ 1], sc.max_tiles,
                          sc.max_emit);
       launch_scatter(d, scatter_grid, sc, par, map, idcap, s);
     }
+  };
+  int depth = 0;
+  bool host_loop = false;
+  if (maxcount > T) {
+    int base = 1;
+    while (((uint64_t)T << base) < maxcount && base < 40) ++base;
+    base += 1;
+    if (base_depths) *base_depths = base;
+    int budget = (int)ceilf((depth_ratio > 1.0f ? depth_ratio : 1.0f) * (float)base);
+    if (budget > kMaxDepth + 1) budget = kMaxDepth + 1;
+    launch_depths(0, budget);
+    depth = budget;
+    PassArgs A;
+    for (int i = 0; i < 2; ++i) {
+      A.seg[i] = sc.seg[i];
+      A.tile_seg[i] = sc.tile_seg[i];
+      A.segtb[i] = sc.segtb[i];
+      A.soa[i] = sc.soa[i];
+    }
+    A.c = sc.ctr;
+    A.jobs = sc.jobs;
+    A.emit = sc.emit;
+    A.tile_left = sc.tile_left;
+    A.tile_off = sc.tile_off;
+    A.fin = sc.fin;
+    A.map = map;
+    A.sel_hist = sc.sel_hist;
+    A.cap = sc.cap;
+    A.max_seg = sc.max_seg;
+    A.max_fin = sc.max_fin;
+    A.max_tiles = sc.max_tiles;
+    A.max_emit = sc.max_emit;
+    A.T = T;
+    A.leaf = leaf;
+    A.idcap = idcap;
+    A.es = es;
+    A.d = d;
+    A.rule = rule;
+    A.par0 = depth & 1;
+    A.depth0 = depth;
+    if (launch_passes(d, A, s) != hipSuccess) {
+      (void)hipGetLastError();
+      host_loop = true;
+    }
+  }
+  if (!host_loop) {
     pt.end(BDL_PH_PASSES);
     pt.begin(BDL_PH_FINISH);
-    const int par_end = depth & 1;
-    if (d <= 3) launch_finish<3, 2304, 144, 768>(par_end, sc, d, leaf, map, idcap, s);
-    else if (d <= 8) launch_finish<8, 1024, 64, 256>(par_end, sc, d, leaf, map, idcap, s);
-    else launch_finish<16, 512, 32, 256>(par_end, sc, d, leaf, map, idcap, s);
+    launch_finisher(obj, sc, d, leaf, map, idcap, s);
     pt.end(BDL_PH_FINISH);
-    if (hipMemcpyAsync(sc.host_ctr, sc.ctr, sizeof(BuildCounters), hipMemcpyDeviceToHost, s) !=
-        hipSuccess)
-      return hip_fail(err, "counter readback failed");
-    if (hipStreamSynchronize(s) != hipSuccess) return hip_fail(err, "build passes failed");
-    const uint32_t e = sc.host_ctr->err;
-    if (e) {
-      *err = (e & (32u | 64u | 128u)) ? "build scratch overflow in the finisher"
-                                       : "build scratch overflow in the global passes";
-      return BDL_EHIP;
+  } else {
+    while (true) {
+      pt.end(BDL_PH_PASSES);
+      pt.begin(BDL_PH_FINISH);
+      hipLaunchKernelGGL(k_set_par_final, dim3(1), dim3(64), 0, s, sc.ctr, depth & 1);
+      launch_finisher(obj, sc, d, leaf, map, idcap, s);
+      pt.end(BDL_PH_FINISH);
+      if (hipMemcpyAsync(sc.host_ctr, sc.ctr, sizeof(BuildCounters), hipMemcpyDeviceToHost,
+                         s) != hipSuccess)
+        return hip_fail(err, "counter readback failed");
+      if (host_waits) ++*host_waits;
+      if (hipStreamSynchronize(s) != hipSuccess) return hip_fail(err, "build passes failed");
+      const uint32_t e = sc.host_ctr->err;
+      if (e) {
+        *err = (e & (32u | 64u | 128u)) ? "build scratch overflow in the finisher"
+                                         : "build scratch overflow in the global passes";
+        return BDL_EHIP;
+      }
+      if (!sc.host_ctr->retry) break;
+      if (depth > kMaxDepth + 2) {
+        *err = "build did not terminate";
+        return BDL_EHIP;
+      }
+      hipLaunchKernelGGL(k_clear_retry, dim3(1), dim3(64), 0, s, sc.ctr);
+      pt.begin(BDL_PH_PASSES);
+      launch_depths(depth, 4);
+      depth += 4;
     }
-    if (!sc.host_ctr->retry) break;
-    if (depth > kMaxDepth + 2) {
-      *err = "build did not terminate";
-      return BDL_EHIP;
-    }
-    hipLaunchKernelGGL(k_clear_retry, dim3(1), dim3(64), 0, s, sc.ctr);
-    budget = 4;
-    pt.begin(BDL_PH_PASSES);
   }
-  const BuildCounters& hc = *sc.host_ctr;
-  const uint32_t nemit = hc.nemit;
-  int maxH = 0;
-  for (int j = 0; j < njobs; ++j) {
-    job_nodes[j] = hc.job_nodes[j];
-    if ((int)hc.job_height[j] > maxH) maxH = (int)hc.job_height[j];
-  }
+  // vEB layout: sort the emitted nodes by (job, vEB key) with the node count
+  // and the key width read on the device, then write every node at its rank
   int jobbits = 0;
   while ((1 << jobbits) < njobs) ++jobbits;
   pt.begin(BDL_PH_LAYOUT);
-  hipLaunchKernelGGL(k_job_offsets, dim3(1), dim3(64), 0, s, sc.ctr, njobs);
-  const bool composite = maxH + jobbits <= 64;
-  const unsigned g = grid_for(nemit, 256);
-  hipLaunchKernelGGL(k_layout_keys, dim3(g), dim3(256), 0, s, sc.emit, es, nemit, sc.ctr,
-                     composite && jobbits > 0 ? maxH : -1, sc.keys[0], sc.vals[0]);
-  int which = radix_sort_pairs_u64(sc.keys[0], sc.vals[0], sc.keys[1], sc.vals[1], nemit, 0,
-                                   composite ? maxH + jobbits : maxH, sc.tmp, s);
-  if (!composite && jobbits > 0) {
-    hipLaunchKernelGGL(k_layout_jobkeys, dim3(g), dim3(256), 0, s, sc.emit, es, nemit,
-                       sc.vals[which], sc.keys[which]);
-    which ^= radix_sort_pairs_u64(sc.keys[which], sc.vals[which], sc.keys[which ^ 1],
-                                  sc.vals[which ^ 1], nemit, 0, jobbits, sc.tmp, s);
+  hipLaunchKernelGGL(k_job_offsets, dim3(1), dim3(64), 0, s, sc.ctr, njobs, jobbits);
+  // a build of R points emits at most 2R - 1 nodes per job
+  const uint64_t ncap = std::min<uint64_t>(sc.max_emit, 2 * R + (uint64_t)njobs);
+  const unsigned g = grid_for(ncap, 256);
+  hipLaunchKernelGGL(k_layout_keys, dim3(g), dim3(256), 0, s, sc.emit, es, sc.ctr, -1, sc.keys[0],
+                     sc.vals[0]);
+  radix_sort_pairs_u64_dev(sc.keys, sc.vals, &sc.ctr->nemit, ncap, &sc.ctr->max_height, 64,
+                           &sc.ctr->sort_sel, sc.tmp, s);
+  if (jobbits > 0) {
+    hipLaunchKernelGGL(k_layout_jobkeys, dim3(g), dim3(256), 0, s, sc.emit, es, sc.ctr,
+                       sc.vals[0], sc.vals[1], sc.keys[0]);
+    radix_sort_pairs_u64_dev(sc.keys, sc.vals, &sc.ctr->nemit, ncap, &sc.ctr->job_bits, 8,
+                             &sc.ctr->sort_sel, sc.tmp, s);
   }
-  hipLaunchKernelGGL(k_layout_rank, dim3(g), dim3(256), 0, s, sc.vals[which], nemit, sc.emit, es,
-                     sc.ctr, sc.final_of);
-  hipLaunchKernelGGL(k_layout_write, dim3(g), dim3(256), 0, s, sc.emit, es, nemit,
-                     sc.vals[which], sc.final_of, sc.jobs, d, &sc.ctr->err);
+  hipLaunchKernelGGL(k_layout_rank, dim3(g), dim3(256), 0, s, sc.vals[0], sc.vals[1], sc.emit,
+                     es, sc.ctr, sc.final_of);
+  hipLaunchKernelGGL(k_layout_write, dim3(g), dim3(256), 0, s, sc.emit, es, sc.ctr, sc.vals[0],
+                     sc.vals[1], sc.final_of, sc.jobs, d, &sc.ctr->err);
+  hipLaunchKernelGGL(k_build_done, dim3(1), dim3(kMaxJobs), 0, s, sc.ctr, sc.jobs, njobs,
+                     level_nodes, sticky_err);
   pt.end(BDL_PH_LAYOUT);
   if (hipGetLastError() != hipSuccess) return hip_fail(err, "build kernel launch failed");
-  if (hipMemcpyAsync(sc.host_ctr, sc.ctr, sizeof(BuildCounters), hipMemcpyDeviceToHost, s) !=
-          hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return hip_fail(err, "layout failed");
-  if (sc.host_ctr->err) {
-    *err = "node layout out of range";
-    return BDL_EHIP;
-  }
   return 0;
 }
 

@@ -27,6 +27,7 @@ struct BuildScratch {
   uint32_t* tmp = nullptr;       // scan / sort scratch
   uint64_t tmp_words = 0;
   uint32_t* tile_cnt = nullptr;  // compaction per-tile counts (tiles of kTile)
+  uint32_t* sel_hist = nullptr;  // object median: 256 digit counts per segment (max_seg rows)
   BuildCounters* ctr = nullptr;
   BuildCounters* host_ctr = nullptr;  // pinned mirror
   Job* jobs = nullptr;           // device copy of the job table
@@ -54,12 +55,27 @@ void launch_compact_live(const float* rec, int d, uint64_t n, float* soa, uint64
                          uint64_t dst, float* out_rec, uint32_t* tile_cnt, uint32_t* tmp,
                          hipStream_t s);
 
-// Build every job of the table from build buffer 0.  Writes records (slot
-// order), nodes (vEB order) and, where requested, the id map.  Fills
-// job_nodes[i] with the node count of job i.  Returns 0 or a BDL_E* code.
+// Build every job of the table from build buffer 0 with split heuristic
+// `rule` (kSplitSpatial or kSplitObject).  Writes records (slot order),
+// nodes (vEB order) and, where requested, the id map, all on stream s with
+// no host wait: each job's node count is stored on the device in
+// level_nodes[level] (level_nodes[kMaxLevels] for the buffer's tree),
+// level_nodes[kMaxLevels + 1] receives the number of global-pass depths the
+// build needed, and the device-side checks (scratch overflow, a build that
+// does not end) leave their bits in *sticky_err (device) for the host's next
+// check.  The host launches depth_ratio x the base budget log2(n / T) + 1
+// of depths (*base_depths receives the base, 0 if the build needs no global
+// pass); a cooperative kernel runs any left.  Without cooperative launch the
+// host drives the rest and waits once per budget of depths (*host_waits
+// counts those waits).  Returns 0 or a BDL_E* code for a launch failure.
 int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32_t T,
-              uint64_t* map, uint32_t idcap, hipStream_t s, uint32_t* job_nodes,
-              const char** err, const PhaseTimer& pt);
+              int rule, float depth_ratio, uint64_t* map, uint32_t idcap, hipStream_t s,
+              uint32_t* level_nodes, uint32_t* sticky_err, int* base_depths,
+              int64_t* host_waits, const char** err, const PhaseTimer& pt);
+
+// Node counts of the trees k-NN visits, from level_nodes (after every
+// upload of the views).
+void launch_patch_views(LevelViews* views, const uint32_t* level_nodes, hipStream_t s);
 
 // small utilities
 void launch_store_u32(uint32_t* dst, const uint32_t* vals, int n, hipStream_t s);

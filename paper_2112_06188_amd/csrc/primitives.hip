@@ -83,8 +83,8 @@ constexpr int kSingleThreads = 1024;
 constexpr int kSingleTile = kSingleThreads * kScanItems;
 constexpr uint64_t kSingleMax = 2 * kSingleTile;
 
-__global__ void __launch_bounds__(kSingleThreads)
-k_scan_single(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* __restrict__ total) {
+__device__ __forceinline__ void scan_single_body(const uint32_t* in, uint32_t* out, uint64_t n,
+                                                 uint32_t* __restrict__ total) {
   __shared__ uint32_t tile[kSingleTile + kSingleTile / 32];
   __shared__ uint32_t wsum[17];
   uint32_t carry = 0;
@@ -121,6 +121,11 @@ k_scan_single(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* __restric
   if (threadIdx.x == 0 && total) *total = carry;
 }
 
+__global__ void __launch_bounds__(kSingleThreads)
+k_scan_single(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* __restrict__ total) {
+  scan_single_body(in, out, n, total);
+}
+
 // Lanes of the wavefront whose digit equals this lane's, found with one
 // ballot per digit bit; only meaningful for valid lanes.
 __device__ inline uint64_t digit_peers(uint32_t dig, bool valid, int bits) {
@@ -140,9 +145,9 @@ __device__ inline uint64_t lanes_below() {
 
 // Digit counts of one tile; one LDS add per distinct digit of a wavefront.
 template <typename K>
-__global__ void __launch_bounds__(kRadixThreads)
-k_radix_hist(const K* __restrict__ keys, uint64_t n, int shift, int bits,
-             uint32_t* __restrict__ hist, uint32_t nb) {
+__device__ __forceinline__ void radix_hist_tile(const K* __restrict__ keys, uint64_t n, int shift,
+                                                int bits, uint32_t* __restrict__ hist,
+                                                uint32_t nb) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
@@ -161,16 +166,20 @@ k_radix_hist(const K* __restrict__ keys, uint64_t n, int shift, int bits,
   hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of one tile.  Each wavefront ranks a contiguous quarter of
-// the tile against its own digit counters (no workgroup barrier between
-// rounds); the counters then give every element its place in the tile
-// sorted by digit, the tile is reordered in LDS, and written out so that
-// consecutive threads store consecutive positions of one digit's run.
 template <typename K>
 __global__ void __launch_bounds__(kRadixThreads)
-k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
-                K* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n, int shift,
-                int bits, const uint32_t* __restrict__ hscan, uint32_t nb) {
+k_radix_hist(const K* __restrict__ keys, uint64_t n, int shift, int bits,
+             uint32_t* __restrict__ hist, uint32_t nb) {
+  radix_hist_tile<K>(keys, n, shift, bits, hist, nb);
+}
+
+template <typename K>
+__device__ __forceinline__ void radix_scatter_tile(const K* __restrict__ kin,
+                                                   const uint32_t* __restrict__ vin,
+                                                   K* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                   uint64_t n, int shift, int bits,
+                                                   const uint32_t* __restrict__ hscan,
+                                                   uint32_t nb) {
   constexpr int kWaves = kRadixThreads / 64;
   constexpr int kRounds = kRadixTile / kRadixThreads;  // rounds of 64 per wavefront
   static_assert(kRadixThreads == 256, "one thread per digit");
@@ -249,6 +258,152 @@ k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
 }
 
 template <typename K>
+__global__ void __launch_bounds__(kRadixThreads)
+k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                K* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n, int shift,
+                int bits, const uint32_t* __restrict__ hscan, uint32_t nb) {
+  radix_scatter_tile<K>(kin, vin, kout, vout, n, shift, bits, hscan, nb);
+}
+
+// ---- sorts whose element count and key width are read on the device ----
+//
+// A fixed grid of kChunkBlocks workgroups: workgroup b owns the contiguous
+// chunk [b * chunk, (b + 1) * chunk) of the n elements (chunk a multiple of
+// the tile), so the digit counts have a fixed shape (256 x kChunkBlocks) and
+// the work follows n, not a host bound.  A pass whose first bit is at or
+// above the width does nothing; passes that run form a prefix, so the
+// result lies in buffer pair (passes run) & 1.
+constexpr uint32_t kChunkBlocks = 256;
+
+__device__ inline void chunk_of(uint64_t n, uint64_t* b0, uint64_t* b1) {
+  uint64_t chunk = (n + kChunkBlocks - 1) / kChunkBlocks;
+  chunk = (chunk + kRadixTile - 1) / kRadixTile * kRadixTile;
+  *b0 = (uint64_t)blockIdx.x * chunk;
+  *b1 = *b0 + chunk < n ? *b0 + chunk : n;
+}
+
+template <typename K>
+__global__ void __launch_bounds__(kRadixThreads)
+k_radix_hist_chunk(const K* __restrict__ keys, const uint32_t* n_dev, const uint32_t* width_dev,
+                   int shift, uint32_t* __restrict__ hist) {
+  if ((uint32_t)shift >= *width_dev) return;
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  uint64_t b0, b1;
+  chunk_of(*n_dev, &b0, &b1);
+  const uint64_t below = lanes_below();
+  for (uint64_t i0 = b0; i0 < b1; i0 += kRadixThreads) {
+    const uint64_t i = i0 + threadIdx.x;
+    const bool valid = i < b1;
+    const uint32_t dig = valid ? (uint32_t)(keys[i] >> shift) & 255u : 0u;
+    const uint64_t m = digit_peers(dig, valid, 8);
+    if (valid && (m & below) == 0) atomicAdd(&h[dig], (uint32_t)__popcll(m));
+  }
+  __syncthreads();
+  hist[(uint64_t)threadIdx.x * kChunkBlocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of the 256 x kChunkBlocks digit counts in one workgroup.
+__global__ void __launch_bounds__(kSingleThreads)
+k_radix_scan_chunk(uint32_t* hist, const uint32_t* width_dev, int shift) {
+  if ((uint32_t)shift >= *width_dev) return;
+  scan_single_body(hist, hist, 256ull * kChunkBlocks, nullptr);
+}
+
+// Stable scatter of a chunk, tile by tile in order: every tile is ranked by
+// digit as in the tiled pass, and each digit's write position advances by
+// the tile's count of that digit.
+template <typename K>
+__global__ void __launch_bounds__(kRadixThreads)
+k_radix_scatter_chunk(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                      K* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* n_dev,
+                      const uint32_t* width_dev, int shift, const uint32_t* __restrict__ hscan) {
+  if ((uint32_t)shift >= *width_dev) return;
+  constexpr int kWaves = kRadixThreads / 64;
+  constexpr int kRounds = kRadixTile / kRadixThreads;
+  __shared__ uint32_t wcnt[kWaves][256];
+  __shared__ uint32_t dstart[256];
+  __shared__ uint32_t gofs[256];
+  __shared__ uint32_t wsum[17];
+  __shared__ K skey[kRadixTile];
+  __shared__ uint32_t sval[kRadixTile];
+  uint64_t b0, b1;
+  chunk_of(*n_dev, &b0, &b1);
+  if (b0 >= b1) return;
+  const int tid = threadIdx.x;
+  const int lane = __lane_id();
+  const int w = tid >> 6;
+  const uint64_t below = lanes_below();
+  gofs[tid] = hscan[(uint64_t)tid * kChunkBlocks + blockIdx.x];
+  for (uint64_t tbase = b0; tbase < b1; tbase += kRadixTile) {
+#pragma unroll
+    for (int v = 0; v < kWaves; ++v) wcnt[v][tid] = 0;
+    __syncthreads();
+    const uint64_t wbase = tbase + (uint64_t)w * (kRounds * 64);
+    K key[kRounds];
+    uint32_t val[kRounds];
+    uint32_t rank[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const uint64_t i = wbase + (uint64_t)r * 64 + lane;
+      key[r] = i < b1 ? kin[i] : (K)0;
+      val[r] = i < b1 ? vin[i] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const bool valid = wbase + (uint64_t)r * 64 + lane < b1;
+      const uint32_t dig = (uint32_t)(key[r] >> shift) & 255u;
+      const uint64_t m = digit_peers(dig, valid, 8);
+      const uint32_t lower = (uint32_t)__popcll(m & below);
+      const uint32_t seen = valid ? wcnt[w][dig] : 0u;
+      rank[r] = seen + lower;
+      if (valid && lower == 0) wcnt[w][dig] = seen + (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    uint32_t tot = 0;
+#pragma unroll
+    for (int v = 0; v < kWaves; ++v) {
+      const uint32_t c = wcnt[v][tid];
+      wcnt[v][tid] = tot;
+      tot += c;
+    }
+    dstart[tid] = block_excl_scan(tot, wsum, nullptr);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      if (wbase + (uint64_t)r * 64 + lane < b1) {
+        const uint32_t dig = (uint32_t)(key[r] >> shift) & 255u;
+        const uint32_t lp = dstart[dig] + wcnt[w][dig] + rank[r];
+        skey[lp] = key[r];
+        sval[lp] = val[r];
+      }
+    }
+    __syncthreads();
+    const uint64_t left = b1 - tbase;
+    const uint32_t tcount = left < (uint64_t)kRadixTile ? (uint32_t)left : (uint32_t)kRadixTile;
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const uint32_t li = (uint32_t)(r * kRadixThreads + tid);
+      if (li < tcount) {
+        const K k = skey[li];
+        const uint32_t dig = (uint32_t)(k >> shift) & 255u;
+        const uint64_t dst = (uint64_t)gofs[dig] + (li - dstart[dig]);
+        kout[dst] = k;
+        vout[dst] = sval[li];
+      }
+    }
+    __syncthreads();
+    gofs[tid] += tot;  // this tile's count of digit tid
+  }
+}
+
+// Index of the buffer holding the result: one flip per pass that ran.
+__global__ void k_radix_sel(const uint32_t* width_dev, uint32_t* sel) {
+  if (threadIdx.x == 0) sel[0] = ((*width_dev + 7u) / 8u) & 1u;
+}
+
+template <typename K>
 int radix_sort_pairs(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, uint64_t n,
                      int begin_bit, int end_bit, uint32_t* tmp, hipStream_t s) {
   if (n == 0 || begin_bit >= end_bit) return 0;
@@ -273,6 +428,25 @@ int radix_sort_pairs(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, u
 }  // namespace
 
 size_t scan_tmp_words(uint64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 2; }
+
+void radix_sort_pairs_u64_dev(uint64_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev,
+                              uint64_t n_cap, const uint32_t* width_dev, int max_bits,
+                              uint32_t* sel_dev, uint32_t* tmp, hipStream_t s) {
+  (void)n_cap;
+  uint32_t* hist = tmp;
+  int p = 0;
+  for (int shift = 0; shift < max_bits; shift += 8, ++p) {
+    const int cur = p & 1;
+    hipLaunchKernelGGL(k_radix_hist_chunk<uint64_t>, dim3(kChunkBlocks), dim3(kRadixThreads), 0,
+                       s, keys[cur], n_dev, width_dev, shift, hist);
+    hipLaunchKernelGGL(k_radix_scan_chunk, dim3(1), dim3(kSingleThreads), 0, s, hist, width_dev,
+                       shift);
+    hipLaunchKernelGGL(k_radix_scatter_chunk<uint64_t>, dim3(kChunkBlocks), dim3(kRadixThreads),
+                       0, s, keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_dev,
+                       width_dev, shift, hist);
+  }
+  hipLaunchKernelGGL(k_radix_sel, dim3(1), dim3(64), 0, s, width_dev, sel_dev);
+}
 
 void scan_exclusive_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
                         uint32_t* tmp, hipStream_t s) {

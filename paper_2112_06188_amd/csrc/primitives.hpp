@@ -80,5 +80,14 @@ int radix_sort_pairs_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
 int radix_sort_pairs_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                          uint32_t* vals_alt, uint64_t n, int begin_bit, int end_bit,
                          uint32_t* tmp, hipStream_t s);
+// Stable sort of *n_dev (device, at most n_cap) pairs from (keys[0], vals[0])
+// by key bits [0, *width_dev) (device, at most max_bits): passes of 8 bits
+// on a fixed grid whose workgroups own contiguous chunks, and a pass whose
+// first bit is at or above the width does nothing, so no host readback is
+// needed.  *sel_dev (device) receives the index of the buffer pair that
+// holds the result.  tmp: 65536 words.
+void radix_sort_pairs_u64_dev(uint64_t* keys[2], uint32_t* vals[2], const uint32_t* n_dev,
+                              uint64_t n_cap, const uint32_t* width_dev, int max_bits,
+                              uint32_t* sel_dev, uint32_t* tmp, hipStream_t s);
 
 }  // namespace bdl

@@ -14,6 +14,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "baseline.hpp"
 #include "bdl.h"
 #include "bdl_common.hpp"
 #include "build.hpp"
@@ -66,6 +67,10 @@ uint32_t* scratch_on(int dev) {
   return g_scratch_ptr[dev];
 }
 
+constexpr int kModeBdl = 0;
+constexpr int kModeRebuildAll = 1;
+constexpr int kModeNoRebuild = 2;
+
 struct LevelState {
   float* rec = nullptr;
   float* nodes = nullptr;
@@ -74,6 +79,12 @@ struct LevelState {
   int64_t live = 0;
   int64_t n_nodes = 0;
   bool on = false;
+  // Bloom filter of the tree's points for the routed erase, built at the
+  // first such erase after the tree changed (2^bloom_log2 words in use)
+  uint64_t* bloom = nullptr;
+  int64_t bloom_words = 0;
+  int bloom_log2 = 0;
+  bool bloom_ok = false;
 };
 
 }  // namespace
@@ -82,6 +93,14 @@ struct bdl_tree {
   bdl_config cfg;
   hipStream_t s = nullptr;
   int dev = 0;
+  int rule = kSplitSpatial;  // split heuristic of every tree (BDL_FLAG_OBJECT_MEDIAN)
+  // the structure: the BDL-tree, or one of the baselines of Section III-B,
+  // which keep one tree as static tree 0 and no buffer
+  int mode = 0;              // kModeBdl, kModeRebuildAll (B1), kModeNoRebuild (B2)
+  float* b2_alt = nullptr;   // B2: spare record arena the next insert lays out into
+  int64_t b2_alt_cap = 0;
+  B2Scratch b2{};            // B2: scratch of one insert
+  uint64_t b2_pts_cap = 0, b2_box_words = 0, b2_tmp_words = 0;
   uint32_t* noalloc_scratch = nullptr;  // this device's `scratch` (bdl_knn_noalloc)
   int d = 0, S = 0, NS = 0;
   uint32_t T = 0;
@@ -91,10 +110,26 @@ struct bdl_tree {
   float* pool[2] = {nullptr, nullptr};
   int pcur = 0;
   int64_t bn = 0;
+  uint64_t* pool_bloom = nullptr;  // the pool's filter (routed erase), rebuilt per erase
+  int64_t pool_bloom_words = 0;
+  int erase_route = 0;             // BDL_PARAM_ERASE_ROUTE
   float* brec = nullptr;
   float* bnodes = nullptr;
   int64_t b_nodes = 0;
   uint64_t* map = nullptr;
+  // node counts of the trees, published by the builds on the device
+  // (kMaxLevels + 1 words, the last for the buffer's tree); the host learns
+  // them from a pinned copy once the builds that wrote them are done
+  uint32_t* d_level_nodes = nullptr;
+  uint32_t* h_level_nodes = nullptr;  // pinned copy, valid once ev_nodes completes
+  hipEvent_t ev_nodes = nullptr;
+  bool nodes_pending = false;         // some n_nodes (< 0) wait for that copy
+  // ratio of the global-pass depths recent builds needed to their base
+  // budget log2(n / T) + 1; the host launches that many depths up front and
+  // the device finishes any left
+  float depth_ratio = 1.0f;
+  int pub_base = 0;                   // base budget of the build last published
+  int64_t host_waits = 0;             // times the library blocked on the stream
   uint32_t* d_live = nullptr;   // kMaxLevels
   uint32_t* d_misc = nullptr;   // erase counters [0..1], validation [4..6]
   unsigned long long* d_stats = nullptr;  // k-NN work counters (profiling)
@@ -212,6 +247,51 @@ void resolve_events(bdl_tree* t) {
 
 int64_t level_cap(const bdl_tree* t, int i) { return ((int64_t)1 << i) * t->cfg.buffer_size; }
 
+// Block until the tree's stream is idle (counted in host_waits).
+hipError_t wait_stream(bdl_tree* t) {
+  ++t->host_waits;
+  return hipStreamSynchronize(t->s);
+}
+
+// Host copies of the node counts the builds published.  With block, wait for
+// the copy; otherwise use it only if it has already arrived.
+void resolve_nodes(bdl_tree* t, bool block) {
+  if (!t->nodes_pending) return;
+  if (block) {
+    ++t->host_waits;
+    if (hipEventSynchronize(t->ev_nodes) != hipSuccess) return;
+  } else if (hipEventQuery(t->ev_nodes) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  for (int i = 0; i < kMaxLevels; ++i)
+    if (t->lev[i].on && t->lev[i].n_nodes < 0) t->lev[i].n_nodes = t->h_level_nodes[i];
+  if (t->b_nodes < 0) t->b_nodes = t->h_level_nodes[kMaxLevels];
+  t->nodes_pending = false;
+  // learn how many depths beyond the base budget the last build needed;
+  // forget slowly, so that one shallow build does not cost the next deep one
+  // a round on the device's leftover path
+  if (t->pub_base > 0) {
+    const float seen = (float)t->h_level_nodes[kMaxLevels + 1] / (float)t->pub_base;
+    const float decayed = t->depth_ratio * 0.9f;
+    t->depth_ratio = seen > decayed ? seen : decayed;
+    if (t->depth_ratio < 1.0f) t->depth_ratio = 1.0f;
+    if (t->depth_ratio > 8.0f) t->depth_ratio = 8.0f;
+    t->pub_base = 0;
+  }
+}
+
+// After a build: bring its node counts to the host when the stream gets
+// there (no wait now).
+void publish_nodes(bdl_tree* t, int base_depths) {
+  t->nodes_pending = true;
+  t->pub_base = base_depths;
+  if (hipMemcpyAsync(t->h_level_nodes, t->d_level_nodes, (kMaxLevels + 2) * 4,
+                     hipMemcpyDeviceToHost, t->s) != hipSuccess ||
+      hipEventRecord(t->ev_nodes, t->s) != hipSuccess)
+    (void)hipGetLastError();
+}
+
 void free_build_scratch(bdl_tree* t) {
   BuildScratch& sc = t->sc;
   for (int i = 0; i < 2; ++i) {
@@ -230,6 +310,7 @@ void free_build_scratch(bdl_tree* t) {
   dfree(t, sc.final_of);
   dfree(t, sc.tmp);
   dfree(t, sc.tile_cnt);
+  dfree(t, sc.sel_hist);
   BuildCounters* hc = sc.host_ctr;
   BuildCounters* dc = sc.ctr;
   Job* jb = sc.jobs;
@@ -256,6 +337,8 @@ bool ensure_build_scratch(bdl_tree* t, uint64_t need) {
   n.tmp_words = radix_tmp_words(n.max_emit);
   uint64_t st = scan_tmp_words(cap) + 16;
   if (st > n.tmp_words) n.tmp_words = st;
+  // the layout's sort keeps 256 digit counts for each of its 256 chunks
+  if (n.tmp_words < 256 * 256 + 16) n.tmp_words = 256 * 256 + 16;
   bool ok = true;
   auto A = [&](size_t bytes) -> void* {
     void* p = ok ? dmalloc(t, bytes) : nullptr;
@@ -278,16 +361,19 @@ bool ensure_build_scratch(bdl_tree* t, uint64_t need) {
   n.final_of = (uint32_t*)A(n.max_emit * 4);
   n.tmp = (uint32_t*)A(n.tmp_words * 4);
   n.tile_cnt = (uint32_t*)A((cap / kTile + 2) * 4 + (2ull << 20));
+  if (t->rule == kSplitObject) n.sel_hist = (uint32_t*)A(n.max_seg * 256 * 4);
   if (!ok) {
     void* ps[] = {n.soa[0], n.soa[1], n.seg[0], n.seg[1], n.segtb[0], n.segtb[1], n.keys[0],
                   n.keys[1], n.vals[0], n.vals[1], n.tile_left, n.tile_seg[0], n.tile_seg[1],
                   n.tile_off, n.fin,
                   n.emit,
-                  n.final_of, n.tmp, n.tile_cnt};
+                  n.final_of, n.tmp, n.tile_cnt, n.sel_hist};
     for (void* p : ps) dfree(t, p);
     return false;
   }
-  (void)hipStreamSynchronize(t->s);
+  // the select kernels expect zero counts and clear them after each use
+  if (n.sel_hist) launch_fill_u32(n.sel_hist, 0u, n.max_seg * 256, t->s);
+  (void)wait_stream(t);
   free_build_scratch(t);
   n.host_ctr = t->sc.host_ctr;
   n.ctr = t->sc.ctr;
@@ -319,11 +405,35 @@ bool ensure_query_scratch(bdl_tree* t, uint64_t need) {
     for (void* p : ps) dfree(t, p);
     return false;
   }
-  (void)hipStreamSynchronize(t->s);
+  (void)wait_stream(t);
   void* old[] = {t->qs.keys[0], t->qs.keys[1], t->qs.vals[0], t->qs.vals[1], t->qs.tmp,
                  t->qs.box};
   for (void* p : old) dfree(t, p);
   t->qs = n;
+  return true;
+}
+
+// Filter size for n records: 16 bits per record, rounded up to a power of
+// two of 64-bit words (a false-positive rate of a few per thousand with four
+// bits per key in one word).
+int bloom_log2_for(int64_t n) {
+  int lg = 0;
+  while ((1ll << lg) * 4 < n) ++lg;
+  return lg;
+}
+
+// Grows a device array of 64-bit words to at least `need` words (contents
+// not kept).
+bool ensure_words(bdl_tree* t, uint64_t*& p, int64_t& have, int64_t need) {
+  if (p && have >= need) return true;
+  uint64_t* q = (uint64_t*)dmalloc(t, (size_t)need * 8);
+  if (!q) return false;
+  if (p) {
+    (void)wait_stream(t);
+    dfree(t, p);
+  }
+  p = q;
+  have = need;
   return true;
 }
 
@@ -357,6 +467,7 @@ LevelViews make_views(const bdl_tree* t);
 void upload_views(bdl_tree* t) {
   LevelViews v = make_views(t);
   launch_store_views(t->d_views, v, t->s);
+  launch_patch_views(t->d_views, t->d_level_nodes, t->s);
 }
 
 // Insert_L (Alg. 3) over the pool = buffer (arrival order) ++ batch.  The
@@ -374,8 +485,13 @@ void upload_views(bdl_tree* t) {
 // null).  Trees in pre_clear are taken out first (Erase_L's half rule: their
 // live points are in the batch); they stay untouched unless the insert
 // succeeds, so that BDL_ENOMEM leaves the trees as they were.
+int insert_single(bdl_tree* t, const float* batch, const uint32_t* batch_ids, int64_t n,
+                  uint64_t pre_clear);
+
 int insert_impl(bdl_tree* t, const float* batch, const uint32_t* batch_ids, int64_t n,
                 uint64_t pre_clear = 0) {
+  resolve_nodes(t, false);  // learn from builds that have finished (no wait)
+  if (t->mode != kModeBdl) return insert_single(t, batch, batch_ids, n, pre_clear);
   const int64_t X = t->cfg.buffer_size;
   const int64_t pn = t->bn + n;
   const uint64_t m = (uint64_t)(pn / X);
@@ -505,10 +621,11 @@ int insert_impl(bdl_tree* t, const float* batch, const uint32_t* batch_ids, int6
                          t->cfg.id_capacity, t->s);
   t->pt.end(BDL_PH_GATHER);
   // ---- build ----
-  uint32_t job_nodes[kMaxJobs] = {0};
   const char* err = nullptr;
-  int rc = run_build(jt, sc, t->d, (uint32_t)t->cfg.leaf_size, t->T, t->map, t->cfg.id_capacity,
-                     t->s, job_nodes, &err, t->pt);
+  int base_depths = 0;
+  int rc = run_build(jt, sc, t->d, (uint32_t)t->cfg.leaf_size, t->T, t->rule, t->depth_ratio,
+                     t->map, t->cfg.id_capacity, t->s, t->d_level_nodes, t->d_misc + 9,
+                     &base_depths, &t->host_waits, &err, t->pt);
   if (rc) return fail(rc, err ? err : "build failed");
   // ---- commit ----
   for (int i = 0; i < kMaxLevels; ++i) {
@@ -516,6 +633,7 @@ int insert_impl(bdl_tree* t, const float* batch, const uint32_t* batch_ids, int6
     LevelState& L = t->lev[i];
     L.on = false;
     L.n_slots = L.live = L.n_nodes = 0;
+    L.bloom_ok = false;
   }
   t->b_nodes = 0;
   for (int i = 0; i < jt.n; ++i) {
@@ -523,15 +641,194 @@ int insert_impl(bdl_tree* t, const float* batch, const uint32_t* batch_ids, int6
       LevelState& L = t->lev[job_level[i]];
       L.on = true;
       L.n_slots = L.live = jt.jobs[i].count;
-      L.n_nodes = job_nodes[i];
+      L.n_nodes = -1;  // on the device until publish_nodes' copy arrives
+      L.bloom_ok = false;
       t->rebuilt += jt.jobs[i].count;
     } else {
-      t->b_nodes = job_nodes[i];
+      t->b_nodes = -1;
     }
   }
+  if (jt.n) publish_nodes(t, base_depths);
   t->pcur ^= 1;
   t->bn = bn_new;
   t->F = Fn;
+  upload_live(t);
+  upload_views(t);
+  if (hipGetLastError() != hipSuccess) return fail(BDL_EHIP, "kernel launch failed in insert");
+  return 0;
+}
+
+// B2's in-place insert (Section III-B): the batch goes into the existing
+// tree's leaves along its splits, and the records are laid out again into
+// the spare arena, which then becomes the tree's.
+int insert_b2(bdl_tree* t, const float* pts, const uint32_t* ids, int64_t n) {
+  LevelState& L = t->lev[0];
+  resolve_nodes(t, true);  // the kernels walk the tree's nodes
+  if (L.n_nodes <= 0) return fail(BDL_EHIP, "tree without nodes");
+  const int64_t total = L.n_slots + n;
+  if (total >= (1ll << 31)) return fail(BDL_EINVAL, "tree too large");
+  // ---- memory first ----
+  if (t->b2_alt_cap < total) {
+    int64_t cap = t->b2_alt_cap > L.cap ? t->b2_alt_cap : L.cap;
+    while (cap < total) cap *= 2;
+    float* alt = (float*)dmalloc(t, (size_t)(cap + kRecPad) * t->S * 4);
+    if (!alt) return fail(BDL_ENOMEM, "cannot allocate the record arena");
+    (void)wait_stream(t);
+    dfree(t, t->b2_alt);
+    t->b2_alt = alt;
+    t->b2_alt_cap = cap;
+  }
+  const uint64_t nbox = (uint64_t)L.n_nodes * 2 * t->d;
+  const uint64_t ntmp = radix_tmp_words((uint64_t)n);
+  if ((uint64_t)n > t->b2_pts_cap || nbox > t->b2_box_words || ntmp > t->b2_tmp_words) {
+    uint64_t pc = t->b2_pts_cap > (uint64_t)n ? t->b2_pts_cap : (uint64_t)n;
+    uint64_t bw = t->b2_box_words > nbox ? t->b2_box_words : nbox;
+    uint64_t tw = radix_tmp_words(pc);
+    B2Scratch b{};
+    bool ok = true;
+    for (int i = 0; i < 2 && ok; ++i) {
+      b.keys[i] = (uint32_t*)dmalloc(t, pc * 4);
+      b.vals[i] = (uint32_t*)dmalloc(t, pc * 4);
+      ok = b.keys[i] && b.vals[i];
+    }
+    b.obox = ok ? (uint32_t*)dmalloc(t, bw * 4) : nullptr;
+    b.tmp = ok && b.obox ? (uint32_t*)dmalloc(t, tw * 4) : nullptr;
+    if (!b.tmp) {
+      void* ps[] = {b.keys[0], b.keys[1], b.vals[0], b.vals[1], b.obox};
+      for (void* q : ps) dfree(t, q);
+      return fail(BDL_ENOMEM, "cannot allocate insert scratch");
+    }
+    (void)wait_stream(t);
+    void* old[] = {t->b2.keys[0], t->b2.keys[1], t->b2.vals[0], t->b2.vals[1], t->b2.obox,
+                   t->b2.tmp};
+    for (void* q : old) dfree(t, q);
+    t->b2 = b;
+    t->b2_pts_cap = pc;
+    t->b2_box_words = bw;
+    t->b2_tmp_words = tw;
+  }
+  t->pt.begin(BDL_PH_GATHER);
+  int rc = b2_insert(pts, ids, (uint64_t)n, t->d, L.nodes, (uint32_t)L.n_nodes, L.rec,
+                     (uint32_t)L.n_slots, t->b2_alt, t->map, t->cfg.id_capacity, 0u,
+                     t->d_misc + 8, t->b2, t->s);
+  t->pt.end(BDL_PH_GATHER);
+  if (rc) return fail(rc, "in-place insert failed to launch");
+  std::swap(L.rec, t->b2_alt);
+  std::swap(L.cap, t->b2_alt_cap);
+  L.n_slots = total;
+  L.live += n;
+  L.bloom_ok = false;
+  upload_live(t);
+  upload_views(t);
+  return 0;
+}
+
+// The baselines' insert.  B1 (and B2's first batch): one build over the live
+// points of tree 0, in slot order (none if pre_clear takes the tree out),
+// followed by the batch (caller rows with ids, or records when batch_ids is
+// null).  B2 afterwards inserts in place.  Tree 0's arenas grow as needed.
+int insert_single(bdl_tree* t, const float* batch, const uint32_t* batch_ids, int64_t n,
+                  uint64_t pre_clear) {
+  LevelState& L = t->lev[0];
+  const bool have = L.on && !(pre_clear & 1u);
+  if (t->mode == kModeNoRebuild && have && L.n_slots > 0) {
+    if (n == 0) return 0;
+    if (!batch_ids) return fail(BDL_EINVAL, "in-place insert takes caller rows");
+    return insert_b2(t, batch, batch_ids, n);
+  }
+  const int64_t keep = have ? L.live : 0;
+  const int64_t total = keep + n;
+  if (total >= (1ll << 31)) return fail(BDL_EINVAL, "tree too large");
+  if (total == 0) {
+    L.on = false;
+    L.n_slots = L.live = L.n_nodes = 0;
+    L.bloom_ok = false;
+    t->F = 0;
+    upload_live(t);
+    upload_views(t);
+    return 0;
+  }
+  // ---- memory first: nothing has been enqueued yet ----
+  float* rec = L.rec;
+  float* nodes = L.nodes;
+  int64_t cap = L.cap;
+  const bool grow = !L.rec || L.cap < total;
+  if (grow) {
+    cap = L.cap > t->cfg.buffer_size ? L.cap : t->cfg.buffer_size;
+    while (cap < total) cap *= 2;
+    rec = (float*)dmalloc(t, (size_t)(cap + kRecPad) * t->S * 4);
+    nodes = rec ? (float*)dmalloc(t, (size_t)(2 * cap) * t->NS * 4) : nullptr;
+    if (!nodes) {
+      dfree(t, rec);
+      return fail(BDL_ENOMEM, "cannot allocate the tree");
+    }
+  }
+  if (!ensure_build_scratch(t, (uint64_t)total)) {
+    if (grow) {
+      dfree(t, rec);
+      dfree(t, nodes);
+    }
+    return fail(BDL_ENOMEM, "cannot allocate build scratch");
+  }
+  BuildScratch& sc = t->sc;
+  JobTable jt;
+  std::memset(&jt, 0, sizeof(jt));
+  jt.n = 1;
+  jt.jobs[0].base = 0;
+  jt.jobs[0].count = (uint32_t)total;
+  jt.jobs[0].level = 0;
+  jt.jobs[0].write_map = 1;
+  jt.jobs[0].rec = rec;
+  jt.jobs[0].nodes = nodes;
+  jt.jobs[0].node_cap = (uint32_t)(2 * cap);
+  // ---- gather (every source is read into the build buffers before the
+  // build writes the tree, so the tree may be rebuilt in its own arena) ----
+  t->pt.begin(BDL_PH_GATHER);
+  if (keep) {
+    if (L.live == L.n_slots)
+      launch_records_to_soa(L.rec, t->d, (uint64_t)L.n_slots, sc.soa[0], sc.cap, 0, t->s);
+    else
+      launch_compact_live(L.rec, t->d, (uint64_t)L.n_slots, sc.soa[0], sc.cap, 0, nullptr,
+                          sc.tile_cnt, sc.tmp, t->s);
+  }
+  if (n) {
+    PoolSrc ps;
+    ps.bufrec = nullptr;
+    ps.bn = 0;
+    ps.batch = batch;
+    ps.batch_ids = batch_ids;
+    ps.n = (uint64_t)n;
+    launch_pool_to_soa(ps, t->d, 0, (uint64_t)n, sc.soa[0], sc.cap, (uint64_t)keep, t->s);
+  }
+  t->pt.end(BDL_PH_GATHER);
+  const char* err = nullptr;
+  int base_depths = 0;
+  int rc = run_build(jt, sc, t->d, (uint32_t)t->cfg.leaf_size, t->T, t->rule, t->depth_ratio,
+                     t->map, t->cfg.id_capacity, t->s, t->d_level_nodes, t->d_misc + 9,
+                     &base_depths, &t->host_waits, &err, t->pt);
+  if (rc) {
+    if (grow) {
+      (void)wait_stream(t);
+      dfree(t, rec);
+      dfree(t, nodes);
+    }
+    return fail(rc, err ? err : "build failed");
+  }
+  if (grow && L.rec) {
+    (void)wait_stream(t);
+    dfree(t, L.rec);
+    dfree(t, L.nodes);
+  }
+  L.rec = rec;
+  L.nodes = nodes;
+  L.cap = cap;
+  L.on = true;
+  L.n_slots = L.live = total;
+  L.n_nodes = -1;
+  L.bloom_ok = false;
+  publish_nodes(t, base_depths);
+  t->F = 1;
+  t->rebuilt += total;
   upload_live(t);
   upload_views(t);
   if (hipGetLastError() != hipSuccess) return fail(BDL_EHIP, "kernel launch failed in insert");
@@ -543,18 +840,20 @@ LevelViews make_views(const bdl_tree* t) {
   std::memset(&v, 0, sizeof(v));
   for (int i = kMaxLevels - 1; i >= 0; --i) {
     const LevelState& L = t->lev[i];
-    if (!L.on || L.n_nodes == 0) continue;
+    if (!L.on || L.n_slots == 0) continue;
     v.v[v.n].rec = L.rec;
     v.v[v.n].nodes = L.nodes;
     v.v[v.n].n_slots = (uint32_t)L.n_slots;
-    v.v[v.n].n_nodes = (uint32_t)L.n_nodes;
+    v.v[v.n].n_nodes = 0;  // set on the device from the published counts
+    v.v[v.n].level = (uint32_t)i;
     ++v.n;
   }
-  if (t->bn > 0 && t->b_nodes > 0) {
+  if (t->bn > 0) {
     v.v[v.n].rec = t->brec;
     v.v[v.n].nodes = t->bnodes;
     v.v[v.n].n_slots = (uint32_t)t->bn;
-    v.v[v.n].n_nodes = (uint32_t)t->b_nodes;
+    v.v[v.n].n_nodes = 0;
+    v.v[v.n].level = (uint32_t)kMaxLevels;
     ++v.n;
   }
   return v;
@@ -590,7 +889,7 @@ bool ensure_batch_scratch(bdl_tree* t, uint64_t cap) {
     for (void* p : ps) dfree(t, p);
     return false;
   }
-  (void)hipStreamSynchronize(t->s);
+  (void)wait_stream(t);
   destroy_graphs(t);
   void* old[] = {t->bq, t->bqreq, t->bqs.keys[0], t->bqs.keys[1], t->bqs.vals[0],
                  t->bqs.vals[1], t->bqs.tmp, t->bqs.box};
@@ -623,9 +922,17 @@ KnnLaunch choose_launch(const bdl_tree* t, int kmax, uint64_t nq, bool* sort) {
   KnnLaunch L;
   L.mode = t->knn_mode;
   // the wavefront-per-query kernel keeps node indices in 26 bits
-  uint64_t max_nodes = (uint64_t)t->b_nodes;
+  resolve_nodes(const_cast<bdl_tree*>(t), false);
+  // a count still on the device is bounded by 2 slots - 1
+  auto nodes_of = [](int64_t nn, int64_t slots) -> uint64_t {
+    return nn >= 0 ? (uint64_t)nn : (uint64_t)(2 * slots);
+  };
+  uint64_t max_nodes = t->bn ? nodes_of(t->b_nodes, t->bn) : 0;
   for (int i = 0; i < kMaxLevels; ++i)
-    if (t->lev[i].on && (uint64_t)t->lev[i].n_nodes > max_nodes) max_nodes = t->lev[i].n_nodes;
+    if (t->lev[i].on) {
+      const uint64_t m = nodes_of(t->lev[i].n_nodes, t->lev[i].n_slots);
+      if (m > max_nodes) max_nodes = m;
+    }
   const bool query_ok = max_nodes < kKnnQueryMaxNodes;
   if (L.mode == kKnnAuto) {
     // a small batch leaves the device idle with one lane per query: one
@@ -633,8 +940,13 @@ KnnLaunch choose_launch(const bdl_tree* t, int kmax, uint64_t nq, bool* sort) {
     // off when the queries are dense among the points (queries adjacent on
     // the Hilbert curve then share most of their paths); otherwise sparse
     // queries take one lane each
+    // In five or more dimensions the 64 queries of a group no longer share
+    // their paths (a Hilbert cell of the group spans little of each
+    // dimension), and one wavefront per query wins at every batch size
+    // (7D clustered, 9M queries: 1.15 s against 2.56 s for the group kernel
+    // and 1.73 s for one lane per query).
     const int64_t live = bdl_size(t);
-    if (nq <= t->query_max && query_ok)
+    if ((nq <= t->query_max || t->d >= 5) && query_ok)
       L.mode = kKnnQuery;
     else
       L.mode = (nq >= 65536 && (int64_t)nq * 2 >= live) ? kKnnWave : kKnnLane;
@@ -798,6 +1110,8 @@ int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out) {
   if (cfg->buffer_size < 1 || cfg->buffer_size > (1 << 24))
     return fail(BDL_EINVAL, "buffer_size must be in 1..2^24");
   if (cfg->id_capacity < 1) return fail(BDL_EINVAL, "id_capacity must be >= 1");
+  if ((cfg->flags & BDL_FLAG_REBUILD_ALL) && (cfg->flags & BDL_FLAG_NO_REBUILD))
+    return fail(BDL_EINVAL, "BDL_FLAG_REBUILD_ALL and BDL_FLAG_NO_REBUILD exclude each other");
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(BDL_EHIP, "no HIP device");
   bdl_tree* t = new bdl_tree();
@@ -805,6 +1119,10 @@ int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out) {
   t->s = (hipStream_t)stream;
   t->dev = dev;
   t->noalloc_scratch = scratch_on(dev);
+  t->rule = (cfg->flags & BDL_FLAG_OBJECT_MEDIAN) ? kSplitObject : kSplitSpatial;
+  t->mode = (cfg->flags & BDL_FLAG_REBUILD_ALL)  ? kModeRebuildAll
+            : (cfg->flags & BDL_FLAG_NO_REBUILD) ? kModeNoRebuild
+                                                 : kModeBdl;
   t->d = cfg->dim;
   t->S = rec_stride(cfg->dim);
   t->NS = node_stride(cfg->dim);
@@ -814,6 +1132,7 @@ int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out) {
     t->pt.mark = phase_mark;
   }
   t->map = (uint64_t*)dmalloc(t, (size_t)cfg->id_capacity * 8);
+  t->d_level_nodes = (uint32_t*)dmalloc(t, (kMaxLevels + 2) * 4);
   t->d_live = (uint32_t*)dmalloc(t, kMaxLevels * 4);
   t->d_misc = (uint32_t*)dmalloc(t, 16 * 4);
   t->d_stats = (unsigned long long*)dmalloc(t, 8 * 8);
@@ -823,8 +1142,8 @@ int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out) {
   t->bcount = (uint64_t*)dmalloc(t, 2 * sizeof(uint64_t));
   t->sc.ctr = (BuildCounters*)dmalloc(t, sizeof(BuildCounters));
   t->sc.jobs = (Job*)dmalloc(t, sizeof(Job) * kMaxJobs);
-  bool ok = t->map && t->d_live && t->d_misc && t->d_stats && t->d_views && t->d_queue && t->breqs &&
-            t->bcount && t->sc.ctr && t->sc.jobs;
+  bool ok = t->map && t->d_level_nodes && t->d_live && t->d_misc && t->d_stats && t->d_views &&
+            t->d_queue && t->breqs && t->bcount && t->sc.ctr && t->sc.jobs;
   for (int i = 0; ok && i < 2; ++i) {
     if (hipHostMalloc((void**)&t->h_breqs[i], sizeof(KnnReqDev) * kMaxBatchReqs,
                       hipHostMallocDefault) != hipSuccess ||
@@ -841,16 +1160,21 @@ int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out) {
   if (ok && hipHostMalloc((void**)&t->sc.host_ctr, sizeof(BuildCounters), hipHostMallocDefault) !=
                 hipSuccess)
     ok = false;
+  if (ok && hipHostMalloc((void**)&t->h_level_nodes, (kMaxLevels + 2) * 4,
+                          hipHostMallocDefault) != hipSuccess)
+    ok = false;
+  if (ok && hipEventCreateWithFlags(&t->ev_nodes, hipEventDisableTiming) != hipSuccess) ok = false;
   if (!ok) {
     bdl_destroy(t);
     return fail(BDL_ENOMEM, "cannot allocate the tree");
   }
   launch_fill_u32((uint32_t*)t->map, 0xFFFFFFFFu, (uint64_t)cfg->id_capacity * 2, t->s);
   launch_fill_u32(t->d_live, 0u, kMaxLevels, t->s);
+  launch_fill_u32(t->d_level_nodes, 0u, kMaxLevels + 2, t->s);
   launch_fill_u32(t->d_misc, 0u, 16, t->s);
   launch_fill_u32((uint32_t*)t->d_stats, 0u, 16, t->s);
   if (ok) upload_views(t);
-  if (hipStreamSynchronize(t->s) != hipSuccess) {
+  if (wait_stream(t) != hipSuccess) {
     bdl_destroy(t);
     return fail(BDL_EHIP, "stream synchronisation failed");
   }
@@ -860,7 +1184,7 @@ int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out) {
 
 void bdl_destroy(bdl_tree* t) {
   if (!t) return;
-  (void)hipStreamSynchronize(t->s);
+  (void)wait_stream(t);
   std::vector<void*> ps;
   for (auto& kv : t->sizes) ps.push_back(kv.first);
   for (void* p : ps) dfree(t, p);
@@ -877,6 +1201,8 @@ void bdl_destroy(bdl_tree* t) {
     if (e) (void)hipEventDestroy(e);
   if (t->h_pin) (void)hipHostFree(t->h_pin);
   if (t->sc.host_ctr) (void)hipHostFree(t->sc.host_ctr);
+  if (t->h_level_nodes) (void)hipHostFree(t->h_level_nodes);
+  if (t->ev_nodes) (void)hipEventDestroy(t->ev_nodes);
   delete t;
 }
 
@@ -910,6 +1236,10 @@ int bdl_set_param(bdl_tree* t, int32_t param, int64_t value) {
       if (value < 0) return fail(BDL_EINVAL, "query_max must be >= 0");
       t->query_max = (uint64_t)value;
       return 0;
+    case BDL_PARAM_ERASE_ROUTE:
+      if (value != 0 && value != 1) return fail(BDL_EINVAL, "erase_route is 0 or 1");
+      t->erase_route = (int)value;
+      return 0;
     case BDL_PARAM_PERSISTENT:
       if (value < 0 || value > 2) return fail(BDL_EINVAL, "persistent is 0, 1 or 2");
       t->persistent = (int)value;
@@ -940,6 +1270,7 @@ int bdl_clear(bdl_tree* t) {
     LevelState& L = t->lev[i];
     L.on = false;
     L.n_slots = L.live = L.n_nodes = 0;
+    L.bloom_ok = false;
   }
   t->F = 0;
   t->bn = 0;
@@ -954,7 +1285,7 @@ int bdl_clear(bdl_tree* t) {
 
 int bdl_profile(bdl_tree* t, bdl_profile_t* out, int reset) {
   if (!t) return fail(BDL_EINVAL, "null tree");
-  if (hipStreamSynchronize(t->s) != hipSuccess) return fail(BDL_EHIP, "stream error");
+  if (wait_stream(t) != hipSuccess) return fail(BDL_EHIP, "stream error");
   resolve_events(t);
   unsigned long long st[3] = {0, 0, 0};
   if (hipMemcpy(st, t->d_stats, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
@@ -974,22 +1305,39 @@ int bdl_profile(bdl_tree* t, bdl_profile_t* out, int reset) {
       t->prof_calls[i] = 0;
     }
     launch_fill_u32((uint32_t*)t->d_stats, 0u, 16, t->s);
-    (void)hipStreamSynchronize(t->s);
+    (void)wait_stream(t);
   }
   return 0;
 }
 
+// Device-side error words: [8] k-NN traversal (an out-of-range tree index,
+// or a route past the tree in B2's insert), [9] builds (scratch overflow, a
+// build that did not end).  Read by the calls that wait anyway; a word that
+// is set is cleared and reported.
+int check_device_errors(bdl_tree* t) {
+  const uint32_t knn = t->h_pin[kMaxLevels + 8], build = t->h_pin[kMaxLevels + 9];
+  if (!knn && !build) return 0;
+  launch_fill_u32(t->d_misc + 8, 0u, 2, t->s);
+  (void)wait_stream(t);
+  if (build)
+    return fail(BDL_EHIP, (build & 1024u) ? "a build did not end (a node stayed above the LDS size)"
+                                          : "build scratch overflow");
+  return fail(BDL_EHIP, "k-NN traversal met an out-of-range tree index");
+}
+
 int bdl_sync(bdl_tree* t) {
   if (!t) return fail(BDL_EINVAL, "null tree");
-  if (hipMemcpyAsync(t->h_pin + kMaxLevels + 8, t->d_misc + 8, 4, hipMemcpyDeviceToHost, t->s) !=
+  if (hipMemcpyAsync(t->h_pin + kMaxLevels + 8, t->d_misc + 8, 8, hipMemcpyDeviceToHost, t->s) !=
           hipSuccess ||
-      hipStreamSynchronize(t->s) != hipSuccess)
+      wait_stream(t) != hipSuccess)
     return fail(BDL_EHIP, "stream error");
-  if (t->h_pin[kMaxLevels + 8]) {
-    launch_fill_u32(t->d_misc + 8, 0u, 1, t->s);
-    (void)hipStreamSynchronize(t->s);
-    return fail(BDL_EHIP, "k-NN traversal met an out-of-range tree index");
-  }
+  resolve_nodes(t, false);
+  return check_device_errors(t);
+}
+
+int bdl_host_waits(const bdl_tree* t, int64_t* waits) {
+  if (!t || !waits) return fail(BDL_EINVAL, "null argument");
+  *waits = t->host_waits;
   return 0;
 }
 
@@ -1003,7 +1351,7 @@ int bdl_insert(bdl_tree* t, const float* pts, const uint32_t* ids, int64_t n) {
     launch_fill_u32(t->d_misc + 4, 0u, 3, t->s);
     launch_validate(pts, ids, (uint64_t)n, t->d, t->map, t->cfg.id_capacity, t->d_misc + 4, t->s);
     if (hipMemcpyAsync(t->h_pin, t->d_misc + 4, 12, hipMemcpyDeviceToHost, t->s) != hipSuccess ||
-        hipStreamSynchronize(t->s) != hipSuccess)
+        wait_stream(t) != hipSuccess)
       return fail(BDL_EHIP, "input validation failed to run");
     if (t->h_pin[0]) return fail(BDL_EINVAL, "ids must be < id_capacity");
     if (t->h_pin[1]) return fail(BDL_EINVAL, "an inserted id is already live");
@@ -1021,14 +1369,14 @@ int bdl_erase(bdl_tree* t, const float* pts, const uint32_t* ids, int64_t n, int
   // Erase_L's R holds at most half of the static trees' capacity; reserve it
   // before anything changes so that ENOMEM leaves the tree unchanged.
   int64_t half = 0;
-  for (int i = 0; i < kMaxLevels; ++i)
+  for (int i = 0; i < kMaxLevels && t->mode == kModeBdl; ++i)
     if (t->lev[i].on) half += t->lev[i].cap / 2;
   if (half > t->rbuf_cap) {
     int64_t cap = t->rbuf_cap ? t->rbuf_cap : 4096;
     while (cap < half) cap *= 2;
     float* nb = (float*)dmalloc(t, (size_t)cap * t->S * 4);
     if (!nb) return fail(BDL_ENOMEM, "cannot allocate the rebuild buffer");
-    (void)hipStreamSynchronize(t->s);
+    (void)wait_stream(t);
     dfree(t, t->rbuf);
     t->rbuf = nb;
     t->rbuf_cap = cap;
@@ -1044,22 +1392,76 @@ int bdl_erase(bdl_tree* t, const float* pts, const uint32_t* ids, int64_t n, int
     }
   et.pool = t->pool[t->pcur];
   et.bn = (uint32_t)t->bn;
+  RouteTable rt;
+  std::memset(&rt, 0, sizeof(rt));
+  if (t->erase_route) {
+    // filters first: ENOMEM here leaves the tree unchanged
+    for (int i = 0; i < kMaxLevels; ++i) {
+      LevelState& L = t->lev[i];
+      if (!L.on || L.n_slots == 0 || L.bloom_ok) continue;
+      const int lg = bloom_log2_for(L.n_slots);
+      if (!ensure_words(t, L.bloom, L.bloom_words, 1ll << lg))
+        return fail(BDL_ENOMEM, "cannot allocate a Bloom filter");
+    }
+    if (t->bn > 0 &&
+        !ensure_words(t, t->pool_bloom, t->pool_bloom_words, 1ll << bloom_log2_for(t->bn)))
+      return fail(BDL_ENOMEM, "cannot allocate a Bloom filter");
+  }
   launch_fill_u32(t->d_misc, 0u, 2, t->s);
   t->pt.begin(BDL_PH_ERASE);
-  launch_erase(pts, ids, (uint64_t)n, t->d, t->map, t->cfg.id_capacity, et, t->d_live, t->d_misc,
-               t->s);
+  if (t->erase_route) {
+    for (int i = 0; i < kMaxLevels; ++i) {
+      LevelState& L = t->lev[i];
+      if (!L.on || L.n_slots == 0) continue;
+      if (!L.bloom_ok) {
+        L.bloom_log2 = bloom_log2_for(L.n_slots);
+        launch_bloom_build(L.rec, (uint64_t)L.n_slots, t->d, L.bloom, L.bloom_log2, t->s);
+        L.bloom_ok = true;
+      }
+      rt.nodes[i] = L.nodes;
+      rt.bloom[i] = L.bloom;
+      rt.bloom_log2[i] = (uint8_t)L.bloom_log2;
+    }
+    if (t->bn > 0) {
+      rt.pool_bloom_log2 = (uint32_t)bloom_log2_for(t->bn);
+      launch_bloom_build(et.pool, (uint64_t)t->bn, t->d, t->pool_bloom, (int)rt.pool_bloom_log2,
+                         t->s);
+      rt.pool_bloom = t->pool_bloom;
+    }
+    rt.level_nodes = t->d_level_nodes;
+    launch_erase_routed(pts, ids, (uint64_t)n, t->d, t->map, t->cfg.id_capacity, et, rt,
+                        t->d_live, t->d_misc, t->s);
+  } else {
+    launch_erase(pts, ids, (uint64_t)n, t->d, t->map, t->cfg.id_capacity, et, t->d_live,
+                 t->d_misc, t->s);
+  }
   t->pt.end(BDL_PH_ERASE);
   if (hipMemcpyAsync(t->h_pin, t->d_live, kMaxLevels * 4, hipMemcpyDeviceToHost, t->s) !=
           hipSuccess ||
-      hipMemcpyAsync(t->h_pin + kMaxLevels, t->d_misc, 8, hipMemcpyDeviceToHost, t->s) !=
+      hipMemcpyAsync(t->h_pin + kMaxLevels, t->d_misc, 10 * 4, hipMemcpyDeviceToHost, t->s) !=
           hipSuccess ||
-      hipStreamSynchronize(t->s) != hipSuccess)
+      wait_stream(t) != hipSuccess)
     return fail(BDL_EHIP, "erase failed");
+  resolve_nodes(t, false);  // every build's copy has arrived
+  if (int rc = check_device_errors(t)) return rc;
   const uint32_t erased = t->h_pin[kMaxLevels];
   const uint32_t bufhits = t->h_pin[kMaxLevels + 1];
   for (int i = 0; i < kMaxLevels; ++i)
     if (t->lev[i].on) t->lev[i].live = t->h_pin[i];
   if (n_erased) *n_erased = erased;
+  if (t->mode != kModeBdl) {
+    // the baselines: B1 rebuilds its tree from the survivors after every
+    // erase that hit; B2 keeps the tombstones (no buffer in either)
+    if (t->mode == kModeRebuildAll && erased > 0) {
+      int rc = insert_single(t, nullptr, nullptr, 0, 0);
+      if (rc) return rc;
+    } else {
+      upload_live(t);
+      upload_views(t);
+    }
+    if (hipGetLastError() != hipSuccess) return fail(BDL_EHIP, "kernel launch failed in erase");
+    return 0;
+  }
   if (bufhits) {
     // the buffer keeps its arrival order and shrinks (no half rule)
     launch_compact_live(t->pool[t->pcur], t->d, (uint64_t)t->bn, nullptr, 0, 0,
@@ -1198,7 +1600,7 @@ int bdl_level_info(const bdl_tree* t, int32_t* nlev, int64_t* live, int64_t* cap
   if (nlev) *nlev = top;
   for (int i = 0; i < top; ++i) {
     if (live) live[i] = t->lev[i].on ? t->lev[i].live : 0;
-    if (cap) cap[i] = level_cap(t, i);
+    if (cap) cap[i] = t->mode == kModeBdl ? level_cap(t, i) : t->lev[i].cap;
   }
   if (buf_live) *buf_live = t->bn;
   if (F) *F = t->F;
@@ -1208,6 +1610,7 @@ int bdl_level_info(const bdl_tree* t, int32_t* nlev, int64_t* live, int64_t* cap
 int bdl_level_sizes(const bdl_tree* t, int32_t* nlev, int64_t* n_slots, int64_t* n_nodes,
                     int64_t* buf_nodes) {
   if (!t) return fail(BDL_EINVAL, "null tree");
+  resolve_nodes(const_cast<bdl_tree*>(t), true);
   int top = 0;
   for (int i = 0; i < kMaxLevels; ++i)
     if (t->lev[i].on) top = i + 1;
@@ -1230,6 +1633,7 @@ int bdl_counters(const bdl_tree* t, int64_t* rebuilt_points, int64_t* reinserted
 int bdl_debug_export_level(bdl_tree* t, int32_t level, uint32_t* ids, float* pts,
                            bdl_node* nodes, int64_t* n_slots, int64_t* n_nodes) {
   if (!t) return fail(BDL_EINVAL, "null tree");
+  resolve_nodes(t, true);
   const float* rec;
   const float* nd;
   int64_t ns, nn;
@@ -1251,7 +1655,7 @@ int bdl_debug_export_level(bdl_tree* t, int32_t level, uint32_t* ids, float* pts
   if (ns == 0) return level == -1 ? 0 : fail(BDL_EINVAL, "empty tree");
   const int d = t->d, S = t->S, NS = t->NS;
   std::vector<float> hr((size_t)ns * S), hn((size_t)nn * NS);
-  if (hipStreamSynchronize(t->s) != hipSuccess ||
+  if (wait_stream(t) != hipSuccess ||
       hipMemcpy(hr.data(), rec, hr.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
       (nn && hipMemcpy(hn.data(), nd, hn.size() * 4, hipMemcpyDeviceToHost) != hipSuccess))
     return fail(BDL_EHIP, "export copy failed");
@@ -1319,7 +1723,7 @@ int bdl_debug_export_buffer(bdl_tree* t, uint32_t* ids, float* pts, int64_t* n) 
   if (t->bn == 0) return 0;
   const int d = t->d, S = t->S;
   std::vector<float> hr((size_t)t->bn * S);
-  if (hipStreamSynchronize(t->s) != hipSuccess ||
+  if (wait_stream(t) != hipSuccess ||
       hipMemcpy(hr.data(), t->pool[t->pcur], hr.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
     return fail(BDL_EHIP, "export copy failed");
   for (int64_t i = 0; i < t->bn; ++i) {
