@@ -79,6 +79,49 @@ def _pct(xs, p):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), p)) if xs else None
 
 
+def traversal_kernel(mode: int, d: int, nq: int, live: int) -> str:
+    """The traversal kernel a plain bdl_knn launch runs (BDL_PARAM_KNN_KERNEL;
+    2 is the library's default choice for one launch of nq queries)."""
+    if mode == 2:
+        if d >= 5 or nq <= 131072:
+            mode = 3
+        else:
+            mode = 1 if (nq >= 65536 and 2 * nq >= live) else 0
+    return {0: "k_knn", 1: "k_knn_wave", 3: "k_knn_query"}[mode]
+
+
+def knn_graph_leg(torch, tree, out_ids, out_d2, qids, k, stream):
+    """The step's k-NN rows (every live point as a query) through
+    bdl_knn_graph, whose searches start from each point's own leaves:
+    device time of the whole call (group list and traversal) against the
+    step's kNN_L, and the rows compared with kNN_L's bit for bit."""
+    gi = torch.empty((tree.id_capacity, k), dtype=torch.int32, device=out_ids.device)
+    gd = torch.empty((tree.id_capacity, k), dtype=torch.float32, device=out_ids.device)
+    ms = []
+    tree.sync()
+    tree.profile(reset=True)
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        tree.knn_graph(k, gi, gd)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    rows = qids.to(torch.int64)
+    same = bool(torch.equal(gi[rows], out_ids)) and \
+        bool(torch.equal(gd[rows].view(torch.int32), out_d2.view(torch.int32)))
+    t = float(np.median(ms))
+    tree.sync()
+    prof = tree.profile(reset=True)
+    nq = qids.shape[0]
+    del gi, gd
+    return {"ms": t, "queries_per_s": nq / (t * 1e-3), "calls_ms": ms,
+            "groups_and_order_ms": prof["order"]["ms"] / 3,
+            "traverse_ms": prof["traverse"]["ms"] / 3,
+            "work_per_query": {kk: v / (3 * nq) for kk, v in prof["knn_work"].items()},
+            "rows_equal_knn": same}
+
+
 def erase_route_leg(torch, bdl, tree, inserts, erases, stream):
     """The step's erases located through the id map and, as Erase_S with
     per-tree Bloom filters (Section V-A), by routing each point down the
@@ -201,10 +244,13 @@ def gpu_bench(args):
     own = qids.to(torch.int64) & 0xFFFFFFFF
     self_ok = bool((out_d2[:, 0] == 0).all()) and bool((first <= own).all())
     self_exact = float((first == own).to(torch.float32).mean())
+    graph_leg = knn_graph_leg(torch, tree, out_ids, out_d2, qids, k, stream) if args.extra \
+        else None
     counters = tree.counters()
 
     info = tree.level_info()
     sizes = tree.level_sizes()
+    bdl_live = int(info["live"].sum()) + int(info["buf_live"])
     S = (w.dim + 1 + 3) & ~3
     NS = (5 + 2 * w.dim + 3) & ~3
     tree_bytes = int(sizes["slots"].sum()) * S * 4 + int(sizes["nodes"].sum()) * NS * 4
@@ -249,6 +295,7 @@ def gpu_bench(args):
         "insert_pts_per_s": n_ins / (ins_ms * 1e-3),
         "erase_pts_per_s": n_er / (er_ms * 1e-3),
         "erase_route": route_leg,
+        "knn_graph": graph_leg,
         "sequential_call_latency_ms": {kind: {"p50": _pct(v, 50), "p99": _pct(v, 99), "n": len(v)}
                        for kind, v in lat.items()},
         "phase_ms_per_step": {kname: v["ms"] / args.steps for kname, v in prof.items()
@@ -264,7 +311,7 @@ def gpu_bench(args):
                             "achieved": ins_bytes / (ins_ms * 1e-3) / 1e9,
                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": ins_bytes / (ins_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
-        "roofline": {"kernel": ("k_knn" if args.knn_kernel == 0 else "k_knn_wave")
+        "roofline": {"kernel": traversal_kernel(args.knn_kernel, w.dim, nq, bdl_live)
                      + " (kNN_L traversal)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),

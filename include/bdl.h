@@ -78,7 +78,8 @@ extern "C" {
 #define BDL_PH_FINISH 2    /* Insert_L: LDS subtree finisher */
 #define BDL_PH_LAYOUT 3    /* Insert_L: vEB ordering and node write-out */
 #define BDL_PH_ERASE 4     /* Erase_L: locate and tombstone */
-#define BDL_PH_ORDER 5     /* kNN_L: Hilbert-curve ordering of the queries */
+#define BDL_PH_ORDER 5     /* kNN_L: Hilbert-curve ordering of the queries
+                              (bdl_knn_graph: its group list) */
 #define BDL_PH_TRAVERSE 6  /* kNN_L: the traversal kernel */
 #define BDL_NPHASES 8
 
@@ -148,6 +149,20 @@ int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_id
  * runtime could not resolve the array's address on the tree's GPU. */
 int bdl_knn_noalloc(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_ids,
                     float* out_d2);
+
+/* The k-NN graph of the live points: kNN_L (Alg. 5) with every live point
+ * as a query, each search started from the query's own leaves (the
+ * leaf-based search of Section II) instead of the root.  Row `id` of out_ids
+ * and out_d2 (device, [id_capacity][k] row-major, caller-owned) receives the
+ * k nearest live points of live point `id`, sorted by (squared distance, id)
+ * and padded as bdl_knn: exactly the row bdl_knn returns for that point as
+ * a query (the point itself comes first at 0 unless another live point has
+ * the same coordinates and a smaller id).  Rows of ids that are not live are
+ * not written.  Asynchronous; the outputs must stay allocated until the
+ * stream passes the call.  Allocates a group list of about 16 bytes per
+ * stored point on first use (BDL_ENOMEM if it cannot).  BDL_EINVAL for k
+ * outside 1..64 or a null output. */
+int bdl_knn_graph(bdl_tree* t, int32_t k, uint32_t* out_ids, float* out_d2);
 
 /* Tuning parameters (bdl_set_param).  They change speed, never results. */
 #define BDL_PARAM_KNN_KERNEL 1 /* 0: one lane per query; 1: one wavefront per

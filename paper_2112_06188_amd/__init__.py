@@ -34,6 +34,7 @@ EXPORTS = [
     "bdl_set_param", "bdl_knn_batch", "bdl_set_knn_shapes",
     "bdl_server_create", "bdl_server_submit", "bdl_server_wait", "bdl_server_poll",
     "bdl_server_drain", "bdl_server_destroy", "bdl_knn_noalloc", "bdl_host_waits",
+    "bdl_knn_graph",
 ]
 REQ_KNN, REQ_INSERT, REQ_ERASE = 0, 1, 2
 SERVE_FIFO, SERVE_BATCHED = 0, 1
@@ -152,6 +153,7 @@ def load_library(path: Optional[str] = None):
     lib.bdl_erase.argtypes = [vp, vp, vp, i64, i64p]
     lib.bdl_knn.argtypes = [vp, vp, i64, i32, vp, vp]
     lib.bdl_knn_noalloc.argtypes = [vp, vp, i64, i32, vp, vp]
+    lib.bdl_knn_graph.argtypes = [vp, i32, vp, vp]
     lib.bdl_sync.argtypes = [vp]
     lib.bdl_clear.argtypes = [vp]
     lib.bdl_set_param.argtypes = [vp, i32, i64]
@@ -334,6 +336,26 @@ class Tree:
         """kNN_L through bdl_knn_noalloc (no device allocation by the library;
         at most 1048576 queries per call)."""
         return self._knn(self._lib.bdl_knn_noalloc, q, k, out_ids, out_d2)
+
+    def knn_graph(self, k: int, out_ids=None, out_d2=None):
+        """The k-NN graph of the live points (bdl_knn_graph): row `id` of
+        (ids int32 [id_capacity, k], squared distances float32 [id_capacity,
+        k]) holds the row kNN_L returns for live point `id` as a query.
+        Rows of ids that are not live are left as they were: when the
+        outputs are allocated here, ids -1 and distances +inf."""
+        torch = _torch()
+        n = self.id_capacity
+        if out_ids is None:
+            out_ids = torch.full((n, k), -1, dtype=torch.int32, device=self.device)
+        if out_d2 is None:
+            out_d2 = torch.full((n, k), float("inf"), dtype=torch.float32, device=self.device)
+        out_ids = self._out(out_ids, n, k, torch.int32, "out_ids")
+        out_d2 = self._out(out_d2, n, k, torch.float32, "out_d2")
+        with torch.cuda.device(self.device):
+            _check(self._lib.bdl_knn_graph(self._h, int(k), ctypes.c_void_p(out_ids.data_ptr()),
+                                           ctypes.c_void_p(out_d2.data_ptr())))
+            self._keep_on_stream(out_ids, out_d2)
+        return out_ids, out_d2
 
     def _knn(self, fn, q, k: int, out_ids, out_d2):
         torch = _torch()

@@ -14,7 +14,9 @@ OUT = os.path.join(HERE, "libbdl.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["knn_d1_4.hip", "knn_d5_8.hip", "knn_d9_12.hip", "knn_d13_16.hip", "build.hip",
-           "primitives.hip", "knn.hip", "erase.hip", "tree.hip", "server.hip", "baseline.hip"]
+           "primitives.hip", "knn.hip", "erase.hip", "tree.hip", "server.hip", "baseline.hip",
+           "knn_graph.hip", "knn_graph_d1_4.hip", "knn_graph_d5_8.hip", "knn_graph_d9_12.hip",
+           "knn_graph_d13_16.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -6,9 +6,11 @@
 //    floats so that a record is a whole number of 16-byte vectors.  Static
 //    trees store their points as records in slot order (leaves contiguous).
 //  * node: `node_stride(d)` floats: [split, dim, a, b, parent, lo[d], hi[d]]
-//    padded to a multiple of 4.  dim < 0 marks a leaf, whose a/b are the
-//    slot range begin/count; an internal node's a/b are its children.
-//    Nodes of one tree are stored in van Emde Boas order (Alg. 1).
+//    padded to a multiple of 4; the last word (always padding, since 5 + 2d
+//    is odd) holds the number of points under the node when it was built,
+//    as uint32 bits.  dim < 0 marks a leaf, whose a/b are the slot range
+//    begin/count; an internal node's a/b are its children.  Nodes of one
+//    tree are stored in van Emde Boas order (Alg. 1).
 //  * build buffers: structure of arrays, coordinate j of position i at
 //    soa[j * cap + i], id at soa[d * cap + i].
 #pragma once
@@ -38,6 +40,8 @@ __host__ __device__ inline int node_stride(int d) { return (5 + 2 * d + 3) & ~3;
 __host__ __device__ inline int emit_stride(int d) { return (10 + 2 * d + 1) & ~1; }
 
 enum NodeField { NF_SPLIT = 0, NF_DIM = 1, NF_A = 2, NF_B = 3, NF_PARENT = 4, NF_BOX = 5 };
+// index of a node's point count (build time; B2 inserts leave it unchanged)
+__host__ __device__ inline int node_count_field(int d) { return node_stride(d) - 1; }
 // emitted (unordered) node: u32 words
 enum EmitField {
   EF_PATH_LO = 0, EF_PATH_HI = 1, EF_DEPTH = 2, EF_JOB = 3, EF_PARENT = 4, EF_SIDE = 5,

@@ -459,6 +459,19 @@ __global__ void k_init_lists(const Job* jobs, int njobs, BuildCounters* c, Seg* 
 
 constexpr uint32_t kListLds = 4096;  // list entries whose tile starts stay in LDS
 
+// Left points of a tile before each of its quarters (eight rows of 64): the
+// counts before quarters 1, 2 and 3 (at most 512, 1024 and 1536) in 10, 11
+// and 11 bits, so that the scatter can hand each quarter to its own
+// wavefront.
+__device__ inline uint32_t pack_quarters(uint32_t l1, uint32_t l2, uint32_t l3) {
+  return l1 | (l2 << 10) | (l3 << 21);
+}
+__device__ inline uint32_t left_before_quarter(uint32_t packed, uint32_t q) {
+  return q == 0 ? 0u : q == 1 ? (packed & 0x3FFu) : q == 2 ? ((packed >> 10) & 0x7FFu)
+                                                           : (packed >> 21);
+}
+static_assert(kTile == 2048, "quarter counts are packed for tiles of 2048 points");
+
 // Left count of every tile: one wavefront per tile (ballots, no barriers),
 // so that all of a tile's loads are in flight at once.  Every wavefront of a
 // segment takes the segment's decision itself (leaf, or split dimension and
@@ -468,8 +481,8 @@ constexpr uint32_t kListLds = 4096;  // list entries whose tile starts stay in L
 __device__ __forceinline__ void count_tiles(Seg* cur, const uint32_t* tile_seg, BuildCounters* c,
                                             int par, const Job* jobs, uint32_t* emit, int es,
                                             int d, uint32_t leaf, const float* src, uint64_t cap,
-                                            uint32_t* tile_left, int rule, uint32_t wv,
-                                            uint32_t nwv) {
+                                            uint32_t* tile_left, uint32_t* tile_q, int rule,
+                                            uint32_t wv, uint32_t nwv) {
   const uint32_t nt = ld_ctr(&c->ntiles[par]);
   const uint32_t ebase = ld_ctr(&c->ebase[par]);
   const int lane = __lane_id();
@@ -494,31 +507,38 @@ __device__ __forceinline__ void count_tiles(Seg* cur, const uint32_t* tile_seg, 
       g.split = split;
     }
     if (dim < 0) {
-      if (lane == 0) tile_left[t] = 0;
+      if (lane == 0) {
+        tile_left[t] = 0;
+        tile_q[t] = 0;
+      }
       continue;
     }
     const uint64_t tstart = (uint64_t)g.begin + (uint64_t)(t - g.tile_begin) * kTile;
     const uint64_t tend = min((uint64_t)g.begin + g.count, tstart + kTile);
     const float* x = src + (uint64_t)dim * cap;
     // loads at a clamped index (always in the tile) so that none waits on
-    // a branch and all of them can be in flight together
-    uint32_t cnt = 0;
+    // a branch and all of them can be in flight together; counts per
+    // quarter of the tile (eight rows each)
+    uint32_t cq[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
     for (int r = 0; r < kTile / 64; ++r) {
       const uint64_t i = tstart + (uint64_t)r * 64 + lane;
       const float xv = x[i < tend ? i : tend - 1];
-      cnt += (uint32_t)__popcll(__ballot((i < tend) & (xv < split)));
+      cq[r / (kTile / 256)] += (uint32_t)__popcll(__ballot((i < tend) & (xv < split)));
     }
-    if (lane == 0) tile_left[t] = cnt;
+    if (lane == 0) {
+      tile_left[t] = cq[0] + cq[1] + cq[2] + cq[3];
+      tile_q[t] = pack_quarters(cq[0], cq[0] + cq[1], cq[0] + cq[1] + cq[2]);
+    }
   }
 }
 
 __global__ void __launch_bounds__(kPassThreads)
 k_count(Seg* cur, const uint32_t* tile_seg, BuildCounters* c, int par, const Job* jobs,
         uint32_t* emit, int es, int d, uint32_t leaf, const float* src, uint64_t cap,
-        uint32_t* tile_left, int rule) {
+        uint32_t* tile_left, uint32_t* tile_q, int rule) {
   constexpr int kWaves = kPassThreads / 64;
-  count_tiles(cur, tile_seg, c, par, jobs, emit, es, d, leaf, src, cap, tile_left, rule,
+  count_tiles(cur, tile_seg, c, par, jobs, emit, es, d, leaf, src, cap, tile_left, tile_q, rule,
               blockIdx.x * kWaves + (threadIdx.x >> 6), gridDim.x * kWaves);
 }
 
@@ -867,7 +887,8 @@ __device__ __forceinline__ void scatter_tiles(const Seg* cur, const uint32_t* ti
                                               const BuildCounters* c, int par,
                                               const float* __restrict__ src,
                                               float* __restrict__ dst, uint64_t cap,
-                                              const uint32_t* tile_off, const Job* jobs,
+                                              const uint32_t* tile_off,
+                                              const uint32_t* tile_q, const Job* jobs,
                                               uint64_t* map, uint32_t idcap, uint32_t blk,
                                               uint32_t nblk) {
   __shared__ uint32_t s_ch[kWaves][2];
@@ -883,18 +904,25 @@ __device__ __forceinline__ void scatter_tiles(const Seg* cur, const uint32_t* ti
   // and boxes (empty until then)
   if (lane < 2) s_ch[w][lane] = kNone;
   if (lane < 4 * D) s_bx[w][lane] = (lane & 1) ? 0u : 0xFFFFFFFFu;
-  for (uint32_t t = blk * kWaves + w; t < nt; t += nw) {
+  // work units are quarter tiles (eight rows), unit un = 4 * tile + quarter
+  const uint32_t nu = nt * 4u;
+  for (uint32_t un = blk * kWaves + w; un < nu; un += nw) {
+    const uint32_t t = un >> 2, qt = un & 3u;
     const uint32_t s = tile_seg[t];
     const Seg& g = cur[s];
     const uint64_t gbegin = g.begin;
     const uint64_t tstart = gbegin + (uint64_t)(t - g.tile_begin) * kTile;
     const uint64_t tend = min(gbegin + g.count, tstart + kTile);
     const uint32_t tcnt = (uint32_t)(tend - tstart);
+    // this unit's points: tile positions [i0, i1)
+    const uint32_t i0 = qt * (kTile / 4);
+    const uint32_t i1 = min(tcnt, i0 + (uint32_t)(kTile / 4));
+    if (i0 >= i1) continue;
     const int dim = g.dim;
     if (dim < 0) {
       const Job J = jobs[g.job];
       constexpr int S = (D + 1 + 3) & ~3;
-      for (uint32_t i = lane; i < tcnt; i += 64) {
+      for (uint32_t i = i0 + lane; i < i1; i += 64) {
         const uint64_t p = tstart + i;
         const uint64_t slot = p - J.base;
         float* rr = J.rec + slot * S;
@@ -920,17 +948,18 @@ __device__ __forceinline__ void scatter_tiles(const Seg* cur, const uint32_t* ti
       bx[j][2] = 0xFFFFFFFFu;
       bx[j][3] = 0u;
     }
-    uint32_t lrun = 0;  // left points in earlier rows
+    // left points in earlier rows of the tile (earlier quarters from the count)
+    uint32_t lrun = left_before_quarter(tile_q[t], qt);
     // groups of kRows rows: all loads of a group are issued before its
-    // stores (indices are clamped into the tile, so no load waits on a branch)
+    // stores (indices are clamped into the unit, so no load waits on a branch)
     constexpr int kRows = 4;
-    for (uint32_t r0 = 0; r0 * 64 < tcnt; r0 += kRows) {
+    for (uint32_t r0 = i0 / 64; r0 * 64 < i1; r0 += kRows) {
       float v[kRows][D];
       uint32_t idv[kRows];
 #pragma unroll
       for (int u = 0; u < kRows; ++u) {
         const uint32_t i = (r0 + u) * 64 + lane;
-        const uint64_t p = tstart + (i < tcnt ? i : tcnt - 1);
+        const uint64_t p = tstart + (i < i1 ? i : i1 - 1);
 #pragma unroll
         for (int j = 0; j < D; ++j) v[u][j] = src[(uint64_t)j * cap + p];
         idv[u] = sid[p];
@@ -938,7 +967,7 @@ __device__ __forceinline__ void scatter_tiles(const Seg* cur, const uint32_t* ti
 #pragma unroll
       for (int u = 0; u < kRows; ++u) {
         const uint32_t i = (r0 + u) * 64 + lane;
-        const bool in = i < tcnt;
+        const bool in = i < i1;
         float vd = 0.0f;
 #pragma unroll
         for (int j = 0; j < D; ++j) vd = j == dim ? v[u][j] : vd;
@@ -966,7 +995,7 @@ __device__ __forceinline__ void scatter_tiles(const Seg* cur, const uint32_t* ti
       wave_minmax(bx[j][2], bx[j][3]);
     }
     const uint32_t c0 = g.child[0], c1 = g.child[1];
-    if (t + nw < nt) {
+    if (un + nw < nu) {
       add_child_boxes<D>(nxt, c0, c1, bx, lane);
     } else {
       if (lane == 0) {
@@ -1008,9 +1037,10 @@ __global__ void __launch_bounds__(kScatterThreads)
 __attribute__((amdgpu_waves_per_eu(D <= 3 ? 8 : 1)))  // d <= 3 fits 64 VGPRs without spills
 k_scatter(const Seg* cur, const uint32_t* tile_seg, Seg* nxt, const BuildCounters* c, int par,
           const float* __restrict__ src, float* __restrict__ dst, uint64_t cap,
-          const uint32_t* tile_off, const Job* jobs, uint64_t* map, uint32_t idcap) {
+          const uint32_t* tile_off, const uint32_t* tile_q, const Job* jobs, uint64_t* map,
+          uint32_t idcap) {
   scatter_tiles<D, kScatterThreads / 64>(cur, tile_seg, nxt, c, par, src, dst, cap, tile_off,
-                                         jobs, map, idcap, blockIdx.x, gridDim.x);
+                                         tile_q, jobs, map, idcap, blockIdx.x, gridDim.x);
 }
 
 // Arguments of the depth loop (every buffer of the global passes).
@@ -1023,6 +1053,7 @@ struct PassArgs {
   const Job* jobs;
   uint32_t* emit;
   uint32_t* tile_left;
+  uint32_t* tile_q;
   uint32_t* tile_off;
   Fin* fin;
   uint64_t* map;
@@ -1060,7 +1091,7 @@ __global__ void __launch_bounds__(kScatterThreads) k_passes(PassArgs A) {
       }
     }
     count_tiles(A.seg[par], A.tile_seg[par], A.c, par, A.jobs, A.emit, A.es, A.d, A.leaf,
-                A.soa[par], A.cap, A.tile_left, A.rule, wv, nwv);
+                A.soa[par], A.cap, A.tile_left, A.tile_q, A.rule, wv, nwv);
     grid.sync();
     if (blockIdx.x == 0)
       tilescan_block(A.seg[par], A.seg[par ^ 1], A.c, par, A.tile_left, A.tile_off, A.fin, A.T,
@@ -1068,7 +1099,8 @@ __global__ void __launch_bounds__(kScatterThreads) k_passes(PassArgs A) {
                      A.max_tiles, A.max_emit);
     grid.sync();
     scatter_tiles<D, KW>(A.seg[par], A.tile_seg[par], A.seg[par ^ 1], A.c, par, A.soa[par],
-                         A.soa[par ^ 1], A.cap, A.tile_off, A.jobs, A.map, A.idcap, blockIdx.x,
+                         A.soa[par ^ 1], A.cap, A.tile_off, A.tile_q, A.jobs, A.map, A.idcap,
+                         blockIdx.x,
                          gridDim.x);
     grid.sync();
     par ^= 1;
@@ -1519,7 +1551,8 @@ __global__ void k_layout_write(const uint32_t* emit, int es, const BuildCounters
     if (dim < 0)
       *reinterpret_cast<float2*>(nd + NF_A) =
           make_float2(__uint_as_float(r[EF_BEGIN]), __uint_as_float(r[EF_COUNT]));
-    // words NF_PARENT.. (parent, box, zero padding) in 16-byte stores
+    // words NF_PARENT.. (parent, box, zero padding, point count) in 16-byte
+    // stores
     const int nbox = 2 * d;
     for (int q4 = NF_PARENT; q4 < NS; q4 += 4) {
       float v[4];
@@ -1527,6 +1560,7 @@ __global__ void k_layout_write(const uint32_t* emit, int es, const BuildCounters
       for (int u = 0; u < 4; ++u) {
         const int j = q4 + u;
         v[u] = j == NF_PARENT ? __int_as_float(parent == kNone ? -1 : (int)fp)
+             : j == NS - 1    ? __uint_as_float(r[EF_COUNT])
              : (j - NF_BOX < nbox ? __uint_as_float(r[EF_BOX + (j - NF_BOX)]) : 0.0f);
       }
       *reinterpret_cast<float4*>(nd + q4) = make_float4(v[0], v[1], v[2], v[3]);
@@ -1593,8 +1627,7 @@ void launch_scatter_d(unsigned grid, const BuildScratch& sc, int par, uint64_t* 
                       uint32_t idcap, hipStream_t s) {
   hipLaunchKernelGGL((k_scatter<D>), dim3(grid), dim3(kScatterThreads), 0, s, sc.seg[par],
                      sc.tile_seg[par], sc.seg[par ^ 1], sc.ctr, par, sc.soa[par], sc.soa[par ^ 1],
-                     sc.cap,
-                     sc.tile_off, sc.jobs, map, idcap);
+                     sc.cap, sc.tile_off, sc.tile_left + sc.max_tiles, sc.jobs, map, idcap);
 }
 
 void launch_scatter(int d, unsigned grid, const BuildScratch& sc, int par, uint64_t* map,
@@ -1810,9 +1843,9 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
   const unsigned pass_grid = grid_for(R, kTile, 2048);
   // one wavefront per segment of a depth (at most max_seg)
   const unsigned sel_grid = grid_for(sc.max_seg, kPassThreads / 64, 1024);
-  // two wavefronts of the scatter per tile of R points (a depth has at most
-  // R / kTile + segments tiles)
-  const unsigned scatter_grid = grid_for(R, kTile * (kScatterThreads / 128), 1024);
+  // four wavefronts of the scatter (one per quarter tile) per tile of R
+  // points (a depth has at most R / kTile + segments tiles)
+  const unsigned scatter_grid = grid_for(R, kTile * (kScatterThreads / 256), 2048);
   auto launch_depths = [&](int from, int count) {
     for (int depth = from; depth < from + count; ++depth) {
       const int par = depth & 1;
@@ -1827,7 +1860,7 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
       }
       hipLaunchKernelGGL(k_count, dim3(pass_grid), dim3(kPassThreads), 0, s, sc.seg[par],
                          sc.tile_seg[par], sc.ctr, par, sc.jobs, sc.emit, es, d, leaf,
-                         sc.soa[par], sc.cap, sc.tile_left, rule);
+                         sc.soa[par], sc.cap, sc.tile_left, sc.tile_left + sc.max_tiles, rule);
       hipLaunchKernelGGL(k_tilescan, dim3(1), dim3(1024), 0, s, sc.seg[par], sc.seg[par ^ 1],
                          sc.ctr, par, sc.tile_left, sc.tile_off, sc.fin, T, sc.max_seg,
                          sc.max_fin, d, sc.segtb[par ^ 1], sc.tile_seg[par ^ 1], sc.max_tiles,
@@ -1857,6 +1890,7 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
     A.jobs = sc.jobs;
     A.emit = sc.emit;
     A.tile_left = sc.tile_left;
+    A.tile_q = sc.tile_left + sc.max_tiles;
     A.tile_off = sc.tile_off;
     A.fin = sc.fin;
     A.map = map;

@@ -15,7 +15,7 @@ struct BuildScratch {
   float* soa[2] = {nullptr, nullptr};  // ping-pong build buffers, (d+1) * cap
   Seg* seg[2] = {nullptr, nullptr};
   uint32_t* segtb[2] = {nullptr, nullptr};
-  uint32_t* tile_left = nullptr;
+  uint32_t* tile_left = nullptr;  // 2 * max_tiles: left count per tile, then its quarter prefixes
   uint32_t* tile_seg[2] = {nullptr, nullptr};  // segment of each tile, by depth parity
   uint32_t* tile_off = nullptr;
   uint64_t max_tiles = 0;

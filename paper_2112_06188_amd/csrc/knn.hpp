@@ -84,6 +84,59 @@ int launch_knn(const KnnLaunch& L, int d, int kmax, const KnnQueries& Q, uint64_
 const uint32_t* spatial_order(int d, const float* q, const uint64_t* nq_dev, uint64_t nq_host,
                              uint64_t cap, QueryScratch& qs, hipStream_t s);
 
+// One wavefront's share of a k-NN graph launch: at most 64 consecutive slots
+// [begin, begin + count) of tree `view` (an index into LevelViews), all in
+// the subtree of node `node` of that tree.
+struct GraphGroup {
+  uint32_t view, node, begin, count;
+};
+
+// Groups a k-NN graph launch needs at most for a tree of n slots: one per
+// subtree (at most one per leaf) plus one per further 64 slots.
+inline uint64_t graph_group_bound(uint64_t n) { return n + n / 64 + 1; }
+
+// Scratch of a k-NN graph launch for at most `cap` groups: the group list
+// and its Hilbert-curve order (sort keys and values, two buffers each, and
+// 65536 words of sort scratch).
+struct GraphScratch {
+  uint64_t cap = 0;
+  GraphGroup* groups = nullptr;
+  uint64_t* keys[2] = {nullptr, nullptr};
+  uint32_t* vals[2] = {nullptr, nullptr};
+  uint32_t* tmp = nullptr;
+};
+size_t graph_scratch_bytes(uint64_t cap);
+
+// Orders the *ngroups groups along the Hilbert curve of their first points
+// (cells of the largest tree's root box): afterwards vals[*sel] (sel and
+// width: one device word each) lists the groups in that order, so that
+// neighbouring wavefronts, and each XCD's range of them, work on
+// neighbouring regions.
+void launch_graph_order(int d, const LevelViews* views, GraphScratch& gs, const uint32_t* ngroups,
+                        uint32_t* width, uint32_t* sel, hipStream_t s);
+
+// Appends the groups of tree `view` of `views` (device) to groups (capacity
+// cap entries, count in *ngroups, device).  A group's subtree is the highest
+// one that holds at most 64 points by the nodes' point counts (or a leaf
+// that holds more); its slots are cut into runs of at most 64.  Slots per
+// tree at most n_slots (host bound for the grid).  err bit 64 on an
+// inconsistent tree or a full list.
+void launch_graph_groups(const LevelViews* views, int view, int d, uint64_t n_slots,
+                         GraphGroup* groups, uint64_t cap, uint32_t* ngroups, uint32_t* err,
+                         hipStream_t s);
+
+// The k-NN graph of the live points of the trees in `views` (device): row
+// `id` of out_ids/out_d2 ([idcap][k]) receives the k nearest live points of
+// live point `id`, by (squared distance, id), exactly the row kNN_L returns
+// for that point as a query; other rows are not written.  The group list
+// comes from launch_graph_groups, in the order launch_graph_order left in
+// gs.vals[*sel].  queue: kKnnQueueWords words (zeroed here).  stats as
+// launch_knn.
+int launch_knn_graph(int d, int k, const LevelViews* views, const GraphScratch& gs,
+                     const uint32_t* ngroups, const uint32_t* sel, uint32_t* out_ids,
+                     float* out_d2, uint32_t idcap, uint32_t* err, unsigned long long* stats,
+                     uint32_t* queue, hipStream_t s);
+
 // Concatenate the queries of counts[1] requests (offsets in reqs[i].qoff,
 // counts[0] <= cap queries in all; device memory) into qall and record each
 // query's request in qreq.

@@ -113,6 +113,7 @@ struct bdl_tree {
   uint64_t* pool_bloom = nullptr;  // the pool's filter (routed erase), rebuilt per erase
   int64_t pool_bloom_words = 0;
   int erase_route = 0;             // BDL_PARAM_ERASE_ROUTE
+  GraphScratch graph;              // group list of bdl_knn_graph and its order
   float* brec = nullptr;
   float* bnodes = nullptr;
   int64_t b_nodes = 0;
@@ -131,7 +132,8 @@ struct bdl_tree {
   int pub_base = 0;                   // base budget of the build last published
   int64_t host_waits = 0;             // times the library blocked on the stream
   uint32_t* d_live = nullptr;   // kMaxLevels
-  uint32_t* d_misc = nullptr;   // erase counters [0..1], validation [4..6]
+  uint32_t* d_misc = nullptr;   // erase counters [0..1], validation [4..6], error words
+                                // [8..9], k-NN graph group count, sort width and buffer [10..12]
   unsigned long long* d_stats = nullptr;  // k-NN work counters (profiling)
   uint32_t* h_pin = nullptr;    // pinned staging, kMaxLevels + 16 words
   BuildScratch sc;
@@ -352,7 +354,7 @@ bool ensure_build_scratch(bdl_tree* t, uint64_t need) {
     n.keys[i] = (uint64_t*)A(n.max_emit * 8);
     n.vals[i] = (uint32_t*)A(n.max_emit * 4);
   }
-  n.tile_left = (uint32_t*)A(n.max_tiles * 4);
+  n.tile_left = (uint32_t*)A(n.max_tiles * 8);  // left counts, then quarter prefixes
   n.tile_seg[0] = (uint32_t*)A(n.max_tiles * 4);
   n.tile_seg[1] = (uint32_t*)A(n.max_tiles * 4);
   n.tile_off = (uint32_t*)A(n.max_tiles * 4);
@@ -1322,6 +1324,8 @@ int check_device_errors(bdl_tree* t) {
   if (build)
     return fail(BDL_EHIP, (build & 1024u) ? "a build did not end (a node stayed above the LDS size)"
                                           : "build scratch overflow");
+  if (knn & 64u)
+    return fail(BDL_EHIP, "an in-place insert or a k-NN graph launch met an inconsistent tree");
   return fail(BDL_EHIP, "k-NN traversal met an out-of-range tree index");
 }
 
@@ -1534,6 +1538,57 @@ int bdl_knn(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t* out_id
                       t->pt.mark ? t->d_stats : nullptr, t->s);
   t->pt.end(BDL_PH_TRAVERSE);
   if (rc) return fail(rc, "k-NN launch failed");
+  return 0;
+}
+
+int bdl_knn_graph(bdl_tree* t, int32_t k, uint32_t* out_ids, float* out_d2) {
+  if (!t) return fail(BDL_EINVAL, "null tree");
+  if (k < 1 || k > BDL_MAX_K) return fail(BDL_EINVAL, "k must be in 1..64");
+  if (!out_ids || !out_d2) return fail(BDL_EINVAL, "null output");
+  const LevelViews v = make_views(t);
+  if (v.n == 0) return 0;
+  uint64_t cap = 0;
+  for (int i = 0; i < v.n; ++i) cap += graph_group_bound(v.v[i].n_slots);
+  if (cap > t->graph.cap) {
+    GraphScratch g;
+    g.cap = cap;
+    bool ok = true;
+    auto A = [&](size_t bytes) -> void* {
+      void* p = ok ? dmalloc(t, bytes) : nullptr;
+      if (!p) ok = false;
+      return p;
+    };
+    g.groups = (GraphGroup*)A((size_t)cap * sizeof(GraphGroup));
+    for (int i = 0; i < 2; ++i) {
+      g.keys[i] = (uint64_t*)A((size_t)cap * 8);
+      g.vals[i] = (uint32_t*)A((size_t)cap * 4);
+    }
+    g.tmp = (uint32_t*)A(65536 * 4);
+    void* fresh[] = {g.groups, g.keys[0], g.keys[1], g.vals[0], g.vals[1], g.tmp};
+    if (!ok) {
+      for (void* p : fresh) dfree(t, p);
+      return fail(BDL_ENOMEM, "cannot allocate the k-NN graph's group list");
+    }
+    void* old[] = {t->graph.groups, t->graph.keys[0], t->graph.keys[1], t->graph.vals[0],
+                   t->graph.vals[1], t->graph.tmp};
+    if (t->graph.groups) (void)wait_stream(t);
+    for (void* p : old) dfree(t, p);
+    t->graph = g;
+  }
+  uint32_t* ngroups = t->d_misc + 10;
+  launch_fill_u32(ngroups, 0u, 1, t->s);
+  t->pt.begin(BDL_PH_ORDER);
+  for (int i = 0; i < v.n; ++i)
+    launch_graph_groups(t->d_views, i, t->d, v.v[i].n_slots, t->graph.groups, t->graph.cap,
+                        ngroups, t->d_misc + 8, t->s);
+  launch_graph_order(t->d, t->d_views, t->graph, ngroups, t->d_misc + 11, t->d_misc + 12, t->s);
+  t->pt.end(BDL_PH_ORDER);
+  t->pt.begin(BDL_PH_TRAVERSE);
+  const int rc = launch_knn_graph(t->d, k, t->d_views, t->graph, ngroups, t->d_misc + 12,
+                                  out_ids, out_d2, t->cfg.id_capacity, t->d_misc + 8,
+                                  t->pt.mark ? t->d_stats : nullptr, t->d_queue, t->s);
+  t->pt.end(BDL_PH_TRAVERSE);
+  if (rc) return fail(rc, "k-NN graph launch failed");
   return 0;
 }
 

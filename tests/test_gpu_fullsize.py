@@ -2,10 +2,12 @@
 benchmark times: 10 Insert_L batches of 1M uniform points, one Erase_L of
 1M random live points, kNN_L k=5 for all 9M live points.
 
-Checked at full size: the level schedule against the binary-counter closed
-form, the self-match property for every query (each query is a live point
-and coordinates are distinct, so its nearest neighbour is itself at 0), and
-sampled rows against the brute-force definition over the live set.
+Checked at full size: every tree (slot order, points, node arrays) against
+the oracle's after the inserts and again after the erase, the level
+schedule against the binary-counter closed form, the self-match property
+for every query (each query is a live point and coordinates are distinct,
+so its nearest neighbour is itself at 0), and sampled rows against the
+brute-force definition over the live set.
 """
 from __future__ import annotations
 
@@ -14,7 +16,7 @@ import pytest
 
 import oracle
 from bdl_inputs import workload
-from gpu_util import assert_knn_equal, bits, log, to_dev
+from gpu_util import assert_knn_equal, bits, compare_structure, log, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -29,19 +31,25 @@ def test_uniform3d_10m_full_size():
     w = workload("uniform3d_10m")
     t = bdl.Tree(w.dim, leaf_size=w.leaf_size, buffer_size=w.buffer_size,
                  id_capacity=w.id_capacity)
+    o = oracle.OracleBDL(w.dim, w.leaf_size, w.buffer_size)
     live = np.ones(w.id_capacity, dtype=bool)
     all_pts = np.concatenate([op.pts for op in w.ops if op.kind == "insert"])
     for op in w.ops:
         if op.kind == "insert":
             t.insert(to_dev(op.pts, torch), to_dev(op.ids, torch))
+            o.insert(op.pts, op.ids)
         elif op.kind == "erase":
             # before the erase: the closed form of 10M insert-only points
             info = t.level_info()
             assert bits(info["F"]) == [0, 2, 5, 9, 10, 13] and info["buf_live"] == 640
+            compare_structure(t, o, w.dim, "10M after the inserts")
             assert t.erase(to_dev(op.pts, torch), to_dev(op.ids, torch)) == op.n
+            assert o.erase(op.pts, op.ids) == op.n
             live[op.ids.astype(np.int64)] = False
+            compare_structure(t, o, w.dim, "10M after the erase")
         else:
             qop = op
+    o.close()
     info = t.level_info()
     assert bits(info["F"]) == [0, 2, 5, 9, 10, 13]
     # the buffer holds the 640 newest points and loses those the erase names
