@@ -871,8 +871,10 @@ def main():
     ap.add_argument("--extra", type=int, default=1,
                     help="1: the plain form also runs the served leg (mixed-load p50/p99) "
                          "and the 7D clustered workload; 0: the 3D step only")
-    ap.add_argument("--served-scale", type=float, default=0.2)
-    ap.add_argument("--clustered-steps", type=int, default=2)
+    ap.add_argument("--served-scale", type=float, default=0.2,
+                    help="scale of the served leg of the plain form (0: skip)")
+    ap.add_argument("--clustered-steps", type=int, default=2,
+                    help="timed steps of the 7D clustered leg of the plain form (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter scaling)")
     args = ap.parse_args()
@@ -895,10 +897,12 @@ def main():
     else:
         res["cpu_baseline"] = None
     if args.extra:
-        print("bench: 7D clustered workload", file=sys.stderr, flush=True)
-        res["clustered7d_10m"] = clustered_leg(args)
-        print("bench: served leg", file=sys.stderr, flush=True)
-        res["served_mixed_load"] = served_leg(args)
+        if args.clustered_steps > 0:
+            print("bench: 7D clustered workload", file=sys.stderr, flush=True)
+            res["clustered7d_10m"] = clustered_leg(args)
+        if args.served_scale > 0:
+            print("bench: served leg", file=sys.stderr, flush=True)
+            res["served_mixed_load"] = served_leg(args)
         if args.mixed_scale > 0:
             print("bench: mixed-operations leg", file=sys.stderr, flush=True)
             m = mixed_bench(args, "mixed2d_10m", args.mixed_scale)

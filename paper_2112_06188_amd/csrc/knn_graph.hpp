@@ -263,12 +263,20 @@ k_knn_graph(const LevelViews* __restrict__ views, const GraphGroup* __restrict__
   GroupSched gs = make_sched(queue, (uint64_t)n * 64u);
   uint32_t g;
   while (gs.next(g)) {
-    const uint32_t o = order[g];
+    // the group is the same for the whole wavefront: keep it in scalar
+    // registers, so that the tree it names is read with scalar loads
+    const uint32_t o = __builtin_amdgcn_readfirstlane(order[g]);
     if (o >= n) {
       if (__lane_id() == 0) atomicOr(err, 64u);
       continue;
     }
-    knn_graph_group<D, KMAX>(views, groups[o], k, out_ids, out_d2, idcap, err, stats);
+    const GraphGroup* gp = groups + o;
+    GraphGroup G;
+    G.view = __builtin_amdgcn_readfirstlane(gp->view);
+    G.node = __builtin_amdgcn_readfirstlane(gp->node);
+    G.begin = __builtin_amdgcn_readfirstlane(gp->begin);
+    G.count = __builtin_amdgcn_readfirstlane(gp->count);
+    knn_graph_group<D, KMAX>(views, G, k, out_ids, out_d2, idcap, err, stats);
   }
 }
 

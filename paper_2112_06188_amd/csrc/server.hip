@@ -313,15 +313,34 @@ bool launch_next(bdl_server* s) {
     }
     head->c.status = rc;
   } else {
-    std::vector<bdl_knn_request> kr;
+    // The k-NN requests up to the next update read one snapshot, so they
+    // may run in any order.  Small ones go together into one batched
+    // launch, ahead of large ones; a large request (more than
+    // kAloneQueries queries) runs alone as a plain call, so that it neither
+    // holds small requests back until it ends nor waits for them.
+    constexpr int64_t kAloneQueries = 16384;
+    std::vector<Req*> pick;
     int64_t nq = 0;
-    while (!s->staged.empty()) {
-      Req* q = s->staged.front();
+    for (auto it = s->staged.begin(); it != s->staged.end();) {
+      Req* q = *it;
       if (q->r.kind != BDL_REQ_KNN) break;
-      if (!kr.empty() && ((int)kr.size() >= s->cfg.max_batch_requests ||
-                          nq + q->r.n > s->cfg.max_batch_queries))
+      if (q->r.n > kAloneQueries) {
+        ++it;
+        continue;
+      }
+      if (!pick.empty() && ((int)pick.size() >= s->cfg.max_batch_requests ||
+                            nq + q->r.n > s->cfg.max_batch_queries))
         break;
+      pick.push_back(q);
+      nq += q->r.n;
+      it = s->staged.erase(it);
+    }
+    if (pick.empty()) {
+      pick.push_back(s->staged.front());  // the run holds only large requests
       s->staged.pop_front();
+    }
+    std::vector<bdl_knn_request> kr;
+    for (Req* q : pick) {
       L.reqs.push_back(q);
       q->c.launch = id;
       q->c.t_start_ms = now;
@@ -335,13 +354,13 @@ bool launch_next(bdl_server* s) {
       r.out_ids = (uint32_t*)q->d_out;
       r.out_d2 = (float*)((char*)q->d_out + (size_t)q->r.n * q->r.k * 4);
       kr.push_back(r);
-      nq += q->r.n;
     }
+    // a lone request runs as a plain call (same results; no request table,
+    // gather or graph bucket to pay for)
     int rc = kr.empty() ? BDL_OK
-                        : (s->cfg.mode == BDL_SERVE_BATCHED || kr.size() > 1
-                               ? bdl_knn_batch(s->t, kr.data(), (int32_t)kr.size())
-                               : bdl_knn(s->t, kr[0].q, kr[0].nq, kr[0].k, kr[0].out_ids,
-                                         kr[0].out_d2));
+                        : (kr.size() > 1 ? bdl_knn_batch(s->t, kr.data(), (int32_t)kr.size())
+                                         : bdl_knn(s->t, kr[0].q, kr[0].nq, kr[0].k,
+                                                   kr[0].out_ids, kr[0].out_d2));
     for (Req* q : L.reqs) q->c.status = rc;
   }
   if (!L.ev_done || !computed || hipEventRecord(computed, s->cs) != hipSuccess ||
@@ -381,16 +400,34 @@ void loop_batched(bdl_server* s) {
     bool progress = false;
     progress |= reap(s, false) > 0;
     progress |= admit(s, 1 << 30) > 0;
-    while ((int)s->running.size() < s->cfg.max_launches && !s->staged.empty())
+    while ((int)s->running.size() < s->cfg.max_launches && !s->staged.empty()) {
+      // an erase blocks this thread until the device has done it (it reads
+      // the live counts back); launch it only once earlier launches are
+      // reaped, so that their completions are not held back behind it
+      if (s->staged.front()->r.kind == BDL_REQ_ERASE && !s->running.empty()) break;
       progress |= launch_next(s);
+    }
     if (progress) continue;
+    if (!s->running.empty()) {
+      // device work outstanding and nothing to admit: wait for the oldest
+      // launch (a timed sleep would add the timer's slack, tens of
+      // microseconds, to every completion); requests that arrive meanwhile
+      // are admitted as soon as it is done
+      bool idle;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        idle = s->pending.empty();
+      }
+      if (idle)
+        (void)hipEventSynchronize(s->running.front().ev_done);
+      else
+        std::this_thread::yield();  // pending work waits for a slot or budget
+      continue;
+    }
     std::unique_lock<std::mutex> lk(s->mu);
     if (s->stop && s->pending.empty() && s->staged.empty() && s->running.empty()) return;
-    // with device work outstanding look again shortly (a submission wakes
-    // the loop at once); otherwise sleep until one arrives
-    if (s->pending.empty() || !s->running.empty())
-      s->cv_work.wait_for(lk, s->running.empty() ? std::chrono::microseconds(5000)
-                                                 : std::chrono::microseconds(20));
+    // nothing on the device: sleep until a submission arrives
+    if (s->pending.empty()) s->cv_work.wait_for(lk, std::chrono::microseconds(5000));
   }
 }
 
