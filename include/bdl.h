@@ -172,7 +172,10 @@ int bdl_knn_graph(bdl_tree* t, int32_t k, uint32_t* out_ids, float* out_d2);
                                   every launch when dim >= 5, 1 when a launch
                                   has at least 65536 queries and half as many
                                   as live points, else 0.  3 needs every tree
-                                  below 2^26 nodes, else 0 runs */
+                                  below 2^26 nodes, else 0 runs; a tree of
+                                  2^25 slots or more whose build is still
+                                  running makes the call wait for that build
+                                  to learn its node count */
 #define BDL_PARAM_SORT_MIN 2   /* query batches of at least this many queries
                                   are visited in Hilbert-curve order (default 4096) */
 #define BDL_PARAM_KNN_BLOCK 3  /* k-NN workgroup size: 64, 128 or 256 (default) */

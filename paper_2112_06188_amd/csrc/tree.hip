@@ -924,17 +924,29 @@ KnnLaunch choose_launch(const bdl_tree* t, int kmax, uint64_t nq, bool* sort) {
   KnnLaunch L;
   L.mode = t->knn_mode;
   // the wavefront-per-query kernel keeps node indices in 26 bits
-  resolve_nodes(const_cast<bdl_tree*>(t), false);
+  bdl_tree* tw = const_cast<bdl_tree*>(t);
+  resolve_nodes(tw, false);
   // a count still on the device is bounded by 2 slots - 1
   auto nodes_of = [](int64_t nn, int64_t slots) -> uint64_t {
     return nn >= 0 ? (uint64_t)nn : (uint64_t)(2 * slots);
   };
-  uint64_t max_nodes = t->bn ? nodes_of(t->b_nodes, t->bn) : 0;
-  for (int i = 0; i < kMaxLevels; ++i)
-    if (t->lev[i].on) {
-      const uint64_t m = nodes_of(t->lev[i].n_nodes, t->lev[i].n_slots);
-      if (m > max_nodes) max_nodes = m;
-    }
+  auto max_nodes_of = [&]() -> uint64_t {
+    uint64_t m = t->bn ? nodes_of(t->b_nodes, t->bn) : 0;
+    for (int i = 0; i < kMaxLevels; ++i)
+      if (t->lev[i].on) {
+        const uint64_t x = nodes_of(t->lev[i].n_nodes, t->lev[i].n_slots);
+        if (x > m) m = x;
+      }
+    return m;
+  };
+  uint64_t max_nodes = max_nodes_of();
+  // a tree of 2^25 slots or more only passes with its exact count: wait for
+  // the build that publishes it (the launch would wait for it on the
+  // stream anyway), rather than fall back to a slower kernel
+  if (max_nodes >= kKnnQueryMaxNodes && t->nodes_pending) {
+    resolve_nodes(tw, true);
+    max_nodes = max_nodes_of();
+  }
   const bool query_ok = max_nodes < kKnnQueryMaxNodes;
   if (L.mode == kKnnAuto) {
     // a small batch leaves the device idle with one lane per query: one
