@@ -89,15 +89,20 @@ __global__ void k_graph_groups(const LevelViews* views, int view, int d, GraphGr
 
 // Sort key of every group: the Hilbert-curve cell of its first point in the
 // root box of the first (largest) tree, floor(30 / D) bits per dimension
-// (points outside the box take the nearest cell).
+// (points outside the box take the nearest cell).  Above it, the key puts
+// the groups of the smaller trees first within each eighth of the curve:
+// their points are spread out, so their wavefronts run longest, and the
+// grid's per-XCD ranges (about one eighth of the curve each) should start
+// them early rather than leave them for the end of the launch.
 template <int D>
 __global__ void k_graph_keys(const LevelViews* views, const GraphGroup* groups,
                              const uint32_t* ngroups, uint64_t* keys, uint32_t* vals,
                              uint32_t* width) {
   constexpr int kBits = 30 / D > 0 ? 30 / D : 1;
+  constexpr int kKeyBits = kBits * D;
   constexpr int S = (D + 1 + 3) & ~3;
   const uint32_t n = *ngroups;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *width = (uint32_t)(kBits * D);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *width = (uint32_t)(kKeyBits + 4);
   const float* root = views->v[0].nodes;
   const float cells = (float)(1u << kBits);
   float lo[D], ext[D];
@@ -117,7 +122,10 @@ __global__ void k_graph_keys(const LevelViews* views, const GraphGroup* groups,
       c = c < 0 ? 0 : (c >= (1 << kBits) ? (1 << kBits) - 1 : c);
       cell[j] = (uint32_t)c;
     }
-    keys[g] = hilbert_key<D, kBits>(cell);
+    const uint64_t h = hilbert_key<D, kBits>(cell);
+    const uint64_t eighth = kKeyBits >= 3 ? h >> (kKeyBits - 3) : h;
+    const uint64_t big = G.view == 0 ? 1u : 0u;
+    keys[g] = (eighth << (kKeyBits + 1)) | (big << kKeyBits) | h;
     vals[g] = g;
   }
 }
@@ -146,7 +154,7 @@ void launch_graph_order(int d, const LevelViews* views, GraphScratch& gs, const 
     default:
       return;
   }
-  radix_sort_pairs_u64_dev(gs.keys, gs.vals, ngroups, gs.cap, width, 32, sel, gs.tmp, s);
+  radix_sort_pairs_u64_dev(gs.keys, gs.vals, ngroups, gs.cap, width, 40, sel, gs.tmp, s);
 }
 
 void launch_graph_groups(const LevelViews* views, int view, int d, uint64_t n_slots,
