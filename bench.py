@@ -90,36 +90,42 @@ def traversal_kernel(mode: int, d: int, nq: int, live: int) -> str:
     return {0: "k_knn", 1: "k_knn_wave", 3: "k_knn_query"}[mode]
 
 
-def knn_graph_leg(torch, tree, out_ids, out_d2, qids, k, stream):
+def knn_graph_leg(torch, bdl, tree, out_ids, out_d2, qids, k, stream):
     """The step's k-NN rows (every live point as a query) through
-    bdl_knn_graph, whose searches start from each point's own leaves:
-    device time of the whole call (group list and traversal) against the
-    step's kNN_L, and the rows compared with kNN_L's bit for bit."""
+    bdl_knn_graph, both ways: presorted queries searched from the roots, and
+    the leaf-based search of Section II (one wavefront per subtree, starting
+    there).  Device time of the whole call against the step's kNN_L, and the
+    rows compared with kNN_L's bit for bit."""
     gi = torch.empty((tree.id_capacity, k), dtype=torch.int32, device=out_ids.device)
     gd = torch.empty((tree.id_capacity, k), dtype=torch.float32, device=out_ids.device)
-    ms = []
-    tree.sync()
-    tree.profile(reset=True)
-    for _ in range(3):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        tree.knn_graph(k, gi, gd)
-        b.record(stream)
-        torch.cuda.synchronize()
-        ms.append(a.elapsed_time(b))
     rows = qids.to(torch.int64)
-    same = bool(torch.equal(gi[rows], out_ids)) and \
-        bool(torch.equal(gd[rows].view(torch.int32), out_d2.view(torch.int32)))
-    t = float(np.median(ms))
-    tree.sync()
-    prof = tree.profile(reset=True)
     nq = qids.shape[0]
+    out = {}
+    for name, start in (("presorted", 0), ("leaf_based", 1)):
+        tree.set_param(bdl.PARAM_GRAPH_START, start)
+        ms = []
+        tree.sync()
+        tree.profile(reset=True)
+        for _ in range(3):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            tree.knn_graph(k, gi, gd)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        same = bool(torch.equal(gi[rows], out_ids)) and \
+            bool(torch.equal(gd[rows].view(torch.int32), out_d2.view(torch.int32)))
+        t = float(np.median(ms))
+        tree.sync()
+        prof = tree.profile(reset=True)
+        out[name] = {"ms": t, "queries_per_s": nq / (t * 1e-3), "calls_ms": ms,
+                     "gather_or_groups_and_order_ms": prof["order"]["ms"] / 3,
+                     "traverse_ms": prof["traverse"]["ms"] / 3,
+                     "work_per_query": {kk: v / (3 * nq) for kk, v in prof["knn_work"].items()},
+                     "rows_equal_knn": same}
+    tree.set_param(bdl.PARAM_GRAPH_START, 0)
     del gi, gd
-    return {"ms": t, "queries_per_s": nq / (t * 1e-3), "calls_ms": ms,
-            "groups_and_order_ms": prof["order"]["ms"] / 3,
-            "traverse_ms": prof["traverse"]["ms"] / 3,
-            "work_per_query": {kk: v / (3 * nq) for kk, v in prof["knn_work"].items()},
-            "rows_equal_knn": same}
+    return out
 
 
 def erase_route_leg(torch, bdl, tree, inserts, erases, stream):
@@ -244,7 +250,8 @@ def gpu_bench(args):
     own = qids.to(torch.int64) & 0xFFFFFFFF
     self_ok = bool((out_d2[:, 0] == 0).all()) and bool((first <= own).all())
     self_exact = float((first == own).to(torch.float32).mean())
-    graph_leg = knn_graph_leg(torch, tree, out_ids, out_d2, qids, k, stream) if args.extra \
+    graph_leg = knn_graph_leg(torch, bdl, tree, out_ids, out_d2, qids, k, stream) \
+        if args.extra \
         else None
     counters = tree.counters()
 

@@ -151,17 +151,19 @@ int bdl_knn_noalloc(bdl_tree* t, const float* q, int64_t nq, int32_t k, uint32_t
                     float* out_d2);
 
 /* The k-NN graph of the live points: kNN_L (Alg. 5) with every live point
- * as a query, each search started from the query's own leaves (the
- * leaf-based search of Section II) instead of the root.  Row `id` of out_ids
+ * as a query (BDL_PARAM_GRAPH_START chooses between presorted queries
+ * searched from the roots and the leaf-based search of Section II).  Row
+ * `id` of out_ids
  * and out_d2 (device, [id_capacity][k] row-major, caller-owned) receives the
  * k nearest live points of live point `id`, sorted by (squared distance, id)
  * and padded as bdl_knn: exactly the row bdl_knn returns for that point as
  * a query (the point itself comes first at 0 unless another live point has
  * the same coordinates and a smaller id).  Rows of ids that are not live are
  * not written.  Asynchronous; the outputs must stay allocated until the
- * stream passes the call.  Allocates a group list of about 16 bytes per
- * stored point on first use (BDL_ENOMEM if it cannot).  BDL_EINVAL for k
- * outside 1..64 or a null output. */
+ * stream passes the call.  Allocates scratch on first use (BDL_ENOMEM if it
+ * cannot): 4(d + 1) + 8k bytes per stored point for presorted queries,
+ * about 40 bytes per stored point for the leaf-based search.  BDL_EINVAL for
+ * k outside 1..64 or a null output. */
 int bdl_knn_graph(bdl_tree* t, int32_t k, uint32_t* out_ids, float* out_d2);
 
 /* Tuning parameters (bdl_set_param).  They change speed, never results. */
@@ -204,6 +206,16 @@ int bdl_knn_graph(bdl_tree* t, int32_t k, uint32_t* out_ids, float* out_d2);
                                    at the first such erase after the tree
                                    changed, the buffer's at every such
                                    erase.  Same results either way. */
+#define BDL_PARAM_GRAPH_START 9 /* how bdl_knn_graph searches.  0 (default):
+                                   every live point becomes a query, the
+                                   queries are ordered along the Hilbert
+                                   curve and searched from the roots as by
+                                   bdl_knn, and each row is moved to the row
+                                   of its id.  1: the leaf-based search of
+                                   Section II: one wavefront per subtree of
+                                   at most 64 points, starting in that
+                                   subtree and climbing through parent links.
+                                   Same results either way. */
 int bdl_set_param(bdl_tree* t, int32_t param, int64_t value);
 
 /* One row of a launch-shape table for kNN_L (bdl_knn and bdl_knn_batch).  A

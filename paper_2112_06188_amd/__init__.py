@@ -51,6 +51,7 @@ PARAM_PERSISTENT = 5
 PARAM_QUERY_MAX = 6
 PARAM_QUERY_STACK = 7
 PARAM_ERASE_ROUTE = 8
+PARAM_GRAPH_START = 9
 MAX_SHAPES = 256
 KNN_LANE = 0
 KNN_WAVE = 1

@@ -137,6 +137,30 @@ int launch_knn_graph(int d, int k, const LevelViews* views, const GraphScratch& 
                      float* out_d2, uint32_t idcap, uint32_t* err, unsigned long long* stats,
                      uint32_t* queue, hipStream_t s);
 
+// The other way to the k-NN graph: every live point gathered as a query
+// (coordinates [cap][d], ids), ordered along the Hilbert curve and searched
+// from the roots by the kNN_L kernels into rows [cap][k], which are then
+// moved to row `id` of the caller's outputs.  count: one 64-bit device word.
+struct GraphQueries {
+  uint64_t cap = 0;      // queries (live points) at most
+  uint64_t row_cap = 0;  // result words per array (cap * k for the largest k so far)
+  float* q = nullptr;
+  uint32_t* ids = nullptr;
+  uint32_t* rid = nullptr;
+  float* rd2 = nullptr;
+  unsigned long long* count = nullptr;
+};
+
+// Appends the live points of tree `view` (at most n_slots, host bound) to
+// gq.q / gq.ids at positions taken from *gq.count.  err bit 64 if more than
+// gq.cap arrive.
+void launch_graph_gather(const LevelViews* views, int view, int d, uint64_t n_slots,
+                         GraphQueries& gq, uint32_t* err, hipStream_t s);
+
+// Rows [*gq.count][k] of gq.rid / gq.rd2 to rows ids[r] of out ([idcap][k]).
+void launch_graph_scatter(const GraphQueries& gq, int k, uint32_t* out_ids, float* out_d2,
+                          uint32_t idcap, hipStream_t s);
+
 // Concatenate the queries of counts[1] requests (offsets in reqs[i].qoff,
 // counts[0] <= cap queries in all; device memory) into qall and record each
 // query's request in qreq.

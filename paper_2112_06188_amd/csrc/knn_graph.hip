@@ -130,7 +130,72 @@ __global__ void k_graph_keys(const LevelViews* views, const GraphGroup* groups,
   }
 }
 
+// One thread per slot of one tree; the live ones take consecutive positions
+// per wavefront (one atomic per wavefront), in no particular order overall.
+__global__ void k_graph_gather(const LevelViews* views, int view, int d, float* q, uint32_t* ids,
+                               unsigned long long* count, uint64_t cap, uint32_t* err) {
+  const LevelView V = views->v[view];
+  const int S = rec_stride(d);
+  const uint64_t ns = V.n_slots;
+  const int lane = __lane_id();
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < ns; base += stride) {
+    const uint64_t i = base + threadIdx.x;
+    const float* r = V.rec + i * S;
+    const uint32_t id = i < ns ? __float_as_uint(r[d]) : kTomb;
+    const bool live = id != kTomb;
+    const uint64_t m = __ballot(live);
+    if (m == 0ull) continue;
+    unsigned long long first = 0;
+    if (lane == __builtin_ctzll(m)) first = atomicAdd(count, (unsigned long long)__popcll(m));
+    first = __shfl(first, __builtin_ctzll(m), 64);
+    if (!live) continue;
+    const uint64_t pos = first + (uint64_t)__popcll(m & below);
+    if (pos >= cap) {
+      atomicOr(err, 64u);
+      continue;
+    }
+    for (int j = 0; j < d; ++j) q[pos * d + j] = r[j];
+    ids[pos] = id;
+  }
+}
+
+// One thread per result word: row r goes to row ids[r] of the outputs.
+__global__ void k_graph_scatter(const uint32_t* rid, const float* rd2, const uint32_t* ids,
+                                const unsigned long long* count, int k, uint32_t* out_ids,
+                                float* out_d2, uint32_t idcap) {
+  const uint64_t n = (uint64_t)*count * (uint64_t)k;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t r = e / (uint64_t)k;
+    const uint32_t id = ids[r];
+    if (id >= idcap) continue;
+    const uint64_t o = (uint64_t)id * (uint64_t)k + (e - r * (uint64_t)k);
+    out_ids[o] = rid[e];
+    out_d2[o] = rd2[e];
+  }
+}
+
 }  // namespace
+
+void launch_graph_gather(const LevelViews* views, int view, int d, uint64_t n_slots,
+                         GraphQueries& gq, uint32_t* err, hipStream_t s) {
+  uint64_t g = (n_slots + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > 16384) g = 16384;
+  hipLaunchKernelGGL(k_graph_gather, dim3((unsigned)g), dim3(256), 0, s, views, view, d, gq.q,
+                     gq.ids, gq.count, gq.cap, err);
+}
+
+void launch_graph_scatter(const GraphQueries& gq, int k, uint32_t* out_ids, float* out_d2,
+                          uint32_t idcap, hipStream_t s) {
+  uint64_t g = (gq.cap * (uint64_t)k + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > 16384) g = 16384;
+  hipLaunchKernelGGL(k_graph_scatter, dim3((unsigned)g), dim3(256), 0, s, gq.rid, gq.rd2, gq.ids,
+                     gq.count, k, out_ids, out_d2, idcap);
+}
 
 size_t graph_scratch_bytes(uint64_t cap) {
   return (size_t)cap * (sizeof(GraphGroup) + 2 * 8 + 2 * 4) + 65536 * 4;

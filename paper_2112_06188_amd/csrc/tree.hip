@@ -114,6 +114,8 @@ struct bdl_tree {
   int64_t pool_bloom_words = 0;
   int erase_route = 0;             // BDL_PARAM_ERASE_ROUTE
   GraphScratch graph;              // group list of bdl_knn_graph and its order
+  GraphQueries gq;                 // bdl_knn_graph from presorted queries
+  int graph_start = 0;             // BDL_PARAM_GRAPH_START
   float* brec = nullptr;
   float* bnodes = nullptr;
   int64_t b_nodes = 0;
@@ -1076,6 +1078,71 @@ int run_batch(bdl_tree* t, const bdl_knn_request* reqs, int nreq) {
   return 0;
 }
 
+// bdl_knn_graph by kNN_L over the live points: they are gathered as
+// queries, ordered along the Hilbert curve with the other queries' machinery
+// and searched from the roots, and each row is moved to the row of its id.
+int knn_graph_presorted(bdl_tree* t, const LevelViews& v, int k, uint32_t* out_ids,
+                        float* out_d2) {
+  uint64_t cap = 0;
+  for (int i = 0; i < v.n; ++i) cap += v.v[i].n_slots;
+  const uint64_t rows = cap * (uint64_t)k;
+  if (!ensure_query_scratch(t, cap)) return fail(BDL_ENOMEM, "query scratch");
+  GraphQueries& g = t->gq;
+  if (cap > g.cap || rows > g.row_cap) {
+    GraphQueries n;
+    n.cap = cap > g.cap ? cap : g.cap;
+    n.row_cap = rows > g.row_cap ? rows : g.row_cap;
+    bool ok = true;
+    auto A = [&](size_t bytes) -> void* {
+      void* p = ok ? dmalloc(t, bytes) : nullptr;
+      if (!p) ok = false;
+      return p;
+    };
+    n.q = (float*)A((size_t)n.cap * t->d * 4);
+    n.ids = (uint32_t*)A((size_t)n.cap * 4);
+    n.rid = (uint32_t*)A((size_t)n.row_cap * 4);
+    n.rd2 = (float*)A((size_t)n.row_cap * 4);
+    n.count = (unsigned long long*)A(8);
+    void* fresh[] = {n.q, n.ids, n.rid, n.rd2, n.count};
+    if (!ok) {
+      for (void* p : fresh) dfree(t, p);
+      return fail(BDL_ENOMEM, "cannot allocate the k-NN graph's queries");
+    }
+    void* old[] = {g.q, g.ids, g.rid, g.rd2, g.count};
+    if (g.q) (void)wait_stream(t);
+    for (void* p : old) dfree(t, p);
+    g = n;
+  }
+  launch_fill_u32((uint32_t*)g.count, 0u, 2, t->s);
+  t->pt.begin(BDL_PH_ORDER);
+  for (int i = 0; i < v.n; ++i)
+    launch_graph_gather(t->d_views, i, t->d, v.v[i].n_slots, g, t->d_misc + 8, t->s);
+  const uint64_t* nq_dev = reinterpret_cast<const uint64_t*>(g.count);
+  const uint32_t* order = spatial_order(t->d, g.q, nq_dev, 0, cap, t->qs, t->s);
+  t->pt.end(BDL_PH_ORDER);
+  bool sort = false;
+  const KnnLaunch L = choose_launch(t, k, cap, &sort);
+  KnnQueries Q;
+  std::memset(&Q, 0, sizeof(Q));
+  Q.q = g.q;
+  Q.nq_dev = nq_dev;
+  Q.nq = cap;
+  Q.one.q = g.q;
+  Q.one.out_ids = g.rid;
+  Q.one.out_d2 = g.rd2;
+  Q.one.qoff = 0;
+  Q.one.nq = (uint32_t)cap;
+  Q.one.k = k;
+  t->pt.begin(BDL_PH_TRAVERSE);
+  int rc = launch_knn(L, t->d, k, Q, cap, order, t->d_views, t->d_misc + 8,
+                      t->pt.mark ? t->d_stats : nullptr, t->s);
+  t->pt.end(BDL_PH_TRAVERSE);
+  if (rc) return fail(rc, "k-NN graph launch failed");
+  launch_graph_scatter(g, k, out_ids, out_d2, t->cfg.id_capacity, t->s);
+  if (hipGetLastError() != hipSuccess) return fail(BDL_EHIP, "k-NN graph launch failed");
+  return 0;
+}
+
 }  // namespace
 
 namespace bdl {
@@ -1249,6 +1316,10 @@ int bdl_set_param(bdl_tree* t, int32_t param, int64_t value) {
     case BDL_PARAM_QUERY_MAX:
       if (value < 0) return fail(BDL_EINVAL, "query_max must be >= 0");
       t->query_max = (uint64_t)value;
+      return 0;
+    case BDL_PARAM_GRAPH_START:
+      if (value != 0 && value != 1) return fail(BDL_EINVAL, "graph_start is 0 or 1");
+      t->graph_start = (int)value;
       return 0;
     case BDL_PARAM_ERASE_ROUTE:
       if (value != 0 && value != 1) return fail(BDL_EINVAL, "erase_route is 0 or 1");
@@ -1559,6 +1630,7 @@ int bdl_knn_graph(bdl_tree* t, int32_t k, uint32_t* out_ids, float* out_d2) {
   if (!out_ids || !out_d2) return fail(BDL_EINVAL, "null output");
   const LevelViews v = make_views(t);
   if (v.n == 0) return 0;
+  if (t->graph_start == 0) return knn_graph_presorted(t, v, k, out_ids, out_d2);
   uint64_t cap = 0;
   for (int i = 0; i < v.n; ++i) cap += graph_group_bound(v.v[i].n_slots);
   if (cap > t->graph.cap) {

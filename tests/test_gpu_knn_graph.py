@@ -1,9 +1,10 @@
 """The k-NN graph (bdl_knn_graph) against the oracle's kNN_L on the GPU.
 
-bdl_knn_graph answers kNN_L (Alg. 5) for every live point, started from the
-point's own leaves.  Its row `id` must equal, id for id and distance bit for
-bit, the oracle's kNN_L row for live point `id` as a query; rows of ids that
-are not live stay untouched.  The cases cover tombstones and the buffer,
+bdl_knn_graph answers kNN_L (Alg. 5) for every live point, either from
+presorted queries searched from the roots or started from each point's own
+subtree (BDL_PARAM_GRAPH_START).  In both ways its row `id` must equal, id
+for id and distance bit for bit, the oracle's kNN_L row for live point `id`
+as a query; rows of ids that are not live stay untouched.  The cases cover tombstones and the buffer,
 leaves larger than a wavefront (leaf size 128, and B2's grown leaves),
 coincident points, both split rules, k from 1 to 64 and dimensions 1 to 16.
 """
@@ -53,19 +54,28 @@ def live_points(o):
 
 
 def check_graph(t, o, k, what):
-    gi, gd = t.knn_graph(k)
-    t.sync()
-    gi = gi.cpu().numpy().view(np.uint32)
-    gd = gd.cpu().numpy()
+    """Both ways to the graph (presorted queries from the roots, and the
+    leaf-based search) against the oracle's kNN_L over the live points."""
+    import paper_2112_06188_amd as bdl
     ids, pts = live_points(o)
     assert len(ids) == o.size() == t.size(), what
+    oi = od = None
     if len(ids):
         oi, od = o.knn(pts, k)
-        assert_knn_equal(gi[ids.astype(np.int64)], gd[ids.astype(np.int64)], oi, od, what)
-    dead = np.ones(gi.shape[0], bool)
-    dead[ids.astype(np.int64)] = False
-    assert (gi[dead] == np.uint32(0xFFFFFFFF)).all(), f"{what}: a row of a dead id was written"
-    assert np.isinf(gd[dead]).all(), what
+    for start in (0, 1):
+        t.set_param(bdl.PARAM_GRAPH_START, start)
+        gi, gd = t.knn_graph(k)
+        t.sync()
+        gi = gi.cpu().numpy().view(np.uint32)
+        gd = gd.cpu().numpy()
+        tag = f"{what} start={start}"
+        if len(ids):
+            assert_knn_equal(gi[ids.astype(np.int64)], gd[ids.astype(np.int64)], oi, od, tag)
+        dead = np.ones(gi.shape[0], bool)
+        dead[ids.astype(np.int64)] = False
+        assert (gi[dead] == np.uint32(0xFFFFFFFF)).all(), f"{tag}: a row of a dead id was written"
+        assert np.isinf(gd[dead]).all(), tag
+    t.set_param(bdl.PARAM_GRAPH_START, 0)
 
 
 @pytest.mark.parametrize("seed,d,leaf,X,k,clustered,split", [
@@ -165,13 +175,16 @@ def test_graph_equals_knn_at_scale(torch, bdl):
     live[e] = False
     lid = np.flatnonzero(live)
     ld = torch.from_numpy(lid).cuda()
-    gi, gd = t.knn_graph(k)
     qi, qd = t.knn(dp[ld], k)
-    t.sync()
-    assert torch.equal(gi[ld], qi), "graph ids differ from kNN_L"
-    assert torch.equal(gd[ld].view(torch.int32), qd.view(torch.int32)), \
-        "graph distances differ from kNN_L"
     sel = lid[np.random.default_rng(42).choice(len(lid), 64, replace=False)]
     oi, od = oracle.bruteforce_knn(pts[live], lid.astype(np.uint32), pts[sel], k)
-    assert_knn_equal(gi.cpu().numpy()[sel], gd.cpu().numpy()[sel], oi, od, "graph 2M sampled")
+    for start in (0, 1):
+        t.set_param(bdl.PARAM_GRAPH_START, start)
+        gi, gd = t.knn_graph(k)
+        t.sync()
+        assert torch.equal(gi[ld], qi), f"start={start}: graph ids differ from kNN_L"
+        assert torch.equal(gd[ld].view(torch.int32), qd.view(torch.int32)), \
+            f"start={start}: graph distances differ from kNN_L"
+        assert_knn_equal(gi.cpu().numpy()[sel], gd.cpu().numpy()[sel], oi, od,
+                         f"graph 2M sampled start={start}")
     t.close()
