@@ -1011,11 +1011,12 @@ int run_batch(bdl_tree* t, const bdl_knn_request* reqs, int nreq) {
   if (hipEventSynchronize(t->bslot_ev[slot]) != hipSuccess)
     return fail(BDL_EHIP, "staging wait failed");
   KnnReqDev* h = t->h_breqs[slot];
-  uint64_t total = 0;
+  uint64_t total = 0, largest = 0;
   int kmax = 0, m = 0;
   for (int i = 0; i < nreq; ++i) {
     const bdl_knn_request& r = reqs[i];
     if (r.nq == 0) continue;
+    if ((uint64_t)r.nq > largest) largest = (uint64_t)r.nq;
     h[m].q = r.q;
     h[m].out_ids = r.out_ids;
     h[m].out_d2 = r.out_d2;
@@ -1039,9 +1040,14 @@ int run_batch(bdl_tree* t, const bdl_knn_request* reqs, int nreq) {
       hipEventRecord(t->bslot_ev[slot], t->s) != hipSuccess)
     return fail(BDL_EHIP, "request table copy failed");
   t->bslot ^= 1;
-  // the shape is chosen for the bucket, so that one graph serves it
+  // the shape is the one a plain call of the largest request would get
+  // (rounded up to a power of two, so that one graph serves every batch
+  // whose largest request falls in the same bucket): merged requests fill
+  // the device better, but their queries are no denser among the points
   bool sort = true;
-  const KnnLaunch L = choose_launch(t, kmax, cap, &sort);
+  uint64_t shape_nq = 1;
+  while (shape_nq < largest) shape_nq <<= 1;
+  const KnnLaunch L = choose_launch(t, kmax, shape_nq, &sort);
   const int kt = kmax_bucket(L.mode, kmax);
   t->pt.begin(BDL_PH_TRAVERSE);
   if (t->use_graphs) {
