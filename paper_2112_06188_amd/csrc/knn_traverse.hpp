@@ -45,6 +45,16 @@ __device__ inline float select_dim(const float (&qq)[D], int dim) {
   return v;
 }
 
+// qq[dim] for a dim that may differ per lane, by masks (a chain of selects here would be
+// turned into an indexed load from private memory)
+template <int D>
+__device__ __forceinline__ float select_dim_masked(const float (&qq)[D], int dim) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) r |= (dim == j ? 0xFFFFFFFFu : 0u) & __float_as_uint(qq[j]);
+  return __uint_as_float(r);
+}
+
 // mindist^2 from the query to a box lo[0..D), hi[0..D): per dimension the
 // gap max(lo - q, 0, q - hi), accumulated like a point distance.
 template <int D>
@@ -52,9 +62,8 @@ __device__ inline float box_dist2(const float (&qq)[D], const float* box) {
   float acc = 0.0f;
 #pragma unroll
   for (int j = 0; j < D; ++j) {
-    float a = box[j] - qq[j];
-    float b = qq[j] - box[D + j];
-    float t = a > 0.0f ? a : (b > 0.0f ? b : 0.0f);
+    // lo <= hi in every box, so at most one of the two gaps is positive
+    const float t = fmaxf(fmaxf(box[j] - qq[j], qq[j] - box[D + j]), 0.0f);
     acc = __builtin_fmaf(t, t, acc);
   }
   return acc;
@@ -64,12 +73,17 @@ __device__ inline float box_dist2(const float (&qq)[D], const float* box) {
 // largest key falls off the end.  With g[j] = (a[j] > c), which is false
 // below the insertion point and true from it on:
 //   new a[j] = g[j-1] ? a[j-1] : (g[j] ? c : a[j]),  new a[0] = g[0] ? c : a[0].
-// All comparisons use the old values, so they issue back to back.
+// All comparisons use the old values, so they issue back to back.  Each
+// g[j] goes through the wave's compare mask (a ballot of the lanes' compares
+// and its inverse), which keeps the compiler from rewriting the selects as
+// a minimum and a maximum per position with a 64-bit compare each.  If c is
+// not below a[KMAX-1], every g[j] is false and a is left as it is.
 template <int KMAX>
 __device__ inline void topk_insert(uint64_t (&a)[KMAX], uint64_t c) {
   bool g[KMAX];
 #pragma unroll
-  for (int j = 0; j < KMAX; ++j) g[j] = a[j] > c;
+  for (int j = 0; j < KMAX; ++j)
+    g[j] = __builtin_amdgcn_inverse_ballot_w64(__builtin_amdgcn_uicmpl(a[j], c, 34 /* ugt */));
 #pragma unroll
   for (int j = KMAX - 1; j > 0; --j) a[j] = g[j - 1] ? a[j - 1] : (g[j] ? c : a[j]);
   a[0] = g[0] ? c : a[0];
@@ -85,8 +99,8 @@ __device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb) {
   return x * q + (x < r ? x : r) + (b >> 3);
 }
 
-// Work distribution in groups of 64 consecutive (Hilbert-ordered) queries,
-// one group per wavefront at a time.
+// Work distribution in groups of `group` (64 unless stated) consecutive
+// (Hilbert-ordered) queries, one group per wavefront at a time.
 //
 // Without a queue, wave w of the launch takes group w once (blocks remapped
 // with xcd_block).  With a queue the grid is persistent: the groups are split
@@ -128,10 +142,10 @@ struct GroupSched {
   }
 };
 
-__device__ inline GroupSched make_sched(uint32_t* queue, uint64_t nq) {
+__device__ inline GroupSched make_sched(uint32_t* queue, uint64_t nq, uint32_t group = 64) {
   GroupSched gs;
   gs.queue = queue;
-  gs.ngroups = (uint32_t)((nq + 63) >> 6);
+  gs.ngroups = (uint32_t)((nq + group - 1) / group);
   gs.home = blockIdx.x & 7u;
   gs.sweep = 0;
   gs.fixed = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -297,6 +311,15 @@ typedef const __attribute__((address_space(4))) vf4* cvf4_ptr;
 
 __device__ inline cvf4_ptr as_cvf4(const float* p) { return (cvf4_ptr)(p); }
 
+// A value the whole wavefront holds alike, kept in a scalar register: the
+// compiler otherwise moves node fields that pass through selects and loop
+// merges into vector registers, and a per-lane split dimension then turns
+// the choice of the query's coordinate into an indexed access to memory.
+__device__ __forceinline__ float wave_uniform(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
 template <int NV>
 __device__ inline void load_node(cvf4_ptr nodes, int n, float (&f)[4 * NV]) {
 #pragma unroll
@@ -309,50 +332,69 @@ __device__ inline void load_node(cvf4_ptr nodes, int n, float (&f)[4 * NV]) {
   }
 }
 
-// Wavefront-cooperative variant: the 64 lanes of a wave hold 64 queries that
-// are neighbours in Hilbert-curve order and walk each tree together, depth first.
-// At an internal node both children are read at once and each is tested by a
-// ballot over the lanes' strict prune tests: a child is entered when ANY lane
-// may still find a neighbour in it.  The near child (the side of the split
-// where the majority of the wave's queries lie) is entered first; the far one
-// is pushed on a wave-uniform stack kept in one VGPR (entry i in lane i) and
-// tested again when popped.  Node and leaf data are read at wave-uniform
-// addresses (scalar loads into SGPRs); every lane keeps its own k best keys.
-// Entering extra nodes never changes a lane's result.
-template <int D, int KMAX>
+// Wavefront-cooperative variant: the 64 lanes of a wave hold 64 * QPL queries
+// that are neighbours in Hilbert-curve order (lane l holds queries l, l + 64,
+// ... of its group) and walk each tree together, depth first.  At an internal
+// node both children are read at once and each is tested by a ballot over the
+// strict prune tests of all the wave's queries: a child is entered when ANY
+// query may still find a neighbour in it.  The near child (the side of the
+// split where the majority of the wave's queries lie) is entered first; the
+// far one is pushed on a wave-uniform stack kept in one VGPR (entry i in
+// lane i) and tested again when popped.  Node and leaf data are read at
+// wave-uniform addresses (scalar loads into SGPRs); every query keeps its own
+// k best keys.  Entering extra nodes never changes a query's result.
+//
+// The kernel is bound by instruction issue: every lane takes part in every
+// node and record any query of its wave needs.  With QPL queries per lane a
+// wave's path serves more queries, and the path of 64 * QPL neighbouring
+// queries grows more slowly than their number (the boundary of the region
+// they cover grows more slowly than its volume), so the work per query
+// drops; each lane pays with QPL sets of registers.
+template <int D, int KMAX, int QPL>
 __device__ __forceinline__ void knn_wave_group(const KnnQueries& Q, const uint32_t* __restrict__ order,
                                                const LevelViews* __restrict__ views,
                                                uint32_t* __restrict__ err,
-                                               unsigned long long* __restrict__ stats, uint64_t t,
+                                               unsigned long long* __restrict__ stats, uint64_t t0,
                                                uint64_t nq) {
   constexpr int S = (D + 1 + 3) & ~3;
   constexpr int NS = (5 + 2 * D + 3) & ~3;
   constexpr int SV = S / 4;
   constexpr int NV = NS / 4;
-  const bool valid = t < nq;
   const int lane = __lane_id();
-  const uint64_t gi = valid ? (order ? (uint64_t)order[t] : t) : 0;
-  // only k is needed during the traversal; the request's output location is
-  // read afterwards, so that it does not occupy registers meanwhile
-  const uint32_t rq = (valid && Q.qreq) ? Q.qreq[gi] : 0u;
-  const int k = !valid ? KMAX : (Q.qreq ? Q.reqs[rq].k : Q.one.k);
-  float qq[D];
+  float qq[QPL][D];
+  uint64_t key[QPL][KMAX];
+  uint64_t vm[QPL];
+  int nvalid = 0;
 #pragma unroll
-  for (int j = 0; j < D; ++j) qq[j] = valid ? Q.q[gi * D + j] : 0.0f;
-  const int skip = KMAX - k;
-  uint64_t key[KMAX];
-  // a lane without a query never asks for a node: its keys are all 0, so no
-  // box distance is ever within its k-th distance
+  for (int u = 0; u < QPL; ++u) {
+    const uint64_t t = t0 + 64u * u;
+    const bool valid = t < nq;
+    const uint64_t gi = valid ? (order ? (uint64_t)order[t] : t) : 0;
+    // only k is needed during the traversal; the request's output location
+    // is read afterwards, so that it does not occupy registers meanwhile
+    const int k = !valid ? KMAX : (Q.qreq ? Q.reqs[Q.qreq[gi]].k : Q.one.k);
 #pragma unroll
-  for (int j = 0; j < KMAX; ++j) key[j] = (j < skip || !valid) ? 0ull : kPadKey;
-  const uint64_t vmask = __ballot(valid);
-  const int nvalid = __popcll(vmask);
+    for (int j = 0; j < D; ++j) qq[u][j] = valid ? Q.q[gi * D + j] : 0.0f;
+    // a lane without a query never asks for a node or a record: its keys are
+    // all 0, so no distance is below its k-th; keys below KMAX - k are 0 too
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) key[u][j] = (j < KMAX - k || !valid) ? 0ull : kPadKey;
+    vm[u] = __ballot(valid);
+    nvalid += __popcll(vm[u]);
+  }
   if (nvalid == 0) return;
   uint32_t c_nodes = 0, c_leaves = 0, c_points = 0;
 
+  // (the lanes without a query are masked out after the ballot, so that the
+  // test itself runs without a branch)
   auto wanted = [&](const float (&f)[NS]) -> bool {
-    const float worst = __uint_as_float((uint32_t)(key[KMAX - 1] >> 32));
-    return __ballot(valid && !(box_dist2<D>(qq, f + NF_BOX) > worst)) != 0ull;
+    uint64_t any = 0;
+#pragma unroll
+    for (int u = 0; u < QPL; ++u) {
+      const float worst = __uint_as_float((uint32_t)(key[u][KMAX - 1] >> 32));
+      any |= __ballot(!(box_dist2<D>(qq[u], f + NF_BOX) > worst)) & vm[u];
+    }
+    return any != 0ull;
   };
 
   const int nviews = views->n;
@@ -376,9 +418,9 @@ __device__ __forceinline__ void knn_wave_group(const KnnQueries& Q, const uint32
           if (lane == 0) atomicOr(err, 8u);
           break;
         }
-        const int dim = __float_as_int(cur[NF_DIM]);
-        const int a = __float_as_int(cur[NF_A]);
-        const int b = __float_as_int(cur[NF_B]);
+        const int dim = wave_uniform(__float_as_int(cur[NF_DIM]));
+        const int a = wave_uniform(__float_as_int(cur[NF_A]));
+        const int b = wave_uniform(__float_as_int(cur[NF_B]));
         if (dim < 0) {
           if ((uint32_t)a > ns || (uint32_t)b > ns - (uint32_t)a) {
             if (lane == 0) atomicOr(err, 2u);
@@ -389,8 +431,11 @@ __device__ __forceinline__ void knn_wave_group(const KnnQueries& Q, const uint32
           // the leaf's records are read four at a time at wave-uniform
           // addresses (scalar loads into SGPRs).  Record arrays carry
           // kRecPad spare records, so reading up to three past the leaf's end
-          // stays in bounds; a record past the end or erased gets the
-          // padding key, which never enters the k best.
+          // stays in bounds; records past the end and erased ones are
+          // skipped by wave-uniform branches.  A record enters the insertion
+          // only where its distance is at most the query's k-th (a superset
+          // of the keys below the k-th key; the insertion leaves the keys as
+          // they are for the others).
           const int end = a + b;
           for (int sl = a; sl < end; sl += 4) {
             float r[4][S];
@@ -398,27 +443,30 @@ __device__ __forceinline__ void knn_wave_group(const KnnQueries& Q, const uint32
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
 #pragma unroll
-              for (int u = 0; u < SV; ++u) {
-                const vf4 x = rp[i * SV + u];
-                r[i][4 * u + 0] = x.x;
-                r[i][4 * u + 1] = x.y;
-                r[i][4 * u + 2] = x.z;
-                r[i][4 * u + 3] = x.w;
+              for (int w = 0; w < SV; ++w) {
+                const vf4 x = rp[i * SV + w];
+                r[i][4 * w + 0] = x.x;
+                r[i][4 * w + 1] = x.y;
+                r[i][4 * w + 2] = x.z;
+                r[i][4 * w + 3] = x.w;
               }
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const uint32_t id = __float_as_uint(r[i][D]);
-              float acc = 0.0f;
+              if (sl + i >= end || id == kTomb) continue;
 #pragma unroll
-              for (int j = 0; j < D; ++j) {
-                float tt = qq[j] - r[i][j];
-                acc = __builtin_fmaf(tt, tt, acc);
+              for (int u = 0; u < QPL; ++u) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                  const float tt = qq[u][j] - r[i][j];
+                  acc = __builtin_fmaf(tt, tt, acc);
+                }
+                const float worst = __uint_as_float((uint32_t)(key[u][KMAX - 1] >> 32));
+                if (acc <= worst)
+                  topk_insert<KMAX>(key[u], ((uint64_t)__float_as_uint(acc) << 32) | id);
               }
-              const bool skip_rec = sl + i >= end || id == kTomb;
-              const uint64_t ck =
-                  skip_rec ? kPadKey : (((uint64_t)__float_as_uint(acc) << 32) | id);
-              if (ck < key[KMAX - 1]) topk_insert<KMAX>(key, ck);
             }
           }
           have = false;
@@ -427,8 +475,12 @@ __device__ __forceinline__ void knn_wave_group(const KnnQueries& Q, const uint32
             if (lane == 0) atomicOr(err, 1u);
             break;
           }
-          const uint64_t lv = __ballot(valid && select_dim<D>(qq, dim) < cur[NF_SPLIT]);
-          const bool left_first = 2 * __popcll(lv) >= nvalid;
+          const float split = wave_uniform(cur[NF_SPLIT]);
+          int nleft = 0;
+#pragma unroll
+          for (int u = 0; u < QPL; ++u)
+            nleft += __popcll(__ballot(select_dim_masked<D>(qq[u], dim) < split) & vm[u]);
+          const bool left_first = 2 * nleft >= nvalid;
           float fa[NS], fb[NS];
           load_node<NV>(nodes, a, fa);
           load_node<NV>(nodes, b, fb);
@@ -447,7 +499,7 @@ __device__ __forceinline__ void knn_wave_group(const KnnQueries& Q, const uint32
           }
           if (wn || wf) {
 #pragma unroll
-            for (int u = 0; u < NS; ++u) cur[u] = (left_first == wn) ? fa[u] : fb[u];
+            for (int w = 0; w < NS; ++w) cur[w] = wave_uniform((left_first == wn) ? fa[w] : fb[w]);
             have = true;
           } else {
             have = false;
@@ -467,31 +519,44 @@ __device__ __forceinline__ void knn_wave_group(const KnnQueries& Q, const uint32
       }
     }
   }
-  // counts per lane with a query: wave-level work times the active lanes
+  // counts per query: wave-level work times the queries of the wave
   if (stats && lane == 0) {
     atomicAdd(&stats[0], (unsigned long long)c_nodes * nvalid);
     atomicAdd(&stats[1], (unsigned long long)c_leaves * nvalid);
     atomicAdd(&stats[2], (unsigned long long)c_points * nvalid);
   }
-  if (!valid) return;
-  const KnnReqDev R = Q.qreq ? Q.reqs[rq] : Q.one;
-  const uint64_t qi = gi - R.qoff;
 #pragma unroll
-  for (int j = 0; j < KMAX; ++j) {
-    if (j >= skip) {
-      const uint64_t o = qi * (uint64_t)k + (uint64_t)(j - skip);
-      R.out_ids[o] = (uint32_t)key[j];
-      R.out_d2[o] = __uint_as_float((uint32_t)(key[j] >> 32));
+  for (int u = 0; u < QPL; ++u) {
+    const uint64_t t = t0 + 64u * u;
+    if (t >= nq) continue;
+    const uint64_t gi = order ? (uint64_t)order[t] : t;
+    const KnnReqDev R = Q.qreq ? Q.reqs[Q.qreq[gi]] : Q.one;
+    const int k = R.k;
+    const uint64_t qi = gi - R.qoff;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      if (j >= KMAX - k) {
+        const uint64_t o = qi * (uint64_t)k + (uint64_t)(j - (KMAX - k));
+        R.out_ids[o] = (uint32_t)key[u][j];
+        R.out_d2[o] = __uint_as_float((uint32_t)(key[u][j] >> 32));
+      }
     }
   }
 }
 
 // Occupancy: for small d and k the kernel is held to eight wavefronts per
-// SIMD (64 VGPRs, a few spilled), which measured 1.5% faster than seven;
-// larger instances keep the compiler's choice (a minimum of one).
+// SIMD (64 VGPRs), which measured faster than seven; larger instances keep
+// the compiler's choice (a minimum of one).
 template <int D, int KMAX>
 constexpr int wave_kernel_min_waves() {
   return (D <= 3 && KMAX <= 5) ? 8 : 1;
+}
+
+// Queries per lane of the wavefront-per-group kernel: two where the registers
+// allow it (small d and k), else one.
+template <int D, int KMAX>
+constexpr int wave_kernel_qpl() {
+  return (D <= 3 && KMAX <= 5) ? 2 : 1;
 }
 
 template <int D, int KMAX, bool PERSIST>
@@ -500,11 +565,13 @@ __attribute__((amdgpu_waves_per_eu(wave_kernel_min_waves<D, KMAX>())))
 k_knn_wave(KnnQueries Q, const uint32_t* __restrict__ order,
            const LevelViews* __restrict__ views, uint32_t* __restrict__ err,
            unsigned long long* __restrict__ stats, uint32_t* __restrict__ queue) {
+  constexpr int QPL = wave_kernel_qpl<D, KMAX>();
   const uint64_t nq = Q.nq_dev ? *Q.nq_dev : Q.nq;
-  GroupSched gs = make_sched(PERSIST ? queue : nullptr, nq);
+  GroupSched gs = make_sched(PERSIST ? queue : nullptr, nq, 64 * QPL);
   uint32_t g;
   while (gs.next(g))
-    knn_wave_group<D, KMAX>(Q, order, views, err, stats, (uint64_t)g * 64 + __lane_id(), nq);
+    knn_wave_group<D, KMAX, QPL>(Q, order, views, err, stats,
+                                 (uint64_t)g * (64 * QPL) + __lane_id(), nq);
 }
 
 // ---------------------------------------------------------------------------
@@ -533,16 +600,6 @@ k_knn_wave(KnnQueries Q, const uint32_t* __restrict__ order,
 constexpr int kQStack = 2048;        // pending nodes per wave (LDS)
 constexpr int kQViewShift = 26;      // stack entry: view << 26 | node
 constexpr uint32_t kQNodeMask = (1u << kQViewShift) - 1u;
-
-// qq[dim] for a per-lane dim, by masks (a chain of selects here would be
-// turned into an indexed load from private memory)
-template <int D>
-__device__ __forceinline__ float select_dim_masked(const float (&qq)[D], int dim) {
-  uint32_t r = 0;
-#pragma unroll
-  for (int j = 0; j < D; ++j) r |= (dim == j ? 0xFFFFFFFFu : 0u) & __float_as_uint(qq[j]);
-  return __uint_as_float(r);
-}
 
 __device__ inline uint64_t lanemask_lt64() {
   const int l = __lane_id();
@@ -834,7 +891,9 @@ void launch_one(const KnnLaunch& L, const KnnQueries& Q, uint64_t grid_q, const 
   const void* kern = L.mode == kKnnWave
                          ? reinterpret_cast<const void*>(&k_knn_wave<D, KMAX, true>)
                          : reinterpret_cast<const void*>(&k_knn<D, KMAX, true>);
-  uint64_t nb = (grid_q + bs - 1) / bs;
+  // queries per thread: the group kernel's lanes hold several
+  const uint64_t per = L.mode == kKnnWave ? (uint64_t)wave_kernel_qpl<D, KMAX>() : 1u;
+  uint64_t nb = (grid_q + bs * per - 1) / (bs * per);
   bool persist = false;
   if (L.persistent && L.queue) {
     const uint64_t res = resident_blocks(kern, bs);
