@@ -55,6 +55,21 @@ __device__ __forceinline__ float select_dim_masked(const float (&qq)[D], int dim
   return __uint_as_float(r);
 }
 
+// qq[dim] for a dim the whole wavefront holds alike (0 <= dim < D): one
+// bitwise select (v_bfi) per dimension above the first, with the bit mask
+// made by the scalar unit as the sign of (dim ^ j) - 1.  (A chain of selects
+// on dim == j is turned by the compiler into an indexed access to memory.)
+template <int D>
+__device__ __forceinline__ float select_dim_uniform(const float (&qq)[D], int dim) {
+  uint32_t v = __float_as_uint(qq[0]);
+#pragma unroll
+  for (int j = 1; j < D; ++j) {
+    const uint32_t m = (uint32_t)(((dim ^ j) - 1) >> 31);
+    v = (m & __float_as_uint(qq[j])) | (~m & v);
+  }
+  return __uint_as_float(v);
+}
+
 // mindist^2 from the query to a box lo[0..D), hi[0..D): per dimension the
 // gap max(lo - q, 0, q - hi), accumulated like a point distance.
 template <int D>
@@ -335,12 +350,12 @@ __device__ inline void load_node(cvf4_ptr nodes, int n, float (&f)[4 * NV]) {
 // Wavefront-cooperative variant: the 64 lanes of a wave hold 64 * QPL queries
 // that are neighbours in Hilbert-curve order (lane l holds queries l, l + 64,
 // ... of its group) and walk each tree together, depth first.  At an internal
-// node both children are read at once and each is tested by a ballot over the
-// strict prune tests of all the wave's queries: a child is entered when ANY
-// query may still find a neighbour in it.  The near child (the side of the
-// split where the majority of the wave's queries lie) is entered first; the
-// far one is pushed on a wave-uniform stack kept in one VGPR (entry i in
-// lane i) and tested again when popped.  Node and leaf data are read at
+// node both children are read at once.  The near child (the side of the split
+// where the majority of the wave's queries lie) is entered first, without a
+// prune test; the far child is tested by a ballot over the strict prune tests
+// of all the wave's queries (it is entered when ANY query may still find a
+// neighbour in it), pushed on a wave-uniform stack kept in one VGPR (entry i
+// in lane i) and tested again when popped.  Node and leaf data are read at
 // wave-uniform addresses (scalar loads into SGPRs); every query keeps its own
 // k best keys.  Entering extra nodes never changes a query's result.
 //
@@ -475,20 +490,22 @@ __device__ __forceinline__ void knn_wave_group(const KnnQueries& Q, const uint32
             if (lane == 0) atomicOr(err, 1u);
             break;
           }
-          const float split = wave_uniform(cur[NF_SPLIT]);
-          int nleft = 0;
-#pragma unroll
-          for (int u = 0; u < QPL; ++u)
-            nleft += __popcll(__ballot(select_dim_masked<D>(qq[u], dim) < split) & vm[u]);
-          const bool left_first = 2 * nleft >= nvalid;
           float fa[NS], fb[NS];
           load_node<NV>(nodes, a, fa);
           load_node<NV>(nodes, b, fb);
           c_nodes += 2;
-          const bool wa = wanted(fa);
-          const bool wb = wanted(fb);
-          const bool wn = left_first ? wa : wb;
-          const bool wf = left_first ? wb : wa;
+          // the near child (the side of the split where at least half of
+          // the wave's queries lie) is entered without a test: at least one
+          // query almost always needs it, and a box test costs about as much
+          // as scanning two records; the far child is tested
+          const float split = wave_uniform(cur[NF_SPLIT]);
+          int nleft = 0;
+#pragma unroll
+          for (int u = 0; u < QPL; ++u)
+            nleft += __popcll(__ballot(select_dim_uniform<D>(qq[u], dim) < split) & vm[u]);
+          const bool left_first = 2 * nleft >= nvalid;
+          const bool wn = true;
+          const bool wf = left_first ? wanted(fb) : wanted(fa);
           if (wn && wf) {
             if (sp >= 64) {
               if (lane == 0) atomicOr(err, 16u);
