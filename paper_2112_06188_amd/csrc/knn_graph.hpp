@@ -76,13 +76,16 @@ __device__ __forceinline__ void knn_graph_group(const LevelViews* __restrict__ v
   // a lane without a live point asks for no node (its keys are all 0)
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) key[j] = (j < skip || !valid) ? 0ull : kPadKey;
-  const int nvalid = __popcll(__ballot(valid));
+  const uint64_t vmask = __ballot(valid);
+  const int nvalid = __popcll(vmask);
   if (nvalid == 0) return;
   uint32_t c_nodes = 0, c_leaves = 0, c_points = 0;
 
+  // (lanes without a point are masked out after the ballot, so that the
+  // test runs without a branch)
   auto wanted = [&](const float (&f)[NS]) -> bool {
     const float worst = __uint_as_float((uint32_t)(key[KMAX - 1] >> 32));
-    return __ballot(valid && !(box_dist2<D>(qq, f + NF_BOX) > worst)) != 0ull;
+    return (__ballot(!(box_dist2<D>(qq, f + NF_BOX) > worst)) & vmask) != 0ull;
   };
 
   bool bad = false;
@@ -117,9 +120,10 @@ __device__ __forceinline__ void knn_graph_group(const LevelViews* __restrict__ v
         break;
       }
       if (have) {
-        const int dim = __float_as_int(cur[NF_DIM]);
-        const int a = __float_as_int(cur[NF_A]);
-        const int b = __float_as_int(cur[NF_B]);
+        // node fields are the same on every lane: kept in scalar registers
+        const int dim = wave_uniform(__float_as_int(cur[NF_DIM]));
+        const int a = wave_uniform(__float_as_int(cur[NF_A]));
+        const int b = wave_uniform(__float_as_int(cur[NF_B]));
         if (dim < 0) {
           if ((uint32_t)a > ns || (uint32_t)b > ns - (uint32_t)a) {
             bad = true;
@@ -129,7 +133,9 @@ __device__ __forceinline__ void knn_graph_group(const LevelViews* __restrict__ v
           c_points += (uint32_t)b;
           // records four at a time at wave-uniform addresses; the arrays
           // carry spare records, so reading up to three past the end stays
-          // in bounds, and such records get the padding key
+          // in bounds, and such records are skipped (as are erased ones); a
+          // record enters the insertion where its distance is at most the
+          // lane's k-th
           const int end = a + b;
           for (int sl = a; sl < end; sl += 4) {
             float r[4][S];
@@ -148,16 +154,16 @@ __device__ __forceinline__ void knn_graph_group(const LevelViews* __restrict__ v
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const uint32_t id = __float_as_uint(r[i][D]);
+              if (sl + i >= end || id == kTomb) continue;
               float acc = 0.0f;
 #pragma unroll
               for (int j = 0; j < D; ++j) {
                 const float tt = qq[j] - r[i][j];
                 acc = __builtin_fmaf(tt, tt, acc);
               }
-              const bool skip_rec = sl + i >= end || id == kTomb;
-              const uint64_t ck =
-                  skip_rec ? kPadKey : (((uint64_t)__float_as_uint(acc) << 32) | id);
-              if (ck < key[KMAX - 1]) topk_insert<KMAX>(key, ck);
+              const float worst = __uint_as_float((uint32_t)(key[KMAX - 1] >> 32));
+              if (acc <= worst)
+                topk_insert<KMAX>(key, ((uint64_t)__float_as_uint(acc) << 32) | id);
             }
           }
           have = false;
@@ -166,7 +172,10 @@ __device__ __forceinline__ void knn_graph_group(const LevelViews* __restrict__ v
             bad = true;
             break;
           }
-          const uint64_t lv = __ballot(valid && select_dim<D>(qq, dim) < cur[NF_SPLIT]);
+          // near child first: the side of the split where at least half of
+          // the lanes' points lie
+          const uint64_t lv =
+              __ballot(select_dim_uniform<D>(qq, dim) < wave_uniform(cur[NF_SPLIT])) & vmask;
           const bool left_first = 2 * __popcll(lv) >= nvalid;
           float fa[NS], fb[NS];
           load_node<NV>(nodes, a, fa);
@@ -186,7 +195,7 @@ __device__ __forceinline__ void knn_graph_group(const LevelViews* __restrict__ v
           }
           if (wn || wf) {
 #pragma unroll
-            for (int u = 0; u < NS; ++u) cur[u] = (left_first == wn) ? fa[u] : fb[u];
+            for (int u = 0; u < NS; ++u) cur[u] = wave_uniform((left_first == wn) ? fa[u] : fb[u]);
             have = true;
           } else {
             have = false;
