@@ -183,20 +183,24 @@ struct PoolSrc {
 // One static tree (or the buffer's tree) as seen by the k-NN kernel.  Its
 // node count is filled in on the device from the builds' counts (slot
 // kMaxLevels of that array is the buffer's tree).
+// flags of a LevelView
+constexpr uint32_t kViewBalanced = 1u;  // height within log2(slots / leaf) + kBalancedMargin
+constexpr int kBalancedMargin = 6;
+
 struct LevelView {
   const float* rec;
   const float* nodes;
   uint32_t n_slots;
   uint32_t n_nodes;
   uint32_t level;  // static tree index, or kMaxLevels for the buffer's tree
-  uint32_t pad_;
+  uint32_t flags;  // kViewBalanced, set on the device with the node count
 };
 
 constexpr int kMaxViews = kMaxLevels + 1;
 constexpr int kMaxBatchReqs = 65536;  // requests per batched k-NN launch
 struct LevelViews {
   int32_t n;
-  int32_t pad_;
+  uint32_t flags;  // kViewBalanced when every view has it
   LevelView v[kMaxViews];
 };
 

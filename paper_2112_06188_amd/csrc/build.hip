@@ -1580,7 +1580,9 @@ __global__ void k_build_done(BuildCounters* c, const Job* jobs, int njobs, uint3
   const int j = threadIdx.x;
   if (j < njobs) {
     const uint32_t lv = jobs[j].level;
-    level_nodes[lv == kBufferLevel ? (uint32_t)kMaxLevels : lv] = c->job_nodes[j];
+    const uint32_t at = lv == kBufferLevel ? (uint32_t)kMaxLevels : lv;
+    level_nodes[at] = c->job_nodes[j];
+    level_nodes[kLevelHeightBase + at] = c->job_height[j];
   }
   if (j == 0) {
     const uint32_t e = c->err | (c->retry ? 1024u : 0u);
@@ -1589,10 +1591,23 @@ __global__ void k_build_done(BuildCounters* c, const Job* jobs, int njobs, uint3
   }
 }
 
-// Node counts of the trees k-NN visits, from the builds' published counts.
-__global__ void k_patch_views(LevelViews* v, const uint32_t* level_nodes) {
+// Node counts of the trees k-NN visits, from the builds' published counts,
+// and their kViewBalanced flags from the published heights.
+__global__ void k_patch_views(LevelViews* v, const uint32_t* level_nodes, uint32_t leaf,
+                              int balanced_ok) {
   const int i = threadIdx.x;
-  if (i < v->n) v->v[i].n_nodes = level_nodes[v->v[i].level];
+  if (i < v->n) {
+    const uint32_t lv = v->v[i].level;
+    v->v[i].n_nodes = level_nodes[lv];
+    const uint32_t h = level_nodes[kLevelHeightBase + lv];
+    // ceil(log2(ceil(slots / leaf)))
+    const uint32_t leaves = (v->v[i].n_slots + leaf - 1) / leaf;
+    const uint32_t lg = leaves <= 1u ? 0u : 32u - (uint32_t)__clz((int)(leaves - 1u));
+    v->v[i].flags = (balanced_ok && h <= lg + (uint32_t)kBalancedMargin) ? kViewBalanced : 0u;
+  }
+  const bool skewed = i < v->n && !(v->v[i].flags & kViewBalanced);
+  if (__ballot(skewed) == 0ull && i == 0) v->flags = kViewBalanced;
+  else if (i == 0) v->flags = 0u;
 }
 
 struct U32x64 {
@@ -1791,9 +1806,11 @@ void launch_store_u32(uint32_t* dst, const uint32_t* vals, int n, hipStream_t s)
   hipLaunchKernelGGL(k_store_vals, dim3(1), dim3(64), 0, s, dst, v, n);
 }
 
-void launch_patch_views(LevelViews* views, const uint32_t* level_nodes, hipStream_t s) {
+void launch_patch_views(LevelViews* views, const uint32_t* level_nodes, uint32_t leaf,
+                        bool balanced_ok, hipStream_t s) {
   static_assert(kMaxViews <= 64, "one lane per view");
-  hipLaunchKernelGGL(k_patch_views, dim3(1), dim3(64), 0, s, views, level_nodes);
+  hipLaunchKernelGGL(k_patch_views, dim3(1), dim3(64), 0, s, views, level_nodes, leaf,
+                     balanced_ok ? 1 : 0);
 }
 
 void launch_store_views(LevelViews* dst, const LevelViews& v, hipStream_t s) {

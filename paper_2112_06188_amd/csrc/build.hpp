@@ -59,7 +59,8 @@ void launch_compact_live(const float* rec, int d, uint64_t n, float* soa, uint64
 // `rule` (kSplitSpatial or kSplitObject).  Writes records (slot order),
 // nodes (vEB order) and, where requested, the id map, all on stream s with
 // no host wait: each job's node count is stored on the device in
-// level_nodes[level] (level_nodes[kMaxLevels] for the buffer's tree),
+// level_nodes[level] (level_nodes[kMaxLevels] for the buffer's tree), its
+// height in level_nodes[kLevelHeightBase + the same index],
 // level_nodes[kMaxLevels + 1] receives the number of global-pass depths the
 // build needed, and the device-side checks (scratch overflow, a build that
 // does not end) leave their bits in *sticky_err (device) for the host's next
@@ -73,9 +74,17 @@ int run_build(const JobTable& jt, BuildScratch& sc, int d, uint32_t leaf, uint32
               uint32_t* level_nodes, uint32_t* sticky_err, int* base_depths,
               int64_t* host_waits, const char** err, const PhaseTimer& pt);
 
+// Words of the device array level_nodes: node counts (kMaxLevels + 1), the
+// depth count of the last build, then the trees' heights.
+constexpr int kLevelHeightBase = kMaxLevels + 2;
+constexpr int kLevelPubWords = kLevelHeightBase + kMaxLevels + 1;
+
 // Node counts of the trees k-NN visits, from level_nodes (after every
-// upload of the views).
-void launch_patch_views(LevelViews* views, const uint32_t* level_nodes, hipStream_t s);
+// upload of the views), and each tree's kViewBalanced flag: set when its
+// height is at most ceil(log2(slots / leaf)) + kBalancedMargin and
+// `balanced_ok` (trees whose leaves grow past the leaf size get none).
+void launch_patch_views(LevelViews* views, const uint32_t* level_nodes, uint32_t leaf,
+                        bool balanced_ok, hipStream_t s);
 
 // small utilities
 void launch_store_u32(uint32_t* dst, const uint32_t* vals, int n, hipStream_t s);

@@ -352,7 +352,8 @@ __device__ inline void load_node(cvf4_ptr nodes, int n, float (&f)[4 * NV]) {
 // ... of its group) and walk each tree together, depth first.  At an internal
 // node both children are read at once.  The near child (the side of the split
 // where the majority of the wave's queries lie) is entered first, without a
-// prune test; the far child is tested by a ballot over the strict prune tests
+// prune test when every tree is balanced (kViewBalanced); the far child, and
+// the near one otherwise, is tested by a ballot over the strict prune tests
 // of all the wave's queries (it is entered when ANY query may still find a
 // neighbour in it), pushed on a wave-uniform stack kept in one VGPR (entry i
 // in lane i) and tested again when popped.  Node and leaf data are read at
@@ -365,7 +366,7 @@ __device__ inline void load_node(cvf4_ptr nodes, int n, float (&f)[4 * NV]) {
 // queries grows more slowly than their number (the boundary of the region
 // they cover grows more slowly than its volume), so the work per query
 // drops; each lane pays with QPL sets of registers.
-template <int D, int KMAX, int QPL>
+template <int D, int KMAX, int QPL, bool NEAR_FREE>
 __device__ __forceinline__ void knn_wave_group(const KnnQueries& Q, const uint32_t* __restrict__ order,
                                                const LevelViews* __restrict__ views,
                                                uint32_t* __restrict__ err,
@@ -495,17 +496,21 @@ __device__ __forceinline__ void knn_wave_group(const KnnQueries& Q, const uint32
           load_node<NV>(nodes, b, fb);
           c_nodes += 2;
           // the near child (the side of the split where at least half of
-          // the wave's queries lie) is entered without a test: at least one
-          // query almost always needs it, and a box test costs about as much
-          // as scanning two records; the far child is tested
+          // the wave's queries lie) is entered without a test when every
+          // tree is balanced: at least one query almost always needs it
+          // there, and a box test costs about as much as scanning two
+          // records.  In a deep, skewed tree (clustered points under
+          // spatial-median splits) an untested near child leads down long
+          // chains of splits no query needs, and it is tested; the far
+          // child always is.
           const float split = wave_uniform(cur[NF_SPLIT]);
           int nleft = 0;
 #pragma unroll
           for (int u = 0; u < QPL; ++u)
             nleft += __popcll(__ballot(select_dim_uniform<D>(qq[u], dim) < split) & vm[u]);
           const bool left_first = 2 * nleft >= nvalid;
-          const bool wn = true;
           const bool wf = left_first ? wanted(fb) : wanted(fa);
+          const bool wn = NEAR_FREE || (left_first ? wanted(fa) : wanted(fb));
           if (wn && wf) {
             if (sp >= 64) {
               if (lane == 0) atomicOr(err, 16u);
@@ -584,11 +589,17 @@ k_knn_wave(KnnQueries Q, const uint32_t* __restrict__ order,
            unsigned long long* __restrict__ stats, uint32_t* __restrict__ queue) {
   constexpr int QPL = wave_kernel_qpl<D, KMAX>();
   const uint64_t nq = Q.nq_dev ? *Q.nq_dev : Q.nq;
+  // every tree balanced: the near child is entered without a test
+  const bool near_free = (views->flags & kViewBalanced) != 0u;
   GroupSched gs = make_sched(PERSIST ? queue : nullptr, nq, 64 * QPL);
   uint32_t g;
-  while (gs.next(g))
-    knn_wave_group<D, KMAX, QPL>(Q, order, views, err, stats,
-                                 (uint64_t)g * (64 * QPL) + __lane_id(), nq);
+  while (gs.next(g)) {
+    const uint64_t t0 = (uint64_t)g * (64 * QPL) + __lane_id();
+    if (near_free)
+      knn_wave_group<D, KMAX, QPL, true>(Q, order, views, err, stats, t0, nq);
+    else
+      knn_wave_group<D, KMAX, QPL, false>(Q, order, views, err, stats, t0, nq);
+  }
 }
 
 // ---------------------------------------------------------------------------

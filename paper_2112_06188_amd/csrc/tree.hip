@@ -471,7 +471,8 @@ LevelViews make_views(const bdl_tree* t);
 void upload_views(bdl_tree* t) {
   LevelViews v = make_views(t);
   launch_store_views(t->d_views, v, t->s);
-  launch_patch_views(t->d_views, t->d_level_nodes, t->s);
+  launch_patch_views(t->d_views, t->d_level_nodes, (uint32_t)t->cfg.leaf_size,
+                     t->mode != kModeNoRebuild, t->s);
 }
 
 // Insert_L (Alg. 3) over the pool = buffer (arrival order) ++ batch.  The
@@ -1219,7 +1220,7 @@ int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out) {
     t->pt.mark = phase_mark;
   }
   t->map = (uint64_t*)dmalloc(t, (size_t)cfg->id_capacity * 8);
-  t->d_level_nodes = (uint32_t*)dmalloc(t, (kMaxLevels + 2) * 4);
+  t->d_level_nodes = (uint32_t*)dmalloc(t, kLevelPubWords * 4);
   t->d_live = (uint32_t*)dmalloc(t, kMaxLevels * 4);
   t->d_misc = (uint32_t*)dmalloc(t, 16 * 4);
   t->d_stats = (unsigned long long*)dmalloc(t, 8 * 8);
@@ -1257,7 +1258,7 @@ int bdl_create(const bdl_config* cfg, void* stream, bdl_tree** out) {
   }
   launch_fill_u32((uint32_t*)t->map, 0xFFFFFFFFu, (uint64_t)cfg->id_capacity * 2, t->s);
   launch_fill_u32(t->d_live, 0u, kMaxLevels, t->s);
-  launch_fill_u32(t->d_level_nodes, 0u, kMaxLevels + 2, t->s);
+  launch_fill_u32(t->d_level_nodes, 0u, kLevelPubWords, t->s);
   launch_fill_u32(t->d_misc, 0u, 16, t->s);
   launch_fill_u32((uint32_t*)t->d_stats, 0u, 16, t->s);
   if (ok) upload_views(t);
