@@ -574,20 +574,24 @@ constexpr int wave_kernel_min_waves() {
   return (D <= 3 && KMAX <= 5) ? 8 : 1;
 }
 
-// Queries per lane of the wavefront-per-group kernel: two where the registers
-// allow it (small d and k), else one.
+// Queries per lane of the wavefront-per-group kernel: up to two where the
+// registers allow it (small d and k), else one.  Two are used only for
+// batches of at least kWaveQpl2Queries queries: below that, 128-query groups
+// would give each resident wavefront fewer than two groups, and the launch
+// would lose the wavefronts that hide its load latency (1M queries on the
+// clustered 2D workload: slower with two per lane).
 template <int D, int KMAX>
-constexpr int wave_kernel_qpl() {
+constexpr int wave_kernel_max_qpl() {
   return (D <= 3 && KMAX <= 5) ? 2 : 1;
 }
+constexpr uint64_t kWaveQpl2Queries = 1ull << 21;
 
-template <int D, int KMAX, bool PERSIST>
+template <int D, int KMAX, bool PERSIST, int QPL>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(wave_kernel_min_waves<D, KMAX>())))
 k_knn_wave(KnnQueries Q, const uint32_t* __restrict__ order,
            const LevelViews* __restrict__ views, uint32_t* __restrict__ err,
            unsigned long long* __restrict__ stats, uint32_t* __restrict__ queue) {
-  constexpr int QPL = wave_kernel_qpl<D, KMAX>();
   const uint64_t nq = Q.nq_dev ? *Q.nq_dev : Q.nq;
   // every tree balanced: the near child is entered without a test
   const bool near_free = (views->flags & kViewBalanced) != 0u;
@@ -916,11 +920,14 @@ void launch_one(const KnnLaunch& L, const KnnQueries& Q, uint64_t grid_q, const 
                 const LevelViews* views, uint32_t* err, unsigned long long* stats,
                 hipStream_t s) {
   const int bs = L.block;
-  const void* kern = L.mode == kKnnWave
-                         ? reinterpret_cast<const void*>(&k_knn_wave<D, KMAX, true>)
-                         : reinterpret_cast<const void*>(&k_knn<D, KMAX, true>);
-  // queries per thread: the group kernel's lanes hold several
-  const uint64_t per = L.mode == kKnnWave ? (uint64_t)wave_kernel_qpl<D, KMAX>() : 1u;
+  // queries per thread: the group kernel's lanes may hold two
+  constexpr int QMAX = wave_kernel_max_qpl<D, KMAX>();
+  const bool two = L.mode == kKnnWave && QMAX == 2 && grid_q >= kWaveQpl2Queries;
+  const void* kern = L.mode != kKnnWave
+                         ? reinterpret_cast<const void*>(&k_knn<D, KMAX, true>)
+                         : (two ? reinterpret_cast<const void*>(&k_knn_wave<D, KMAX, true, QMAX>)
+                                : reinterpret_cast<const void*>(&k_knn_wave<D, KMAX, true, 1>));
+  const uint64_t per = two ? 2u : 1u;
   uint64_t nb = (grid_q + bs * per - 1) / (bs * per);
   bool persist = false;
   if (L.persistent && L.queue) {
@@ -934,13 +941,20 @@ void launch_one(const KnnLaunch& L, const KnnQueries& Q, uint64_t grid_q, const 
   }
   if (L.dry_run) return;
   const unsigned g = (unsigned)nb;
-  if (L.mode == kKnnWave) {
+  if (L.mode == kKnnWave && two) {
     if (persist)
-      hipLaunchKernelGGL((k_knn_wave<D, KMAX, true>), dim3(g), dim3(bs), 0, s, Q, order, views,
-                         err, stats, L.queue);
+      hipLaunchKernelGGL((k_knn_wave<D, KMAX, true, QMAX>), dim3(g), dim3(bs), 0, s, Q, order,
+                         views, err, stats, L.queue);
     else
-      hipLaunchKernelGGL((k_knn_wave<D, KMAX, false>), dim3(g), dim3(bs), 0, s, Q, order, views,
-                         err, stats, nullptr);
+      hipLaunchKernelGGL((k_knn_wave<D, KMAX, false, QMAX>), dim3(g), dim3(bs), 0, s, Q, order,
+                         views, err, stats, nullptr);
+  } else if (L.mode == kKnnWave) {
+    if (persist)
+      hipLaunchKernelGGL((k_knn_wave<D, KMAX, true, 1>), dim3(g), dim3(bs), 0, s, Q, order,
+                         views, err, stats, L.queue);
+    else
+      hipLaunchKernelGGL((k_knn_wave<D, KMAX, false, 1>), dim3(g), dim3(bs), 0, s, Q, order,
+                         views, err, stats, nullptr);
   } else {
     if (persist)
       hipLaunchKernelGGL((k_knn<D, KMAX, true>), dim3(g), dim3(bs), 0, s, Q, order, views, err,
