@@ -630,6 +630,7 @@ k_knn_wave(KnnQueries Q, const uint32_t* __restrict__ order,
 // harmless.  Any visiting order gives the exact k nearest, as in the other
 // kernels.
 constexpr int kQStack = 2048;        // pending nodes per wave (LDS)
+constexpr int kQLeaves = 8;          // small leaves scanned together
 constexpr int kQViewShift = 26;      // stack entry: view << 26 | node
 constexpr uint32_t kQNodeMask = (1u << kQViewShift) - 1u;
 
@@ -696,6 +697,75 @@ __device__ __forceinline__ void scan_leaf_wave(const float (&qq)[D], const float
         }
         cand = ((uint64_t)__float_as_uint(acc) << 32) | id;
       }
+    }
+    uint64_t m = __ballot(cand < T.worst);
+    while (m) {
+      const int l = __builtin_ctzll(m);
+      m &= m - 1;
+      T.insert(readlane64(cand, l));
+    }
+  }
+}
+
+// Up to NL leaves of at most 16 records each at once: lane group g (64 / NL
+// lanes) takes leaf g, and each of its lanes NL / 4 of the leaf's records,
+// so that the leaves' records are read by NL / 4 loads per lane instead of
+// one round trip to memory per leaf.  recs/la/lb/cnt are the same on every
+// lane.
+template <int D, int NL>
+__device__ __forceinline__ void scan_leaves_wave(const float (&qq)[D],
+                                                 const float* const (&recs)[NL],
+                                                 const uint32_t (&la)[NL],
+                                                 const uint32_t (&lb)[NL], int cnt,
+                                                 WaveTopK& T) {
+  constexpr int S = (D + 1 + 3) & ~3;
+  constexpr int LPL = 64 / NL;  // lanes per leaf
+  constexpr int RPL = 16 / LPL;  // records per lane
+  static_assert(LPL * NL == 64 && RPL * LPL == 16, "leaves of 16 records over 64 lanes");
+  const int lane = __lane_id();
+  const int g = lane / LPL;
+  const uint32_t r0 = (uint32_t)(lane % LPL);
+  // the lane's leaf by bitwise selects on masks (-1 where g == h), which
+  // the compiler does not turn into an indexed access to memory
+  uint64_t rpv = (uint64_t)recs[0];
+  uint32_t a = la[0], b = lb[0];
+#pragma unroll
+  for (int h = 1; h < NL; ++h) {
+    const uint32_t mk = (uint32_t)(((g ^ h) - 1) >> 31);
+    const uint64_t mk2 = ((uint64_t)mk << 32) | mk;
+    rpv = (mk2 & (uint64_t)recs[h]) | (~mk2 & rpv);
+    a = (mk & la[h]) | (~mk & a);
+    b = (mk & lb[h]) | (~mk & b);
+  }
+  const float* rp = (const float*)rpv;
+  // every record is loaded before any is used
+  float x[RPL][D];
+  uint32_t id[RPL];
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    const uint32_t r = r0 + (uint32_t)(u * LPL);
+    id[u] = kTomb;
+    if (g < cnt && r < b) {
+      const float* xp = rp + (uint64_t)(a + r) * S;
+#pragma unroll
+      for (int j = 0; j < D; ++j) x[u][j] = xp[j];
+      id[u] = __float_as_uint(xp[D]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < D; ++j) x[u][j] = 0.0f;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    uint64_t cand = kPadKey;
+    if (id[u] != kTomb) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const float tt = qq[j] - x[u][j];
+        acc = __builtin_fmaf(tt, tt, acc);
+      }
+      cand = ((uint64_t)__float_as_uint(acc) << 32) | id[u];
     }
     uint64_t m = __ballot(cand < T.worst);
     while (m) {
@@ -887,8 +957,34 @@ k_knn_query(KnnQueries Q, const uint32_t* __restrict__ order, const LevelViews* 
       stk[pos + 1] = tag | nearc;
     }
     size += 2 * (int)__popcll(im);
-    // scan the leaves, one after another with the whole wave
-    uint64_t lm = __ballot(leafn);
+    // scan the leaves with the whole wave: those of at most 16 records
+    // kQLeaves at a time (one memory round trip for them all), larger ones
+    // one after another
+    uint64_t sm = __ballot(leafn && b <= 16u);
+    uint64_t lm = __ballot(leafn) & ~sm;
+    while (sm) {
+      const float* recs[kQLeaves];
+      uint32_t la[kQLeaves], lb[kQLeaves];
+      int cnt = 0;
+#pragma unroll
+      for (int h = 0; h < kQLeaves; ++h) {
+        recs[h] = nullptr;
+        la[h] = 0u;
+        lb[h] = 0u;
+        if (sm) {
+          const int l = __builtin_ctzll(sm);
+          sm &= sm - 1;
+          const int lv = __builtin_amdgcn_readlane(v, l);
+          recs[h] = views->v[lv].rec;
+          la[h] = (uint32_t)__builtin_amdgcn_readlane((int)a, l);
+          lb[h] = (uint32_t)__builtin_amdgcn_readlane((int)b, l);
+          ++cnt;
+          ++c_leaves;
+          c_points += lb[h];
+        }
+      }
+      scan_leaves_wave<D, kQLeaves>(qq, recs, la, lb, cnt, T);
+    }
     while (lm) {
       const int l = __builtin_ctzll(lm);
       lm &= lm - 1;
