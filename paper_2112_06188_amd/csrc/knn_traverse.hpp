@@ -783,6 +783,11 @@ k_knn_query(KnnQueries Q, const uint32_t* __restrict__ order, const LevelViews* 
   constexpr int NS = (5 + 2 * D + 3) & ~3;
   constexpr int NV = NS / 4;
   __shared__ uint32_t stack_all[4][kQStack];
+  // the tree table in LDS: a popped node's tree is read from there, one
+  // dependent trip to memory less per round
+  __shared__ LevelView s_views[kMaxViews];
+  for (int i = threadIdx.x; i < kMaxViews; i += blockDim.x) s_views[i] = views->v[i];
+  __syncthreads();
   const int lane = __lane_id();
   const int w = threadIdx.x >> 6;
   uint32_t* stk = stack_all[w];
@@ -915,7 +920,7 @@ k_knn_query(KnnQueries Q, const uint32_t* __restrict__ order, const LevelViews* 
     __builtin_amdgcn_wave_barrier();
     const int v = (int)(e >> kQViewShift);
     const uint32_t n = e & kQNodeMask;
-    const LevelView* Vp = &views->v[v];
+    const LevelView* Vp = &s_views[v < kMaxViews ? v : 0];
     const uint32_t nn = act0 ? Vp->n_nodes : 0u;
     const uint32_t ns = act0 ? Vp->n_slots : 0u;
     bool act = act0 && n < nn;
