@@ -192,7 +192,7 @@ int bdl_knn_graph(bdl_tree* t, int32_t k, uint32_t* out_ids, float* out_d2);
                                   wavefront per query under kernel 2 (default
                                   131072; 0 disables) */
 #define BDL_PARAM_QUERY_STACK 7 /* pending-node entries per wavefront of kernel
-                                   3, at least 130 (default and maximum 2048);
+                                   3, at least 130 (default and maximum 1536);
                                    a smaller stack walks more subtrees through
                                    parent links instead */
 #define BDL_PARAM_ERASE_ROUTE 8 /* how bdl_erase finds a point.  0 (default):

@@ -629,8 +629,8 @@ k_knn_wave(KnnQueries Q, const uint32_t* __restrict__ order,
 // A key already held is not inserted again, so a leaf met twice is
 // harmless.  Any visiting order gives the exact k nearest, as in the other
 // kernels.
-constexpr int kQStack = 2048;        // pending nodes per wave (LDS)
-constexpr int kQLeaves = 8;          // small leaves scanned together
+constexpr int kQStack = 1536;        // pending nodes per wave (LDS)
+constexpr int kQLeaves = 4;          // small leaves scanned together
 constexpr int kQViewShift = 26;      // stack entry: view << 26 | node
 constexpr uint32_t kQNodeMask = (1u << kQViewShift) - 1u;
 
