@@ -864,7 +864,7 @@ def main():
     ap.add_argument("--workload", default="uniform3d_10m")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--knn-kernel", type=int, default=2, choices=[0, 1, 2],
-                    help="0: one lane per query, 1: one wavefront per 64 queries, "
+                    help="0: one lane per query, 1: one wavefront per group of 64 or 128 queries, "
                          "2: chosen per launch from the query density")
     ap.add_argument("--cpu-sample", type=int, default=200_000,
                     help="queries the serial CPU oracle answers for the baseline (0: skip)")

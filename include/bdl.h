@@ -185,7 +185,8 @@ int bdl_knn_graph(bdl_tree* t, int32_t k, uint32_t* out_ids, float* out_d2);
                                   hipGraphs; 0: it launches eagerly */
 #define BDL_PARAM_PERSISTENT 5 /* 1: a k-NN batch larger than the device holds at
                                   once runs on a resident grid that draws groups
-                                  of 64 queries from per-XCD work counters;
+                                  of queries (64, or 128 for two per lane) from
+                                  per-XCD work counters;
                                   0: one wavefront per group; 2 (default): 1 for
                                   the wavefront kernel, 0 for the lane kernel */
 #define BDL_PARAM_QUERY_MAX 6  /* launches of at most this many queries use one

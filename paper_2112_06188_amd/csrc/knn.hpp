@@ -20,7 +20,8 @@ size_t query_scratch_bytes(uint64_t cap);
 constexpr uint64_t kSortQueriesMin = 4096;
 
 // Traversal variants: one lane per query, or one wavefront per group of 64
-// neighbouring queries.
+// neighbouring queries (128 with two per lane, for d <= 3, k <= 5 and large
+// batches).
 constexpr int kKnnLane = 0;
 constexpr int kKnnWave = 1;
 constexpr int kKnnAuto = 2;  // chosen per launch from the query density
@@ -55,7 +56,7 @@ struct KnnQueries {
 // and a queue given (kKnnQueueWords words of device memory owned by the
 // caller, not in use by another launch on another stream), a batch larger
 // than the device holds at once runs on a resident grid whose waves draw
-// groups of 64 queries from per-XCD counters.  dry_run only prepares the
+// groups of queries from per-XCD counters.  dry_run only prepares the
 // launch (occupancy lookups), so that a later launch under stream capture
 // makes no such query.
 struct KnnLaunch {
